@@ -12,12 +12,14 @@ sum_q w_q Psi_j(x_q) Psi_k(x_q) = delta_jk; the eigenfunctions are then
 evaluated anywhere by the Nystrom interpolation
 Psi_j(x) = (1/lambda_j) sum_q w_q C(x, x_q) Psi_j(x_q).
 
-Sign convention: each eigenvector is flipped so that its entry of largest
-magnitude on the quadrature points is positive.  Degenerate eigenvalues (the
-isotropic kernel on a square has mode pairs (a, b) and (b, a)) leave the basis
-inside each eigenspace to the eigensolver; quantities invariant under that
-choice (eigenvalues, the covariance B^T B of the truncated field) are what may
-be compared between independent eigensolvers.
+Canonical basis: the isotropic kernel on a square has degenerate eigenvalues
+(mode pairs (a, b) and (b, a)), inside which an eigensolver may return any
+rotation, differently on different machines.  The oracle therefore replaces
+each eigenspace (eigenvalues equal to a relative 1e-8) by the Gram-Schmidt
+orthonormalisation of the projections of fixed seeded probe vectors onto it
+(the projector does not depend on the rotation), and fixes the sign of a simple
+eigenvector by its inner product with a probe.  The eigenfunctions are thereby
+defined independently of the eigensolver.
 """
 from __future__ import annotations
 
@@ -72,11 +74,29 @@ def nystrom(cov, points, weights, n_modes=None):
         lam, V = sla.eigh(S, subset_by_index=[Q - n_modes, Q - 1])
     order = np.argsort(-lam, kind="stable")
     lam, V = lam[order], V[:, order]
-    big = np.argmax(np.abs(V), axis=0)
-    sign = np.sign(V[big, np.arange(V.shape[1])])
-    sign[sign == 0] = 1.0
-    V = V * sign
+    V = canonical_eigenvectors(lam, V)
     return lam, V / sw[:, None]
+
+
+def canonical_eigenvectors(lam, V, rtol=1e-8):
+    """Rotation- and sign-free eigenvectors: per cluster of equal eigenvalues, orthonormalised
+    projections of seeded probe vectors (PCG64 seed 20190321) onto the cluster's span."""
+    Q, M = V.shape
+    probes = np.random.Generator(np.random.PCG64(20190321)).standard_normal((Q, M))
+    out = np.empty_like(V)
+    a = 0
+    while a < M:
+        b = a + 1
+        while b < M and abs(lam[b] - lam[a]) <= rtol * abs(lam[a]):
+            b += 1
+        span = V[:, a:b]
+        for k in range(a, b):
+            v = span @ (span.T @ probes[:, k])
+            for q in range(a, k):
+                v = v - out[:, q] * (out[:, q] @ v)
+            out[:, k] = v / np.linalg.norm(v)
+        a = b
+    return out
 
 
 def interpolate(cov, points_q, weights, lam, psi_q, points):
