@@ -1,0 +1,203 @@
+/*
+ * rmg.h - C ABI of the batched Picard-multigrid sampler for the stochastic
+ * Richards equation (gfx950 / MI355X).
+ *
+ * Method: Kumar, Rodrigo, Gaspar, Oosterlee, "A parametric acceleration of
+ * multilevel Monte Carlo convergence for nonlinear variably saturated flow".
+ *   - random fields: Section 3, eqs. RandK and KLexp (lognormal Ks from a
+ *     truncated Karhunen-Loeve expansion);
+ *   - time stepping: Section 4.1, eqs. Mixed_based .. Mixed_based_3 (backward
+ *     Euler on the mixed form, modified Picard iteration, ||dp||_inf stop);
+ *   - linear solver: Section 4.2, eq. five_stencil and eq. transfer (cell-centred
+ *     multigrid, harmonic-mean faces, arithmetic-mean face upscaling,
+ *     piecewise-constant prolongation, restriction = prolongation^T / 4);
+ *   - estimator: Section 5.1, eqs. telescope, MLMCestimator, SMC, ML_var.
+ *
+ * Conventions shared by every entry point
+ *   Domain (0,1)^2, n x n cells, h = 1/n, n a power of two with 4 <= n <= 4096.
+ *   Cell c = j*n + i, x (index i) fastest, j = 0 the bottom row, z up.
+ *   Top (z = 1) and bottom (z = 0) faces are Dirichlet, the sides are no-flux.
+ *   Pointers named d_* are device memory, h_* host memory; all are owned by the
+ *   caller and must stay valid until the work enqueued on `stream` completes.
+ *   The context owns only its workspace (grown on demand, reused across calls,
+ *   freed by rmg_ctx_destroy).  A context is not thread safe.
+ *   Every call returns an rmg_status; on failure rmg_last_error() explains it.
+ *   No C++ exception crosses this interface.
+ */
+#ifndef RMG_H_
+#define RMG_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmg_ctx rmg_ctx;
+
+typedef enum {
+  RMG_OK = 0,
+  RMG_EINVAL = -1,    /* invalid argument (shape, pointer, option) */
+  RMG_ENOMEM = -2,    /* workspace allocation failed */
+  RMG_EHIP = -3,      /* a HIP runtime call failed */
+  RMG_ENOTCONV = -4   /* outputs valid, but at least one sample did not converge */
+} rmg_status;
+
+/* Per-sample outcome (Section 4.3: a sample fails when the Picard iteration
+ * exceeds its iteration limit at some time step). */
+typedef enum {
+  RMG_SAMPLE_OK = 0,
+  RMG_SAMPLE_MAXITER = 1,
+  RMG_SAMPLE_NONFINITE = 2
+} rmg_sample_status;
+
+typedef enum { RMG_GARDNER = 0, RMG_VGM = 1, RMG_LINEAR = 2 } rmg_model;
+typedef enum { RMG_QOI_MEAN_SATURATION = 0, RMG_QOI_BOTTOM_OUTFLUX = 1 } rmg_qoi;
+typedef enum { RMG_FP64 = 0, RMG_MIXED = 1 } rmg_precision;
+typedef enum { RMG_CYCLE_V = 1, RMG_CYCLE_W = 2 } rmg_cycle;
+
+/* Pointwise marginal of a random field built from the Gaussian KL sum G:
+ * value = shift + exp(log_mean + scale * G)  (eq. RandK with Ks_bl = exp(log_mean)). */
+typedef struct {
+  double shift, log_mean, scale;
+} rmg_marginal;
+
+/* One deterministic problem (closure model, boundary and initial data, time grid).
+ * Fields per cell: Gardner and linear use field 0 = Ks; van Genuchten-Mualem uses
+ * field 0 = Ks, 1 = alpha, 2 = n (so n_fields = 1 or 3).
+ *   Gardner: K = Ks e^{a h}, theta = theta_r + (theta_s - theta_r) e^{a h} (h < 0);
+ *            saturated (h >= 0): K = Ks, theta = theta_s, C = 0.
+ *   vG-Mualem: eqs. Sw, sc_van, Krw with m = 1 - 1/n.
+ *   Linear (test only): K = Ks, theta = theta_r + linear_c0 * h. */
+typedef struct {
+  int32_t model;          /* rmg_model */
+  int32_t n_steps;        /* number of backward-Euler steps */
+  int32_t qoi;            /* rmg_qoi */
+  int32_t pad_;
+  double theta_r, theta_s;
+  double gardner_a;       /* Gardner exponent a */
+  double linear_c0;       /* linear-law capacity */
+  double vg_alpha_shift;  /* added to the alpha field (parametric continuation offset) */
+  double vg_n_shift;      /* added to the n field */
+  double h_top, h_bottom; /* Dirichlet pressure head on z = 1 and z = 0 */
+  double h_init;          /* uniform initial pressure head */
+  double dt;              /* time step */
+} rmg_problem;
+
+/* Solver options.  Defaults for the benchmark workloads: MIXED, V, 2, 2, 1,
+ * eps_mg 1e-5 (unused when cycles_per_picard > 0), eps_picard 1e-8,
+ * max_picard 100, coarsest_n 4. */
+typedef struct {
+  int32_t precision;          /* rmg_precision: FP64 everywhere, or FP32 multigrid inside FP64 Picard */
+  int32_t cycle;              /* rmg_cycle */
+  int32_t nu1, nu2;           /* pre/post red-black Gauss-Seidel sweeps, 0..8 */
+  int32_t cycles_per_picard;  /* >= 1: fixed number of cycles per Picard step */
+  int32_t max_picard;         /* Picard iterations allowed per time step, >= 1 */
+  int32_t coarsest_n;         /* coarsest grid size (2, 4 or 8), solved exactly in FP64 */
+  int32_t flags;              /* bit 0: force the level-streaming path (no whole-sample-in-LDS kernel) */
+  double eps_mg;              /* reserved for a residual-controlled cycle count */
+  double eps_picard;          /* stop when ||dp||_inf < eps_picard (strict) */
+} rmg_solver_opts;
+
+/* Per-sample statistics written by picard_mg_solve (device memory). */
+typedef struct {
+  int32_t picard_its;   /* Picard iterations summed over all time steps */
+  int32_t mg_cycles;    /* multigrid cycles summed over all time steps */
+  int32_t steps_done;   /* time steps completed */
+  int32_t status;       /* rmg_sample_status */
+  double final_dp_inf;  /* ||dp||_inf of the last Picard iteration */
+} rmg_sample_stats;
+
+/* Compensated (Neumaier) double-double sum: value = hi + lo. */
+typedef struct {
+  double hi, lo;
+} rmg_dd;
+
+/* Sums over the successful pairs of one MLMC level (Section 5.1, eqs. SMC, MC_var):
+ * Y = Q_fine - Q_coarse (Q_coarse = 0 on level 0). */
+typedef struct {
+  int64_t n, n_failed, picard_its, mg_cycles;
+  rmg_dd sY, sY2, sQf, sQf2, sQc, sQc2;
+} rmg_level_sums;
+
+/* One MLMC level: fine grid n_fine, coarse partner n_coarse = n_fine / 2
+ * (0 on level 0), n_samples pairs sharing their KL draws (Section 5.1: the two
+ * members of a correction use the same random input). */
+typedef struct {
+  int32_t n_fine, n_coarse;
+  int64_t n_samples;
+  rmg_problem fine, coarse;       /* per-level problems (continuation may differ) */
+  const double* d_basis_fine;     /* [n_modes][n_fine^2] */
+  const double* d_basis_coarse;   /* [n_modes][n_coarse^2], NULL on level 0 */
+  const double* d_xi;             /* [n_samples][n_fields][n_modes] standard normals */
+} rmg_level;
+
+/* Size in bytes of the named ABI struct ("rmg_problem", "rmg_solver_opts",
+ * "rmg_sample_stats", "rmg_level_sums", "rmg_level", "rmg_marginal"), or -1 if
+ * unknown; lets bindings check their struct layouts against this build. */
+int64_t rmg_struct_size(const char* name);
+
+/* Create a context on HIP device `hip_device`; *out receives it. */
+int rmg_ctx_create(rmg_ctx** out, int hip_device);
+/* Release the context and its workspace (waits for its device to be idle). */
+void rmg_ctx_destroy(rmg_ctx* ctx);
+/* Text of the last error on this context ("" if none); valid until the next call. */
+const char* rmg_last_error(const rmg_ctx* ctx);
+
+/*
+ * sample_fields - KL random fields, Section 3 eqs. KLexp and RandK.
+ *   G[s][f][c] = sum_j d_xi[s][f][j] * d_basis[j][c]   (dense product on FP64 matrix cores)
+ *   d_fields[s][f][c] = h_marg[f].shift + exp(h_marg[f].log_mean + h_marg[f].scale * G[s][f][c])
+ * d_basis [n_modes][n*n] holds sqrt(lambda_j) Psi_j(x_c); d_xi [S][n_fields][n_modes];
+ * d_fields [S][n_fields][n*n].  All FP64.  Asynchronous on `stream`.
+ * EINVAL: bad n, S < 1, n_fields not in 1..4, n_modes not in 1..1024, NULL pointer.
+ */
+int sample_fields(rmg_ctx* ctx, int n, int n_fields, int n_modes,
+                  const double* d_basis, const double* d_xi, const rmg_marginal* h_marg,
+                  int64_t S, double* d_fields, hipStream_t stream);
+
+/*
+ * picard_mg_solve - S independent samples on one n x n grid, Sections 4.1-4.2.
+ * Each sample integrates problem->n_steps backward-Euler steps from h_init; each
+ * step runs modified Picard iterations, each solving its correction equation
+ * with opts->cycles_per_picard multigrid cycles, until ||dp||_inf < eps_picard.
+ *   d_fields  [S][n_fields][n*n] FP64 (n_fields = 1 for Gardner/linear, 3 for vG)
+ *   d_h_out   [S][n*n] FP64: pressure head at the final time (last iterate for a failed sample)
+ *   d_qoi     [S] FP64: the problem's QoI (NaN for a failed sample)
+ *   d_status  [S] int32: rmg_sample_status
+ *   d_stats   [S] rmg_sample_stats, may be NULL
+ * Synchronises with `stream` once per poll of the active-sample count.
+ * Returns RMG_ENOTCONV if some sample failed (its outputs are flagged).
+ * EINVAL: bad n or coarsest_n, S < 1, NULL pointer, unknown model/precision/cycle,
+ * nu1 + nu2 == 0, max_picard < 1, eps_picard <= 0, dt <= 0, n_steps < 1.
+ */
+int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+                    const double* d_fields, int64_t S,
+                    double* d_h_out, double* d_qoi, int32_t* d_status,
+                    rmg_sample_stats* d_stats, hipStream_t stream);
+
+/*
+ * mlmc_level_estimate - one batched evaluation of n_levels MLMC levels
+ * (Section 5.1 eqs. MLMCestimator, SMC, ML_var).  For level l and pair i the
+ * fine solve (n_fine, fine problem) and the coarse solve (n_coarse, coarse
+ * problem) draw their fields from the same d_xi row through their own basis
+ * tables; Y_i = Q_fine - Q_coarse.  All solves of all levels run in one batch
+ * (grouped by grid size).  Failed pairs are excluded from the sums and counted.
+ *   h_levels [n_levels], h_marg [n_fields], h_out [n_levels] (host).
+ *   d_qoi_out: optional device array [sum_l 2*n_samples_l] receiving, level by
+ *   level, the fine QoIs then the coarse QoIs (NaN marks failure); may be NULL.
+ * Synchronises with `stream` before returning.  Returns RMG_ENOTCONV if some
+ * sample failed.  EINVAL as for picard_mg_solve, plus n_coarse != n_fine / 2 on
+ * levels >= 1, or n_coarse != 0 on level 0.
+ */
+int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* h_levels,
+                        int n_fields, int n_modes, const rmg_marginal* h_marg,
+                        const rmg_solver_opts* opts, rmg_level_sums* h_out,
+                        double* d_qoi_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMG_H_ */

@@ -1,0 +1,232 @@
+"""Batched Picard-multigrid sampler for the stochastic Richards equation on MI355X.
+
+Python binding of the C ABI in include/rmg.h (argument marshalling only; every
+step of the computation runs in the HIP kernels of librmg.so).  Device memory and
+streams come from PyTorch: arrays are torch CUDA tensors (ROCm) and work is
+enqueued on the current torch stream.
+
+    sample_fields(n, basis, xi, marginals)           KL fields (Section 3)
+    picard_mg_solve(n, fields, problem, opts)        S samples on one grid (Sections 4.1-4.2)
+    mlmc_level_estimate(levels, marginals, opts)     batched MLMC level sums (Section 5.1)
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field, fields as dc_fields
+
+from . import _abi
+from ._abi import (CYCLE_V, CYCLE_W, FLAG_FORCE_STREAMING, FP64, GARDNER, LINEAR, MIXED,  # noqa: F401
+                   QOI_MEAN_SATURATION, RMG_ENOTCONV, RMG_OK, SAMPLE_MAXITER, SAMPLE_NONFINITE,
+                   SAMPLE_OK, VGM)
+
+__all__ = ["Problem", "SolverOpts", "Context", "RmgError", "sample_fields", "picard_mg_solve",
+           "mlmc_level_estimate", "default_context"]
+
+
+class RmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rmg error {code}: {msg}")
+        self.code = code
+
+
+@dataclass
+class Problem:
+    """Deterministic problem data (mirrors rmg_problem)."""
+    model: int = GARDNER
+    n_steps: int = 10
+    qoi: int = QOI_MEAN_SATURATION
+    theta_r: float = 0.05
+    theta_s: float = 0.5
+    gardner_a: float = 1.0
+    linear_c0: float = 0.0
+    vg_alpha_shift: float = 0.0
+    vg_n_shift: float = 0.0
+    h_top: float = 0.0
+    h_bottom: float = -10.0
+    h_init: float = -10.0
+    dt: float = 0.01
+
+    def c(self) -> _abi.Problem:
+        return _abi.Problem(**{f.name: getattr(self, f.name) for f in dc_fields(self)})
+
+    @property
+    def n_fields(self) -> int:
+        return 3 if self.model == VGM else 1
+
+
+@dataclass
+class SolverOpts:
+    """Solver options (mirrors rmg_solver_opts)."""
+    precision: int = MIXED
+    cycle: int = CYCLE_V
+    nu1: int = 2
+    nu2: int = 2
+    cycles_per_picard: int = 1
+    max_picard: int = 100
+    coarsest_n: int = 4
+    flags: int = 0
+    eps_mg: float = 1e-5
+    eps_picard: float = 1e-8
+
+    def c(self) -> _abi.SolverOpts:
+        return _abi.SolverOpts(**{f.name: getattr(self, f.name) for f in dc_fields(self)})
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t, name, dtype=None, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (ROCm) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Context:
+    """An rmg_ctx on one HIP device (owns the workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = _abi.lib()
+        h = C.c_void_p()
+        rc = self._lib.rmg_ctx_create(C.byref(h), int(device))
+        if rc != RMG_OK:
+            raise RmgError(rc, f"rmg_ctx_create(device={device}) failed")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rmg_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, rc, allow_notconv=False):
+        if rc == RMG_OK or (allow_notconv and rc == RMG_ENOTCONV):
+            return rc
+        raise RmgError(rc, self._lib.rmg_last_error(self._h).decode())
+
+    # -- entry points ----------------------------------------------------------
+    def sample_fields(self, n, basis, xi, marginals, out=None, stream=None):
+        """KL fields [S][F][n*n] from basis [M][n*n] and standard normals xi [S][F][M] (FP64)."""
+        torch = _torch()
+        M = basis.shape[0]
+        S, F = xi.shape[0], xi.shape[1]
+        _check_dev(basis, "basis", torch.float64, (M, n * n))
+        _check_dev(xi, "xi", torch.float64, (S, F, M))
+        if len(marginals) != F:
+            raise ValueError("one marginal per field is required")
+        if out is None:
+            out = torch.empty((S, F, n * n), dtype=torch.float64, device=xi.device)
+        _check_dev(out, "out", torch.float64, (S, F, n * n))
+        marg = (_abi.Marginal * F)(*[_abi.Marginal(*m) for m in marginals])
+        rc = self._lib.sample_fields(self._h, n, F, M, C.c_void_p(basis.data_ptr()),
+                                     C.c_void_p(xi.data_ptr()), marg, S, C.c_void_p(out.data_ptr()),
+                                     _stream_ptr(stream))
+        self._raise(rc)
+        return out
+
+    def picard_mg_solve(self, n, fields, problem: Problem, opts: SolverOpts, stream=None):
+        """Solve S samples on an n x n grid; returns dict(h, qoi, status, stats, rc)."""
+        torch = _torch()
+        S = fields.shape[0]
+        _check_dev(fields, "fields", torch.float64, (S, problem.n_fields, n * n))
+        dev = fields.device
+        h = torch.empty((S, n * n), dtype=torch.float64, device=dev)
+        qoi = torch.empty(S, dtype=torch.float64, device=dev)
+        status = torch.empty(S, dtype=torch.int32, device=dev)
+        stats = torch.empty((S, C.sizeof(_abi.SampleStats)), dtype=torch.uint8, device=dev)
+        pr, op = problem.c(), opts.c()
+        rc = self._lib.picard_mg_solve(self._h, n, C.byref(pr), C.byref(op), C.c_void_p(fields.data_ptr()),
+                                       S, C.c_void_p(h.data_ptr()), C.c_void_p(qoi.data_ptr()),
+                                       C.c_void_p(status.data_ptr()), C.c_void_p(stats.data_ptr()),
+                                       _stream_ptr(stream))
+        self._raise(rc, allow_notconv=True)
+        return dict(h=h, qoi=qoi, status=status, stats=_decode_stats(stats), rc=rc)
+
+    def mlmc_level_estimate(self, levels, marginals, opts: SolverOpts, return_qoi=False, stream=None):
+        """levels: list of dict(n_fine, n_coarse, fine: Problem, coarse: Problem|None,
+        basis_fine, basis_coarse, xi); returns (list of per-level sums dicts, qoi tensor|None, rc)."""
+        torch = _torch()
+        L = len(levels)
+        arr = (_abi.Level * L)()
+        F = levels[0]["xi"].shape[1]
+        M = levels[0]["xi"].shape[2]
+        tot = 0
+        for i, lv in enumerate(levels):
+            S = lv["xi"].shape[0]
+            _check_dev(lv["xi"], f"levels[{i}].xi", torch.float64, (S, F, M))
+            _check_dev(lv["basis_fine"], f"levels[{i}].basis_fine", torch.float64,
+                       (M, lv["n_fine"] ** 2))
+            coarse = lv.get("coarse") or lv["fine"]
+            bc = lv.get("basis_coarse")
+            if lv["n_coarse"]:
+                _check_dev(bc, f"levels[{i}].basis_coarse", torch.float64, (M, lv["n_coarse"] ** 2))
+            arr[i] = _abi.Level(lv["n_fine"], lv["n_coarse"], S, lv["fine"].c(), coarse.c(),
+                                C.c_void_p(lv["basis_fine"].data_ptr()),
+                                C.c_void_p(bc.data_ptr()) if bc is not None else None,
+                                C.c_void_p(lv["xi"].data_ptr()))
+            tot += 2 * S
+        marg = (_abi.Marginal * F)(*[_abi.Marginal(*m) for m in marginals])
+        out = (_abi.LevelSums * L)()
+        q = torch.empty(tot, dtype=torch.float64, device=levels[0]["xi"].device) if return_qoi else None
+        op = opts.c()
+        rc = self._lib.mlmc_level_estimate(self._h, L, arr, F, M, marg, C.byref(op), out,
+                                           C.c_void_p(q.data_ptr()) if q is not None else None,
+                                           _stream_ptr(stream))
+        self._raise(rc, allow_notconv=True)
+        sums = []
+        for s in out:
+            d = {k: getattr(s, k) for k in ("n", "n_failed", "picard_its", "mg_cycles")}
+            for k in ("sY", "sY2", "sQf", "sQf2", "sQc", "sQc2"):
+                v = getattr(s, k)
+                d[k] = (v.hi, v.lo)
+            sums.append(d)
+        return sums, q, rc
+
+
+def _decode_stats(raw):
+    import numpy as np
+    a = raw.cpu().numpy()
+    dt = np.dtype([("picard_its", "<i4"), ("mg_cycles", "<i4"), ("steps_done", "<i4"), ("status", "<i4"),
+                   ("final_dp_inf", "<f8")])
+    return a.view(dt).reshape(-1)
+
+
+_default = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def sample_fields(n, basis, xi, marginals, out=None, stream=None):
+    return default_context(xi.device.index or 0).sample_fields(n, basis, xi, marginals, out, stream)
+
+
+def picard_mg_solve(n, fields, problem: Problem, opts: SolverOpts, stream=None):
+    return default_context(fields.device.index or 0).picard_mg_solve(n, fields, problem, opts, stream)
+
+
+def mlmc_level_estimate(levels, marginals, opts: SolverOpts, return_qoi=False, stream=None):
+    dev = levels[0]["xi"].device.index or 0
+    return default_context(dev).mlmc_level_estimate(levels, marginals, opts, return_qoi, stream)

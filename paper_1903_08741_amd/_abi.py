@@ -1,0 +1,101 @@
+"""ctypes mirror of include/rmg.h and loader of the in-tree HIP library.
+
+The library must have been built (``__graft_entry__.build()`` or
+``python -m paper_1903_08741_amd.build_lib``); there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmg.so")
+
+RMG_OK, RMG_EINVAL, RMG_ENOMEM, RMG_EHIP, RMG_ENOTCONV = 0, -1, -2, -3, -4
+SAMPLE_OK, SAMPLE_MAXITER, SAMPLE_NONFINITE = 0, 1, 2
+GARDNER, VGM, LINEAR = 0, 1, 2
+QOI_MEAN_SATURATION, QOI_BOTTOM_OUTFLUX = 0, 1
+FP64, MIXED = 0, 1
+CYCLE_V, CYCLE_W = 1, 2
+FLAG_FORCE_STREAMING = 1
+
+EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
+            "sample_fields", "picard_mg_solve", "mlmc_level_estimate")
+
+
+class Marginal(C.Structure):
+    _fields_ = [("shift", C.c_double), ("log_mean", C.c_double), ("scale", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("model", C.c_int32), ("n_steps", C.c_int32), ("qoi", C.c_int32), ("pad_", C.c_int32),
+                ("theta_r", C.c_double), ("theta_s", C.c_double), ("gardner_a", C.c_double),
+                ("linear_c0", C.c_double), ("vg_alpha_shift", C.c_double), ("vg_n_shift", C.c_double),
+                ("h_top", C.c_double), ("h_bottom", C.c_double), ("h_init", C.c_double), ("dt", C.c_double)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("cycle", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("cycles_per_picard", C.c_int32), ("max_picard", C.c_int32), ("coarsest_n", C.c_int32),
+                ("flags", C.c_int32), ("eps_mg", C.c_double), ("eps_picard", C.c_double)]
+
+
+class SampleStats(C.Structure):
+    _fields_ = [("picard_its", C.c_int32), ("mg_cycles", C.c_int32), ("steps_done", C.c_int32),
+                ("status", C.c_int32), ("final_dp_inf", C.c_double)]
+
+
+class DD(C.Structure):
+    _fields_ = [("hi", C.c_double), ("lo", C.c_double)]
+
+
+class LevelSums(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_failed", C.c_int64), ("picard_its", C.c_int64),
+                ("mg_cycles", C.c_int64), ("sY", DD), ("sY2", DD), ("sQf", DD), ("sQf2", DD),
+                ("sQc", DD), ("sQc2", DD)]
+
+
+class Level(C.Structure):
+    _fields_ = [("n_fine", C.c_int32), ("n_coarse", C.c_int32), ("n_samples", C.c_int64),
+                ("fine", Problem), ("coarse", Problem), ("d_basis_fine", C.c_void_p),
+                ("d_basis_coarse", C.c_void_p), ("d_xi", C.c_void_p)]
+
+
+STRUCTS = {"rmg_problem": Problem, "rmg_solver_opts": SolverOpts, "rmg_sample_stats": SampleStats,
+           "rmg_level_sums": LevelSums, "rmg_level": Level, "rmg_marginal": Marginal}
+
+_lib = None
+
+
+def lib():
+    """Load librmg.so once and declare the exported signatures; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first "
+                           "(there is no fallback implementation)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
+    L.rmg_struct_size.argtypes = [C.c_char_p]
+    L.rmg_struct_size.restype = i64
+    L.rmg_ctx_create.argtypes = [C.POINTER(vp), i32]
+    L.rmg_ctx_create.restype = i32
+    L.rmg_ctx_destroy.argtypes = [vp]
+    L.rmg_ctx_destroy.restype = None
+    L.rmg_last_error.argtypes = [vp]
+    L.rmg_last_error.restype = C.c_char_p
+    L.sample_fields.argtypes = [vp, i32, i32, i32, vp, vp, C.POINTER(Marginal), i64, vp, vp]
+    L.sample_fields.restype = i32
+    L.picard_mg_solve.argtypes = [vp, i32, C.POINTER(Problem), C.POINTER(SolverOpts), vp, i64, vp, vp, vp,
+                                  vp, vp]
+    L.picard_mg_solve.restype = i32
+    L.mlmc_level_estimate.argtypes = [vp, i32, C.POINTER(Level), i32, i32, C.POINTER(Marginal),
+                                      C.POINTER(SolverOpts), C.POINTER(LevelSums), vp, vp]
+    L.mlmc_level_estimate.restype = i32
+    for name, cls in STRUCTS.items():
+        got = L.rmg_struct_size(name.encode())
+        if got != C.sizeof(cls):
+            raise RuntimeError(f"ABI mismatch: {name} is {got} bytes in the library, {C.sizeof(cls)} here")
+    _lib = L
+    return L

@@ -1,0 +1,128 @@
+// Karhunen-Loeve field sampling on FP64 matrix cores (gfx950).
+//
+// Section 3 eq. KLexp truncated at M terms, for a batch of rows r = s*F + f:
+//   G[r][c] = sum_k xi[r][k] * B[k][c],   B[k][c] = sqrt(lambda_k) Psi_k(x_c),
+// followed by the pointwise marginal of eq. RandK (lognormal, optionally shifted):
+//   out[r][c] = shift_f + exp(log_mean_f + scale_f * G[r][c]).
+// One wave computes a 16-row x 64-column block with four 16x16 FP64 MFMA
+// accumulators (v_mfma_f64_16x16x4f64, K = 4 per instruction); a workgroup of
+// four waves covers 64 rows x 64 columns.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "rmg_internal.hpp"
+
+namespace rmg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct Marg4 {
+  rmg_marginal m[4];
+};
+
+__global__ __launch_bounds__(256) void k_kl_fields(int N, int M, int64_t rows, int F,
+                                                   const double* __restrict__ B,
+                                                   const double* __restrict__ xi, Marg4 mg,
+                                                   double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * 64 + wave * 16;
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  // operand layouts: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k
+  const int64_t arow = r0 + li;
+  v4d acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < M; k0 += 4) {
+    const int k = k0 + lk;
+    const double a = (arow < rows && k < M) ? xi[arow * M + k] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t col = c0 + 16 * t + li;
+      const double b = (k < M && col < N) ? B[(int64_t)k * N + col] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  // result layout of v_mfma_f64_16x16x4f64: D[i][j] in lane j + 16*(i%4), element i/4
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t col = c0 + 16 * t + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = r0 + 4 * e + lk;
+      if (row < rows && col < N) {
+        const rmg_marginal& q = mg.m[(int)(row % F)];
+        out[row * N + col] = q.shift + exp(q.log_mean + q.scale * acc[t][e]);
+      }
+    }
+  }
+}
+
+hipError_t launch_kl_fields(int N, int M, int64_t rows, int F, const double* B, const double* xi,
+                            const rmg_marginal* marg, double* out, hipStream_t st) {
+  Marg4 mg;
+  for (int f = 0; f < 4; ++f) mg.m[f] = f < F ? marg[f] : rmg_marginal{0.0, 0.0, 0.0};
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((rows + 63) / 64));
+  hipLaunchKernelGGL(k_kl_fields, grid, dim3(256), 0, st, N, M, rows, F, B, xi, mg, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- level sums
+// Neumaier-compensated sums over the pairs of one level in sample order
+// (Section 5.1 eqs. SMC, MC_var need sum Y, sum Y^2 and the same for Q_f, Q_c).
+struct Neu {
+  double s, c;
+};
+__device__ __forceinline__ void neu_add(Neu& a, double x) {
+  const double t = a.s + x;
+  if (fabs(a.s) >= fabs(x))
+    a.c += (a.s - t) + x;
+  else
+    a.c += (x - t) + a.s;
+  a.s = t;
+}
+
+__global__ void k_level_sums(const double* qf, const double* qc, int64_t n, const int32_t* stf,
+                             const int32_t* stc, const rmg_sample_stats* sf,
+                             const rmg_sample_stats* sc, rmg_level_sums* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Neu y = {0, 0}, y2 = {0, 0}, f = {0, 0}, f2 = {0, 0}, c = {0, 0}, c2 = {0, 0};
+  int64_t ok = 0, bad = 0, its = 0, cyc = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    its += sf[i].picard_its + (sc ? sc[i].picard_its : 0);
+    cyc += sf[i].mg_cycles + (sc ? sc[i].mg_cycles : 0);
+    const bool good = stf[i] == RMG_SAMPLE_OK && (!stc || stc[i] == RMG_SAMPLE_OK);
+    if (!good) {
+      ++bad;
+      continue;
+    }
+    ++ok;
+    const double a = qf[i], b = qc ? qc[i] : 0.0, d = a - b;
+    neu_add(y, d);
+    neu_add(y2, d * d);
+    neu_add(f, a);
+    neu_add(f2, a * a);
+    neu_add(c, b);
+    neu_add(c2, b * b);
+  }
+  rmg_level_sums o;
+  o.n = ok;
+  o.n_failed = bad;
+  o.picard_its = its;
+  o.mg_cycles = cyc;
+  o.sY = {y.s, y.c};
+  o.sY2 = {y2.s, y2.c};
+  o.sQf = {f.s, f.c};
+  o.sQf2 = {f2.s, f2.c};
+  o.sQc = {c.s, c.c};
+  o.sQc2 = {c2.s, c2.c};
+  *out = o;
+}
+
+hipError_t launch_level_sums(const double* qf, const double* qc, int64_t n, const int32_t* stf,
+                             const int32_t* stc, const rmg_sample_stats* sf,
+                             const rmg_sample_stats* sc, rmg_level_sums* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_level_sums, dim3(1), dim3(64), 0, st, qf, qc, n, stf, stc, sf, sc, out);
+  return hipGetLastError();
+}
+
+}  // namespace rmg

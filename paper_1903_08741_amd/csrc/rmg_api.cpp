@@ -1,0 +1,512 @@
+// C ABI of the batched Picard-multigrid sampler: validation, workspace,
+// scheduling of grid-size classes, and the polling loop of the level-streaming
+// path.  All arithmetic runs in the HIP kernels; this file only plans launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rmg.h"
+#include "rmg_internal.hpp"
+
+using namespace rmg;
+
+struct rmg_ctx {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  int32_t* h_count = nullptr;  // pinned host mirror of the active-sample counters
+  hipStream_t side[8] = {};
+  hipEvent_t ev[8] = {};
+  std::string err;
+};
+
+namespace {
+
+int fail(rmg_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                       \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(ctx, RMG_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                     \
+  } while (0)
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+int ilog2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Bump allocator over the context workspace.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0, cap = 0;
+  void* take(size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+int reserve(rmg_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_cap) return RMG_OK;
+  if (ctx->ws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+  }
+  const size_t want = bytes + bytes / 8 + (1 << 20);
+  if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(ctx, RMG_ENOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  ctx->ws_cap = want;
+  return RMG_OK;
+}
+
+int check_problem(rmg_ctx* ctx, const rmg_problem* p, int n_fields) {
+  if (!p) return fail(ctx, RMG_EINVAL, "problem is NULL");
+  if (p->model != RMG_GARDNER && p->model != RMG_VGM && p->model != RMG_LINEAR)
+    return fail(ctx, RMG_EINVAL, "unknown closure model %d", p->model);
+  const int need = p->model == RMG_VGM ? 3 : 1;
+  if (n_fields < need) return fail(ctx, RMG_EINVAL, "model %d needs %d fields, got %d", p->model, need, n_fields);
+  if (p->qoi != RMG_QOI_MEAN_SATURATION)
+    return fail(ctx, RMG_EINVAL, "qoi %d is not supported by this build", p->qoi);
+  if (!(p->dt > 0.0) || p->n_steps < 1) return fail(ctx, RMG_EINVAL, "need dt > 0 and n_steps >= 1");
+  if (!(p->theta_s > p->theta_r)) return fail(ctx, RMG_EINVAL, "need theta_s > theta_r");
+  return RMG_OK;
+}
+
+int check_opts(rmg_ctx* ctx, const rmg_solver_opts* o, int n) {
+  if (!o) return fail(ctx, RMG_EINVAL, "opts is NULL");
+  if (o->precision != RMG_FP64 && o->precision != RMG_MIXED)
+    return fail(ctx, RMG_EINVAL, "unknown precision %d", o->precision);
+  if (o->cycle != RMG_CYCLE_V) return fail(ctx, RMG_EINVAL, "only the V-cycle is built (cycle=%d)", o->cycle);
+  if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 4 || o->nu2 > 4 || o->nu1 + o->nu2 == 0)
+    return fail(ctx, RMG_EINVAL, "nu1, nu2 must be in 0..4 and not both 0");
+  if (o->cycles_per_picard < 1 || o->cycles_per_picard > 16)
+    return fail(ctx, RMG_EINVAL, "cycles_per_picard must be in 1..16");
+  if (o->max_picard < 1) return fail(ctx, RMG_EINVAL, "max_picard must be >= 1");
+  if (!(o->eps_picard > 0.0)) return fail(ctx, RMG_EINVAL, "eps_picard must be > 0");
+  if (o->coarsest_n != 2 && o->coarsest_n != 4)
+    return fail(ctx, RMG_EINVAL, "coarsest_n must be 2 or 4");
+  if (n < o->coarsest_n) return fail(ctx, RMG_EINVAL, "n=%d below coarsest_n=%d", n, o->coarsest_n);
+  return RMG_OK;
+}
+
+// One grid-size class of a solve: its problems, fields and outputs.
+struct ClassJob {
+  SolveArgs a{};
+  bool fp64 = false;
+  bool whole = false;
+  StreamPlan pl{};
+  hipStream_t stream = nullptr;
+  int32_t* d_count = nullptr;
+  int32_t* h_count = nullptr;
+  bool done = false;
+};
+
+// Workspace bytes a class needs beyond its caller-visible outputs.
+size_t class_ws_bytes(const ClassJob& j) {
+  const int64_t S = j.a.S;
+  const int n = j.a.n;
+  size_t b = 256 + 8 * (size_t)S * n * n;  // theta_old
+  if (!j.whole) {
+    for (int l = 0; l <= j.pl.ltop; ++l) b += 256 * 6 + level_bytes(n >> l, S, j.fp64);
+    b += 3 * 256 + sizeof(SampleState) * S + 8 * S + 8;
+  }
+  return b;
+}
+
+void class_carve(ClassJob& j, Arena& ar) {
+  const int64_t S = j.a.S;
+  const int n = j.a.n;
+  j.a.theta_old = (double*)ar.take(8 * (size_t)S * n * n);
+  if (j.whole) return;
+  const size_t es = j.fp64 ? 8 : 4;
+  for (int l = 0; l <= j.pl.ltop; ++l) {
+    const size_t m = (size_t)(n >> l);
+    j.pl.lv.u[l] = ar.take(es * S * m * m);
+    j.pl.lv.f[l] = ar.take(es * S * m * m);
+    j.pl.lv.cw[l] = ar.take(es * S * m * m);
+    j.pl.lv.cs[l] = ar.take(es * S * m * m);
+    j.pl.lv.cdt[l] = ar.take(es * S * m * m);
+    j.pl.lv.ctop[l] = ar.take(es * S * m);
+  }
+  j.pl.state = (SampleState*)ar.take(sizeof(SampleState) * S);
+  j.pl.dpmax = (unsigned long long*)ar.take(8 * S);
+  j.pl.active_count = (int32_t*)ar.take(8);
+}
+
+void class_plan(ClassJob& j, const rmg_solver_opts* o) {
+  j.fp64 = o->precision == RMG_FP64;
+  const int n = j.a.n;
+  j.whole = !(o->flags & 1) && whole_sample_lds_bytes(n, o->coarsest_n, j.fp64) > 0;
+  j.pl.n = n;
+  j.pl.nlev = j.a.nlev;
+  j.pl.fp64 = j.fp64;
+  j.pl.ltop = std::max(0, ilog2i(n) - ilog2i(kCoarseTop));
+}
+
+// Run every class to completion: whole-sample classes are single launches;
+// streaming classes advance k Picard iterations per launch batch and poll the
+// number of still-active samples (one 4-byte read-back per batch and class).
+int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs) {
+  for (auto& j : jobs) {
+    if (j.whole) {
+      HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
+      j.done = true;
+    } else {
+      HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
+    }
+  }
+  const int k = 8;
+  // every sample stops after at most n_steps * max_picard iterations
+  long bound = 0;
+  for (auto& j : jobs) {
+    const long steps = std::max(j.a.cp.prob[0].n_steps, j.a.cp.prob[1].n_steps);
+    bound = std::max(bound, steps * (long)j.a.max_picard + 2L * k);
+  }
+  long launched = 0;
+  for (;;) {
+    bool any = false;
+    for (auto& j : jobs) {
+      if (j.done) continue;
+      any = true;
+      for (int i = 0; i < k; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream));
+      HIP_TRY(ctx, hipMemcpyAsync(j.h_count, j.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  j.stream));
+    }
+    if (!any) break;
+    for (auto& j : jobs) {
+      if (j.done) continue;
+      HIP_TRY(ctx, hipStreamSynchronize(j.stream));
+      if (*j.h_count == 0) {
+        HIP_TRY(ctx, launch_stream_finish(j.a, j.pl, j.stream));
+        j.done = true;
+      }
+    }
+    launched += k;
+    if (launched > bound) return fail(ctx, RMG_EHIP, "samples still active after %ld iterations", launched);
+  }
+  return RMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t rmg_struct_size(const char* name) {
+  if (!name) return -1;
+  const std::string s(name);
+  if (s == "rmg_problem") return sizeof(rmg_problem);
+  if (s == "rmg_solver_opts") return sizeof(rmg_solver_opts);
+  if (s == "rmg_sample_stats") return sizeof(rmg_sample_stats);
+  if (s == "rmg_level_sums") return sizeof(rmg_level_sums);
+  if (s == "rmg_level") return sizeof(rmg_level);
+  if (s == "rmg_marginal") return sizeof(rmg_marginal);
+  return -1;
+}
+
+int rmg_ctx_create(rmg_ctx** out, int hip_device) {
+  if (!out) return RMG_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return RMG_EINVAL;
+  rmg_ctx* c = new (std::nothrow) rmg_ctx();
+  if (!c) return RMG_ENOMEM;
+  c->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_count, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RMG_EHIP;
+  }
+  for (auto& s : c->side) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      rmg_ctx_destroy(c);
+      return RMG_EHIP;
+    }
+  }
+  for (auto& e : c->ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      rmg_ctx_destroy(c);
+      return RMG_EHIP;
+    }
+  }
+  *out = c;
+  return RMG_OK;
+}
+
+void rmg_ctx_destroy(rmg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& s : c->side)
+    if (s) (void)hipStreamDestroy(s);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->h_count) (void)hipHostFree(c->h_count);
+  delete c;
+}
+
+const char* rmg_last_error(const rmg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int sample_fields(rmg_ctx* ctx, int n, int n_fields, int n_modes, const double* d_basis,
+                  const double* d_xi, const rmg_marginal* h_marg, int64_t S, double* d_fields,
+                  hipStream_t stream) {
+  if (!ctx) return RMG_EINVAL;
+  ctx->err.clear();
+  if (!pow2_in(n, 4, 4096)) return fail(ctx, RMG_EINVAL, "n=%d must be a power of two in 4..4096", n);
+  if (n_fields < 1 || n_fields > 4) return fail(ctx, RMG_EINVAL, "n_fields=%d not in 1..4", n_fields);
+  if (n_modes < 1 || n_modes > 1024) return fail(ctx, RMG_EINVAL, "n_modes=%d not in 1..1024", n_modes);
+  if (S < 1) return fail(ctx, RMG_EINVAL, "S must be >= 1");
+  if (!d_basis || !d_xi || !h_marg || !d_fields) return fail(ctx, RMG_EINVAL, "NULL pointer");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_kl_fields(n * n, n_modes, S * n_fields, n_fields, d_basis, d_xi, h_marg, d_fields,
+                                stream));
+  return RMG_OK;
+}
+
+int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+                    const double* d_fields, int64_t S, double* d_h_out, double* d_qoi,
+                    int32_t* d_status, rmg_sample_stats* d_stats, hipStream_t stream) {
+  if (!ctx) return RMG_EINVAL;
+  ctx->err.clear();
+  if (!pow2_in(n, 2, 1024)) return fail(ctx, RMG_EINVAL, "n=%d must be a power of two in 2..1024", n);
+  if (S < 1 || S > 65535) return fail(ctx, RMG_EINVAL, "S=%lld not in 1..65535", (long long)S);
+  if (!d_fields || !d_h_out || !d_qoi || !d_status) return fail(ctx, RMG_EINVAL, "NULL pointer");
+  int rc = check_problem(ctx, problem, problem ? (problem->model == RMG_VGM ? 3 : 1) : 1);
+  if (rc) return rc;
+  if ((rc = check_opts(ctx, opts, n))) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+  std::vector<ClassJob> jobs(1);
+  ClassJob& j = jobs[0];
+  j.a.n = n;
+  j.a.lg = ilog2i(n);
+  j.a.nlev = ilog2i(n) - ilog2i(opts->coarsest_n) + 1;
+  j.a.F = problem->model == RMG_VGM ? 3 : 1;
+  j.a.S = S;
+  j.a.fields = d_fields;
+  j.a.cp.prob[0] = *problem;
+  j.a.cp.prob[1] = *problem;
+  j.a.cp.seg_split = S;
+  j.a.nu1 = opts->nu1;
+  j.a.nu2 = opts->nu2;
+  j.a.cpp = opts->cycles_per_picard;
+  j.a.max_picard = opts->max_picard;
+  j.a.eps = opts->eps_picard;
+  j.a.p = d_h_out;
+  j.a.qoi = d_qoi;
+  j.a.status = d_status;
+  j.a.stats = d_stats;
+  class_plan(j, opts);
+  j.stream = stream;
+  j.h_count = ctx->h_count;
+  if ((rc = reserve(ctx, class_ws_bytes(j)))) return rc;
+  Arena ar;
+  ar.base = (char*)ctx->ws;
+  ar.cap = ctx->ws_cap;
+  class_carve(j, ar);
+  if ((rc = run_classes(ctx, jobs))) return rc;
+  std::vector<int32_t> st(S);
+  HIP_TRY(ctx, hipMemcpyAsync(st.data(), d_status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  for (int32_t v : st)
+    if (v != RMG_SAMPLE_OK) return fail(ctx, RMG_ENOTCONV, "some samples did not converge");
+  return RMG_OK;
+}
+
+int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fields, int n_modes,
+                        const rmg_marginal* h_marg, const rmg_solver_opts* opts, rmg_level_sums* h_out,
+                        double* d_qoi_out, hipStream_t stream) {
+  if (!ctx) return RMG_EINVAL;
+  ctx->err.clear();
+  if (n_levels < 1 || n_levels > 16 || !L || !h_marg || !h_out)
+    return fail(ctx, RMG_EINVAL, "bad level list");
+  if (n_fields < 1 || n_fields > 4 || n_modes < 1 || n_modes > 1024)
+    return fail(ctx, RMG_EINVAL, "bad n_fields / n_modes");
+  int rc;
+  // classes by grid size: (level, role) segments, at most one fine and one coarse per size
+  struct Seg {
+    int level, role;  // role 0 fine, 1 coarse
+  };
+  std::map<int, std::vector<Seg>> cls;
+  for (int l = 0; l < n_levels; ++l) {
+    const rmg_level& v = L[l];
+    if (!pow2_in(v.n_fine, 4, 1024)) return fail(ctx, RMG_EINVAL, "level %d: bad n_fine %d", l, v.n_fine);
+    if (l == 0 ? v.n_coarse != 0 : v.n_coarse * 2 != v.n_fine)
+      return fail(ctx, RMG_EINVAL, "level %d: n_coarse must be %s", l, l == 0 ? "0" : "n_fine/2");
+    if (v.n_samples < 1 || !v.d_basis_fine || !v.d_xi || (l > 0 && !v.d_basis_coarse))
+      return fail(ctx, RMG_EINVAL, "level %d: bad samples or NULL pointer", l);
+    if ((rc = check_problem(ctx, &v.fine, n_fields))) return rc;
+    if (l > 0 && (rc = check_problem(ctx, &v.coarse, n_fields))) return rc;
+    if ((rc = check_opts(ctx, opts, l > 0 ? v.n_coarse : v.n_fine))) return rc;
+    cls[v.n_fine].push_back({l, 0});
+    if (l > 0) cls[v.n_coarse].push_back({l, 1});
+  }
+  for (auto& kv : cls) {
+    if (kv.second.size() > 2) return fail(ctx, RMG_EINVAL, "grid %d used by more than two segments", kv.first);
+    if (kv.second.size() == 2 && kv.second[0].role == kv.second[1].role)
+      return fail(ctx, RMG_EINVAL, "grid %d appears twice in the same role", kv.first);
+    std::sort(kv.second.begin(), kv.second.end(), [](const Seg& a, const Seg& b) { return a.role < b.role; });
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+  // plan every class, then size the workspace once
+  std::vector<ClassJob> jobs;
+  std::vector<int> jn;
+  struct Out {
+    double *fields, *p, *qoi;
+    int32_t* status;
+    rmg_sample_stats* stats;
+  };
+  for (auto& kv : cls) {
+    ClassJob j;
+    const int n = kv.first;
+    int64_t S = 0;
+    for (auto& sg : kv.second) S += L[sg.level].n_samples;
+    if (S > 65535) return fail(ctx, RMG_EINVAL, "grid %d: more than 65535 solves", n);
+    j.a.n = n;
+    j.a.lg = ilog2i(n);
+    j.a.nlev = ilog2i(n) - ilog2i(opts->coarsest_n) + 1;
+    j.a.F = n_fields;
+    j.a.S = S;
+    const Seg& s0 = kv.second[0];
+    j.a.cp.prob[0] = s0.role == 0 ? L[s0.level].fine : L[s0.level].coarse;
+    j.a.cp.prob[1] = j.a.cp.prob[0];
+    j.a.cp.seg_split = L[s0.level].n_samples;
+    if (kv.second.size() == 2) {
+      const Seg& s1 = kv.second[1];
+      j.a.cp.prob[1] = s1.role == 0 ? L[s1.level].fine : L[s1.level].coarse;
+    }
+    j.a.nu1 = opts->nu1;
+    j.a.nu2 = opts->nu2;
+    j.a.cpp = opts->cycles_per_picard;
+    j.a.max_picard = opts->max_picard;
+    j.a.eps = opts->eps_picard;
+    class_plan(j, opts);
+    jobs.push_back(j);
+    jn.push_back(n);
+  }
+  size_t need = 0;
+  for (auto& j : jobs) {
+    const int64_t S = j.a.S;
+    const size_t N = (size_t)j.a.n * j.a.n;
+    need += class_ws_bytes(j) + 6 * 256 + 8 * S * n_fields * N + 8 * S * N + 8 * S + 4 * S +
+            sizeof(rmg_sample_stats) * S;
+  }
+  need += 256 + sizeof(rmg_level_sums) * n_levels;
+  if ((rc = reserve(ctx, need))) return rc;
+  Arena ar;
+  ar.base = (char*)ctx->ws;
+  ar.cap = ctx->ws_cap;
+  std::vector<Out> outs(jobs.size());
+  for (size_t c = 0; c < jobs.size(); ++c) {
+    ClassJob& j = jobs[c];
+    const int64_t S = j.a.S;
+    const size_t N = (size_t)j.a.n * j.a.n;
+    outs[c].fields = (double*)ar.take(8 * S * n_fields * N);
+    outs[c].p = (double*)ar.take(8 * S * N);
+    outs[c].qoi = (double*)ar.take(8 * S);
+    outs[c].status = (int32_t*)ar.take(4 * S);
+    outs[c].stats = (rmg_sample_stats*)ar.take(sizeof(rmg_sample_stats) * S);
+    j.a.fields = outs[c].fields;
+    j.a.p = outs[c].p;
+    j.a.qoi = outs[c].qoi;
+    j.a.status = outs[c].status;
+    j.a.stats = outs[c].stats;
+    class_carve(j, ar);
+  }
+  rmg_level_sums* d_sums = (rmg_level_sums*)ar.take(sizeof(rmg_level_sums) * n_levels);
+
+  // fields: both members of a pair draw from the same xi row through their own basis
+  for (size_t c = 0; c < jobs.size(); ++c) {
+    const size_t N = (size_t)jn[c] * jn[c];
+    int64_t row = 0;
+    for (auto& sg : cls[jn[c]]) {
+      const rmg_level& v = L[sg.level];
+      const double* B = sg.role == 0 ? v.d_basis_fine : v.d_basis_coarse;
+      HIP_TRY(ctx, launch_kl_fields((int)N, n_modes, v.n_samples * n_fields, n_fields, B, v.d_xi, h_marg,
+                                    outs[c].fields + (size_t)row * n_fields * N, stream));
+      row += v.n_samples;
+    }
+  }
+  // whole-sample classes on side streams, streaming classes each on their own stream
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
+  const int nside = (int)std::min<size_t>(jobs.size(), 7);
+  for (size_t c = 0; c < jobs.size(); ++c) {
+    jobs[c].stream = ctx->side[c % 7];
+    jobs[c].h_count = ctx->h_count + 4 * (int)(c % 16);
+  }
+  for (int q = 0; q < nside; ++q) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[q], ctx->ev[0], 0));
+  if ((rc = run_classes(ctx, jobs))) return rc;
+  for (int q = 0; q < nside; ++q) {
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1 + q], ctx->side[q]));
+    HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1 + q], 0));
+  }
+  // level sums and optional per-sample QoIs
+  int64_t qoff = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    const rmg_level& v = L[l];
+    auto locate = [&](int n, int role, const double** q, const int32_t** st, const rmg_sample_stats** ss) {
+      size_t c = std::find(jn.begin(), jn.end(), n) - jn.begin();
+      int64_t off = 0;
+      for (auto& sg : cls[n]) {
+        if (sg.role == role && sg.level == l) break;
+        off += L[sg.level].n_samples;
+      }
+      *q = outs[c].qoi + off;
+      *st = outs[c].status + off;
+      *ss = outs[c].stats + off;
+    };
+    const double *qf, *qc = nullptr;
+    const int32_t *sf, *sc = nullptr;
+    const rmg_sample_stats *tf, *tc = nullptr;
+    locate(v.n_fine, 0, &qf, &sf, &tf);
+    if (l > 0) locate(v.n_coarse, 1, &qc, &sc, &tc);
+    HIP_TRY(ctx, launch_level_sums(qf, qc, v.n_samples, sf, sc, tf, tc, d_sums + l, stream));
+    if (d_qoi_out) {
+      HIP_TRY(ctx, hipMemcpyAsync(d_qoi_out + qoff, qf, 8 * v.n_samples, hipMemcpyDeviceToDevice, stream));
+      if (qc) {
+        HIP_TRY(ctx, hipMemcpyAsync(d_qoi_out + qoff + v.n_samples, qc, 8 * v.n_samples,
+                                    hipMemcpyDeviceToDevice, stream));
+      } else {
+        std::vector<double> nanv(v.n_samples, std::nan(""));
+        HIP_TRY(ctx, hipMemcpyAsync(d_qoi_out + qoff + v.n_samples, nanv.data(), 8 * v.n_samples,
+                                    hipMemcpyHostToDevice, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+      }
+      qoff += 2 * v.n_samples;
+    }
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(h_out, d_sums, sizeof(rmg_level_sums) * n_levels, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  for (int l = 0; l < n_levels; ++l)
+    if (h_out[l].n_failed) return fail(ctx, RMG_ENOTCONV, "level %d: %lld failed pairs", l, (long long)h_out[l].n_failed);
+  return RMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal interfaces between the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rmg.h"
+
+namespace rmg {
+
+constexpr int kMaxLevels = 12;
+constexpr int kTile = 32;       // output tile edge of the level-streaming kernels
+constexpr int kCoarseTop = 32;  // streaming levels are those finer than this
+
+// Per-sample iteration state of the level-streaming path (device memory).
+struct SampleState {
+  int32_t active, new_step, step, it;
+  int32_t status, tot_its, cycles, nanflag;
+  double final_dp;
+};
+
+// Problems of one grid-size class: samples [0, seg_split) use prob[0], the rest prob[1].
+struct ClassProblems {
+  rmg_problem prob[2];
+  int64_t seg_split;
+};
+
+struct LevelPtrs {
+  void* u[kMaxLevels];
+  void* f[kMaxLevels];
+  void* cw[kMaxLevels];
+  void* cs[kMaxLevels];
+  void* cdt[kMaxLevels];
+  void* ctop[kMaxLevels];
+};
+
+struct SolveArgs {
+  int n, lg, nlev;  // nlev levels from n down to the coarsest grid
+  int F;
+  int64_t S;
+  const double* fields;
+  ClassProblems cp;
+  int nu1, nu2, cpp, max_picard;
+  double eps;
+  double* p;
+  double* theta_old;
+  double* qoi;
+  int32_t* status;
+  rmg_sample_stats* stats;
+};
+
+// LDS bytes of the whole-sample kernel for grid n (0 if it does not fit).
+size_t whole_sample_lds_bytes(int n, int nc, bool fp64);
+hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st);
+
+// Level-streaming path.
+struct StreamPlan {
+  int n, nlev, ltop;  // ltop: first level handled by the coarse LDS kernel
+  bool fp64;
+  LevelPtrs lv;
+  SampleState* state;
+  unsigned long long* dpmax;
+  int32_t* active_count;
+};
+hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
+hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
+hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
+size_t level_bytes(int m, int64_t S, bool fp64);
+
+// KL fields: out[r][c] = shift_f + exp(log_mean_f + scale_f * sum_k xi[r][k] B[k][c]), f = r mod F.
+hipError_t launch_kl_fields(int N, int M, int64_t rows, int F, const double* B, const double* xi,
+                            const rmg_marginal* marg, double* out, hipStream_t st);
+
+// Neumaier level sums of one MLMC level.
+hipError_t launch_level_sums(const double* qf, const double* qc, int64_t n, const int32_t* stf,
+                             const int32_t* stc, const rmg_sample_stats* sf,
+                             const rmg_sample_stats* sc, rmg_level_sums* out, hipStream_t st);
+
+}  // namespace rmg

@@ -1,0 +1,191 @@
+// Whole-grid multigrid levels held in LDS by one workgroup (gfx950, 160 KiB LDS per CU).
+//
+// Layout of a level with m x m cells (element type R):
+//   u   : one zero row, m*m cells, one zero row (plus one guard each end), so
+//         u[c - m], u[c + m], u[c - 1], u[c + 1] are always readable; neighbours
+//         outside the domain read 0 and meet a zero or Dirichlet-only coefficient;
+//   f, cdt : m*m;
+//   cw  : m*m + 1, cw[j*m] = 0 (no-flux left face) and cw[m*m] = 0, so the east
+//         coefficient cw[c + 1] of a right-edge cell is the next row's left face = 0;
+//   cs  : (m+1)*m, rows 0..m-1 are south faces (row 0: bottom Dirichlet weight),
+//         row m holds the top Dirichlet weights, so the north coefficient is cs[c + m].
+// The zero rows and guards are written once when the workgroup starts.
+#pragma once
+
+#include "rmg_device.hpp"
+
+namespace rmg {
+
+template <class R>
+struct LdsLevel {
+  R* u;
+  R* f;
+  R* cw;
+  R* cs;
+  R* cdt;
+  int m, lg;  // m = 1 << lg
+};
+
+// Elements of R needed by one level.
+__host__ __device__ constexpr int lds_level_elems(int m) {
+  return ((m + 2) * m + 2) + m * m + (m * m + 1) + (m + 1) * m + m * m;
+}
+
+// Carve levels of sizes m_top, m_top/2, ..., m_bottom out of `base`; returns the
+// end pointer.  The level table `lev` lives in LDS (a runtime-indexed table in
+// registers would be spilled to scratch); thread 0 fills it, the caller must
+// synchronise before reading it.
+template <class R>
+__device__ R* lds_carve(R* base, LdsLevel<R>* lev, int m_top, int nlev) {
+  R* p = base;
+  int m = m_top;
+  int lg = 31 - __clz(m_top);
+  const bool w = threadIdx.x == 0;
+  for (int l = 0; l < nlev; ++l) {
+    if (w) {
+      lev[l].m = m;
+      lev[l].lg = lg;
+      lev[l].u = p + 1 + m;
+    }
+    p += (m + 2) * m + 2;
+    if (w) lev[l].f = p;
+    p += m * m;
+    if (w) lev[l].cw = p;
+    p += m * m + 1;
+    if (w) lev[l].cs = p;
+    p += (m + 1) * m;
+    if (w) lev[l].cdt = p;
+    p += m * m;
+    m >>= 1;
+    --lg;
+  }
+  return p;
+}
+
+template <class R>
+__device__ __forceinline__ St5<R> lds_st5(const LdsLevel<R>& L, int c) {
+  const int m = L.m;
+  return st5<R>(L.cdt[c], L.cw[c], L.cw[c + 1], L.cs[c], L.cs[c + m], L.u[c - 1], L.u[c + 1],
+                L.u[c - m], L.u[c + m]);
+}
+
+// One colour of a red-black Gauss-Seidel sweep (colour 0 = red = (i+j) even).
+template <class R>
+__device__ void lds_half_sweep(const LdsLevel<R>& L, int colour) {
+  const int m = L.m, hlg = L.lg - 1;
+  const int tot = (m * m) >> 1;
+  for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+    const int j = k >> hlg;
+    const int q = k - (j << hlg);
+    const int i = 2 * q + ((j + colour) & 1);
+    const int c = j * m + i;
+    L.u[c] = gs_value<R>(L.f[c], lds_st5(L, c));
+  }
+}
+
+template <class R>
+__device__ void lds_sweeps(const LdsLevel<R>& L, int nu) {
+  for (int s = 0; s < nu; ++s) {
+    lds_half_sweep(L, 0);
+    __syncthreads();
+    lds_half_sweep(L, 1);
+    __syncthreads();
+  }
+}
+
+// Coarse right-hand side = R (f - A u); coarse initial iterate 0.
+template <class R>
+__device__ void lds_residual_restrict(const LdsLevel<R>& F, const LdsLevel<R>& C) {
+  const int mc = C.m, m = F.m;
+  for (int kc = threadIdx.x; kc < mc * mc; kc += blockDim.x) {
+    const int J = kc >> C.lg, I = kc - (J << C.lg);
+    const int c00 = (2 * J) * m + 2 * I;
+    const R r00 = residual_value<R>(F.f[c00], F.u[c00], lds_st5(F, c00));
+    const R r01 = residual_value<R>(F.f[c00 + 1], F.u[c00 + 1], lds_st5(F, c00 + 1));
+    const R r10 = residual_value<R>(F.f[c00 + m], F.u[c00 + m], lds_st5(F, c00 + m));
+    const R r11 = residual_value<R>(F.f[c00 + m + 1], F.u[c00 + m + 1], lds_st5(F, c00 + m + 1));
+    C.f[kc] = restrict4<R>(r00, r01, r10, r11);
+    C.u[kc] = (R)0;
+  }
+}
+
+// Piecewise-constant prolongation of the coarse correction (eq. transfer).
+template <class R>
+__device__ void lds_prolong_add(const LdsLevel<R>& F, const LdsLevel<R>& C) {
+  const int m = F.m;
+  for (int c = threadIdx.x; c < m * m; c += blockDim.x) {
+    const int j = c >> F.lg, i = c - (j << F.lg);
+    F.u[c] = F.u[c] + C.u[(j >> 1) * C.m + (i >> 1)];
+  }
+}
+
+// Coefficients of the next coarser level.
+template <class R>
+__device__ void lds_coarsen(const LdsLevel<R>& F, const LdsLevel<R>& C) {
+  const int mc = C.m, m = F.m;
+  for (int kc = threadIdx.x; kc < mc * mc; kc += blockDim.x) {
+    const int J = kc >> C.lg, I = kc - (J << C.lg);
+    const int c00 = (2 * J) * m + 2 * I;
+    C.cw[kc] = coarse_face<R>(F.cw[c00], F.cw[c00 + m]);
+    C.cs[kc] = coarse_face<R>(F.cs[c00], F.cs[c00 + 1]);
+    C.cdt[kc] = coarse_cdt<R>(F.cdt[c00], F.cdt[c00 + 1], F.cdt[c00 + m], F.cdt[c00 + m + 1]);
+  }
+  for (int I = threadIdx.x; I < mc; I += blockDim.x)
+    C.cs[mc * mc + I] = coarse_face<R>(F.cs[m * m + 2 * I], F.cs[m * m + 2 * I + 1]);
+}
+
+// Exact solve on the coarsest level in FP64: Gauss-Jordan elimination without
+// pivoting on the symmetric positive definite matrix, one barrier per pivot.
+// `A` is LDS scratch of N*(N+1) doubles, N = m*m <= 64.
+template <class R>
+__device__ void lds_coarsest_solve(const LdsLevel<R>& L, double* A) {
+  const int m = L.m, N = m * m, W = N + 1;
+  for (int e = threadIdx.x; e < N * W; e += blockDim.x) A[e] = 0.0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    const int j = c / m, i = c - j * m;
+    const double aw = (double)L.cw[c], ae = (double)L.cw[c + 1];
+    const double as = (double)L.cs[c], an = (double)L.cs[c + m];
+    const St5<double> s = st5<double>((double)L.cdt[c], aw, ae, as, an, 0.0, 0.0, 0.0, 0.0);
+    double* row = A + c * W;
+    row[c] = s.d;
+    if (i > 0) row[c - 1] = -aw;
+    if (i < m - 1) row[c + 1] = -ae;
+    if (j > 0) row[c - m] = -as;
+    if (j < m - 1) row[c + m] = -an;
+    row[N] = (double)L.f[c];
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    // rows i != k lose their column-k entry; only columns > k change, so the
+    // entries read in this step (column k and row k) are not written in it
+    const int cols = N - k;  // columns k+1 .. N
+    for (int e = threadIdx.x; e < (N - 1) * cols; e += blockDim.x) {
+      int i = e / cols;
+      const int jj = k + 1 + (e - i * cols);
+      if (i >= k) ++i;
+      A[i * W + jj] -= (A[i * W + k] / A[k * W + k]) * A[k * W + jj];
+    }
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < N; c += blockDim.x) L.u[c] = (R)(A[c * W + N] / A[c * W + c]);
+  __syncthreads();
+}
+
+// One V(nu1, nu2) cycle from level `top` of the LDS hierarchy (levels top .. nlev-1).
+template <class R>
+__device__ void lds_vcycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, double* A) {
+  for (int l = top; l < nlev - 1; ++l) {
+    lds_sweeps(lev[l], nu1);
+    lds_residual_restrict(lev[l], lev[l + 1]);
+    __syncthreads();
+  }
+  lds_coarsest_solve(lev[nlev - 1], A);
+  for (int l = nlev - 2; l >= top; --l) {
+    lds_prolong_add(lev[l], lev[l + 1]);
+    __syncthreads();
+    lds_sweeps(lev[l], nu2);
+  }
+}
+
+}  // namespace rmg

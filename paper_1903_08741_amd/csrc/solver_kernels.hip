@@ -1,0 +1,691 @@
+// Batched modified-Picard / cell-centred multigrid solver kernels (gfx950).
+//
+// Two execution shapes share the per-cell arithmetic of rmg_device.hpp and
+// therefore produce bit-identical iterates:
+//   * whole-sample kernel: one workgroup owns one sample for its whole time
+//     integration; every multigrid level lives in LDS (n <= 64 in FP32,
+//     n <= 32 in FP64), the FP64 state p, theta_old, fields stay in global memory;
+//   * level-streaming kernels: one launch per phase of a Picard iteration over
+//     all samples of a grid size, 32 x 32 output tiles staged in LDS with a halo
+//     wide enough to fuse nu red-black sweeps with the residual/restriction
+//     (down leg) or with the prolongation (up leg); levels of 32 x 32 and
+//     coarser are handled by one workgroup per sample in LDS.
+// Section 4.1 (modified Picard) and Section 4.2 (cell-centred multigrid).
+#include <math.h>
+
+#include "rmg_device.hpp"
+#include "rmg_internal.hpp"
+#include "rmg_lds.hpp"
+
+namespace rmg {
+
+__device__ __forceinline__ const rmg_problem& class_problem(const ClassProblems& cp, int64_t s) {
+  return s < cp.seg_split ? cp.prob[0] : cp.prob[1];
+}
+
+// Mean effective saturation (theta - theta_r)/(theta_s - theta_r) over the cells,
+// summed by each thread over cells t, t + blockDim, ... and then in a fixed tree.
+__device__ double mean_saturation(const rmg_problem& P, const double* fields, int F, int64_t N,
+                                  int64_t s, const double* p, double* red) {
+  double acc = 0.0;
+  for (int64_t c = threadIdx.x; c < N; c += blockDim.x) {
+    const CellFields cf = load_fields(fields, F, N, s, c);
+    const Closure cl = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg);
+    acc += (cl.theta - P.theta_r) / (P.theta_s - P.theta_r);
+  }
+  return block_sum(acc, red) / (double)N;
+}
+
+// ============================================================ whole sample
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_whole_sample(SolveArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t s = blockIdx.x;
+  const rmg_problem P = class_problem(a.cp, s);
+  const int n = a.n, lg = a.lg;
+  const int64_t N = (int64_t)n * n;
+  const int mc = n >> (a.nlev - 1), NC = mc * mc;
+
+  double* Kc = (double*)smem;
+  double* A = Kc + N;
+  double* red = A + NC * (NC + 1);
+  R* rbase = (R*)(red + kBlock);
+  __shared__ LdsLevel<R> lev[kMaxLevels];
+  R* rend = lds_carve(rbase, lev, n, a.nlev);
+  for (R* q = rbase + threadIdx.x; q < rend; q += blockDim.x) *q = (R)0;
+
+  double* p = a.p + s * N;
+  double* thold = a.theta_old + s * N;
+  for (int64_t c = threadIdx.x; c < N; c += blockDim.x) p[c] = P.h_init;
+  __syncthreads();
+
+  int step = 0, it = 0, new_step = 1, status = RMG_SAMPLE_OK, tot_its = 0, cycles = 0;
+  double dp = 0.0;
+  const LdsLevel<R>& L0 = lev[0];
+  for (;;) {
+    // conductivity at every cell (FP64)
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+      Kc[c] = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg).K;
+    }
+    __syncthreads();
+    // outer residual and fine-level coefficients
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      const int j = c >> lg, i = c - (j << lg);
+      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+      const Closure cl = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg);
+      double th_old;
+      if (new_step) {
+        th_old = cl.theta;
+        thold[c] = cl.theta;
+      } else {
+        th_old = thold[c];
+      }
+      const double pw = i > 0 ? p[c - 1] : 0.0, pe = i < n - 1 ? p[c + 1] : 0.0;
+      const double ps = j > 0 ? p[c - n] : 0.0, pn = j < n - 1 ? p[c + n] : 0.0;
+      const double Kw = i > 0 ? Kc[c - 1] : 0.0, Ke = i < n - 1 ? Kc[c + 1] : 0.0;
+      const double Ks_ = j > 0 ? Kc[c - n] : 0.0, Kn = j < n - 1 ? Kc[c + n] : 0.0;
+      const FineCell fc = fine_cell(i, j, n, p[c], pw, pe, ps, pn, Kc[c], Kw, Ke, Ks_, Kn, cl.theta,
+                                    th_old, cl.C, P.dt, P.h_bottom, P.h_top);
+      L0.f[c] = (R)fc.f;
+      L0.cw[c] = (R)fc.cw;
+      L0.cs[c] = (R)fc.cs;
+      L0.cdt[c] = (R)fc.cdt;
+      if (j == n - 1) L0.cs[c + n] = (R)fc.ctop;
+      L0.u[c] = (R)0;
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < a.nlev; ++l) {
+      lds_coarsen(lev[l], lev[l + 1]);
+      __syncthreads();
+    }
+    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_vcycle(lev, 0, a.nlev, a.nu1, a.nu2, A);
+    // Picard update p <- p + dp and ||dp||_inf
+    double mx = 0.0, bad = 0.0;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      const double d = (double)L0.u[c];
+      p[c] += d;
+      mx = fmax(mx, fabs(d));
+      if (!isfinite(d)) bad = 1.0;
+    }
+    dp = block_max(mx, red);
+    const double anybad = block_max(bad, red);
+    ++it;
+    ++tot_its;
+    cycles += a.cpp;
+    if (anybad > 0.0) {
+      status = RMG_SAMPLE_NONFINITE;
+      break;
+    }
+    if (dp < a.eps) {
+      ++step;
+      it = 0;
+      new_step = 1;
+      if (step == P.n_steps) break;
+    } else {
+      new_step = 0;
+      if (it >= a.max_picard) {
+        status = RMG_SAMPLE_MAXITER;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  const double q = mean_saturation(P, a.fields, a.F, N, s, p, red);
+  if (threadIdx.x == 0) {
+    a.qoi[s] = status == RMG_SAMPLE_OK ? q : __longlong_as_double(0x7ff8000000000000ll);
+    a.status[s] = status;
+    if (a.stats) {
+      rmg_sample_stats st;
+      st.picard_its = tot_its;
+      st.mg_cycles = cycles;
+      st.steps_done = step;
+      st.status = status;
+      st.final_dp_inf = dp;
+      a.stats[s] = st;
+    }
+  }
+}
+
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+size_t whole_sample_lds_bytes(int n, int nc, bool fp64) {
+  const int nlev = ilog2(n) - ilog2(nc) + 1;
+  size_t relems = 0;
+  for (int l = 0, m = n; l < nlev; ++l, m >>= 1) relems += lds_level_elems(m);
+  const size_t NC = (size_t)nc * nc;
+  size_t bytes = 8 * ((size_t)n * n + NC * (NC + 1) + kBlock) + relems * (fp64 ? 8 : 4);
+  return bytes <= 160 * 1024 ? bytes : 0;
+}
+
+hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
+  const int nc = a.n >> (a.nlev - 1);
+  const size_t lds = whole_sample_lds_bytes(a.n, nc, fp64);
+  if (lds == 0) return hipErrorInvalidValue;
+  hipError_t e;
+  if (fp64) {
+    e = hipFuncSetAttribute((const void*)k_whole_sample<double>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_whole_sample<double>, dim3((unsigned)a.S), dim3(kBlock), lds, st, a);
+  } else {
+    e = hipFuncSetAttribute((const void*)k_whole_sample<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_whole_sample<float>, dim3((unsigned)a.S), dim3(kBlock), lds, st, a);
+  }
+  return hipGetLastError();
+}
+
+// ============================================================ level streaming
+__global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long long* dpmax) {
+  const int64_t N = (int64_t)a.n * a.n;
+  const int64_t tot = a.S * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / N;
+    a.p[e] = class_problem(a.cp, s).h_init;
+  }
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < a.S;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    SampleState z;
+    z.active = 1;
+    z.new_step = 1;
+    z.step = 0;
+    z.it = 0;
+    z.status = RMG_SAMPLE_OK;
+    z.tot_its = 0;
+    z.cycles = 0;
+    z.nanflag = 0;
+    z.final_dp = 0.0;
+    state[s] = z;
+    dpmax[s] = 0ull;
+  }
+}
+
+// Outer residual + fine coefficients for one tile, then the coarser levels
+// 1 .. ltop of the same tile by in-tile coarsening (cells of level l inside a
+// 32 x 32 fine tile are complete for 2^l <= 32).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
+  __shared__ double sp[34 * 34], sK[34 * 34];
+  __shared__ R bufA[3 * 32 * 32 + 32], bufB[3 * 16 * 16 + 16];
+  const int64_t s = blockIdx.y;
+  if (blockIdx.x == 0 && s == 0 && threadIdx.x == 0) *pl.active_count = 0;
+  if (!pl.state[s].active) return;
+  const int new_step = pl.state[s].new_step;
+  const rmg_problem P = class_problem(a.cp, s);
+  const int n = a.n;
+  const int T = n < kTile ? n : kTile, TL = T + 2;
+  const int ntx = n / T;
+  const int x0 = (blockIdx.x % ntx) * T, y0 = (blockIdx.x / ntx) * T;
+  const int64_t N = (int64_t)n * n;
+  const double* p = a.p + s * N;
+  for (int e = threadIdx.x; e < TL * TL; e += blockDim.x) {
+    const int lj = e / TL, li = e - lj * TL;
+    const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
+    double pv = 0.0, K = 0.0;
+    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+      const int64_t c = (int64_t)gj * n + gi;
+      pv = p[c];
+      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+      K = closure(P, pv, cf.Ks, cf.alpha, cf.nvg).K;
+    }
+    sp[e] = pv;
+    sK[e] = K;
+  }
+  __syncthreads();
+  R* tcw = bufA;
+  R* tcdt = bufA + T * T;
+  R* tcs = bufA + 2 * T * T;  // (T+1) x T, row T = top Dirichlet weights
+  R* f0 = (R*)pl.lv.f[0] + s * N;
+  R* cw0 = (R*)pl.lv.cw[0] + s * N;
+  R* cs0 = (R*)pl.lv.cs[0] + s * N;
+  R* cdt0 = (R*)pl.lv.cdt[0] + s * N;
+  R* ctop0 = (R*)pl.lv.ctop[0] + s * n;
+  double* thold = a.theta_old + s * N;
+  for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+    const int lj = e / T, li = e - lj * T;
+    const int gi = x0 + li, gj = y0 + lj;
+    const int64_t c = (int64_t)gj * n + gi;
+    const int le = (lj + 1) * TL + li + 1;
+    const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+    const Closure cl = closure(P, sp[le], cf.Ks, cf.alpha, cf.nvg);
+    double th_old;
+    if (new_step) {
+      th_old = cl.theta;
+      thold[c] = cl.theta;
+    } else {
+      th_old = thold[c];
+    }
+    const FineCell fc = fine_cell(gi, gj, n, sp[le], sp[le - 1], sp[le + 1], sp[le - TL], sp[le + TL],
+                                  sK[le], sK[le - 1], sK[le + 1], sK[le - TL], sK[le + TL], cl.theta,
+                                  th_old, cl.C, P.dt, P.h_bottom, P.h_top);
+    const R rf = (R)fc.f, rcw = (R)fc.cw, rcs = (R)fc.cs, rcdt = (R)fc.cdt;
+    f0[c] = rf;
+    cw0[c] = rcw;
+    cs0[c] = rcs;
+    cdt0[c] = rcdt;
+    tcw[e] = rcw;
+    tcs[e] = rcs;
+    tcdt[e] = rcdt;
+    if (lj == T - 1) {
+      const R rct = (R)fc.ctop;
+      tcs[T * T + li] = rct;
+      if (gj == n - 1) ctop0[gi] = rct;
+    }
+  }
+  // in-tile coarsening, ping-pong between bufA and bufB
+  R* src = bufA;
+  R* dst = bufB;
+  int t = T;
+  for (int l = 1; l <= pl.ltop; ++l) {
+    __syncthreads();
+    const int tc = t >> 1;
+    const int m = n >> l;
+    const int64_t M2 = (int64_t)m * m;
+    R* scw = src;
+    R* scdt = src + t * t;
+    R* scs = src + 2 * t * t;
+    R* dcw = dst;
+    R* dcdt = dst + tc * tc;
+    R* dcs = dst + 2 * tc * tc;
+    R* gcw = (R*)pl.lv.cw[l] + s * M2;
+    R* gcs = (R*)pl.lv.cs[l] + s * M2;
+    R* gcdt = (R*)pl.lv.cdt[l] + s * M2;
+    R* gctop = (R*)pl.lv.ctop[l] + s * m;
+    const int X0 = x0 >> l, Y0 = y0 >> l;
+    for (int e = threadIdx.x; e < tc * tc; e += blockDim.x) {
+      const int J = e / tc, I = e - J * tc;
+      const int f00 = (2 * J) * t + 2 * I;
+      const R cw = coarse_face<R>(scw[f00], scw[f00 + t]);
+      const R cs = coarse_face<R>(scs[f00], scs[f00 + 1]);
+      const R cd = coarse_cdt<R>(scdt[f00], scdt[f00 + 1], scdt[f00 + t], scdt[f00 + t + 1]);
+      dcw[e] = cw;
+      dcs[e] = cs;
+      dcdt[e] = cd;
+      const int64_t gc = (int64_t)(Y0 + J) * m + X0 + I;
+      gcw[gc] = cw;
+      gcs[gc] = cs;
+      gcdt[gc] = cd;
+    }
+    for (int I = threadIdx.x; I < tc; I += blockDim.x) {
+      const R ct = coarse_face<R>(scs[t * t + 2 * I], scs[t * t + 2 * I + 1]);
+      dcs[tc * tc + I] = ct;
+      if (y0 + T == n) gctop[X0 + I] = ct;
+    }
+    R* tmp = src;
+    src = dst;
+    dst = tmp;
+    t = tc;
+  }
+}
+
+// Shared loader of a (32 + 2H)^2 tile of level arrays into LDS.  Cells outside
+// the domain get u = f = cw = cdt = 0; the row just above the top boundary gets
+// cs = ctop so that the north coefficient of top cells is the Dirichlet weight.
+template <class R>
+struct TileLds {
+  R *u, *f, *cw, *cs, *cdt;
+  int TW;
+};
+
+template <class R>
+__device__ void tile_load(const TileLds<R>& L, int H, int m, int x0, int y0, const R* U, const R* UC,
+                          int mc, const R* F, const R* CW, const R* CS, const R* CDT, const R* CTOP,
+                          bool u_zero) {
+  const int TW = L.TW;
+  for (int e = threadIdx.x; e < TW * TW; e += blockDim.x) {
+    const int lj = e / TW, li = e - lj * TW;
+    const int gi = x0 - H + li, gj = y0 - H + lj;
+    R u = (R)0, f = (R)0, cw = (R)0, cs = (R)0, cdt = (R)0;
+    if (gi >= 0 && gi < m && gj >= 0 && gj < m) {
+      const int64_t c = (int64_t)gj * m + gi;
+      if (!u_zero) u = U[c];
+      if (UC) u = u + UC[(int64_t)(gj >> 1) * mc + (gi >> 1)];
+      f = F[c];
+      cw = CW[c];
+      cs = CS[c];
+      cdt = CDT[c];
+    } else if (gj == m && gi >= 0 && gi < m) {
+      cs = CTOP[gi];
+    }
+    L.u[e] = u;
+    L.f[e] = f;
+    L.cw[e] = cw;
+    L.cs[e] = cs;
+    L.cdt[e] = cdt;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ St5<R> tile_st5(const TileLds<R>& L, int e) {
+  const int TW = L.TW;
+  return st5<R>(L.cdt[e], L.cw[e], L.cw[e + 1], L.cs[e], L.cs[e + TW], L.u[e - 1], L.u[e + 1],
+                L.u[e - TW], L.u[e + TW]);
+}
+
+// One colour over the tile grown by `grow` cells on each side (clipped to the domain).
+template <class R>
+__device__ void tile_half_sweep(const TileLds<R>& L, int H, int m, int x0, int y0, int grow,
+                                int colour) {
+  const int TW = L.TW;
+  const int lo = H - grow, hi = H + kTile + grow;
+  const int w = hi - lo;
+  for (int k = threadIdx.x; k < w * w; k += blockDim.x) {
+    const int rj = k / w, ri = k - rj * w;
+    const int li = lo + ri, lj = lo + rj;
+    const int gi = x0 - H + li, gj = y0 - H + lj;
+    if (gi < 0 || gi >= m || gj < 0 || gj >= m || ((gi + gj) & 1) != colour) continue;
+    const int e = lj * TW + li;
+    L.u[e] = gs_value<R>(L.f[e], tile_st5(L, e));
+  }
+}
+
+template <class R>
+__device__ TileLds<R> tile_carve(unsigned char* smem, int TW) {
+  TileLds<R> L;
+  R* b = (R*)smem;
+  const int A = TW * TW;
+  L.u = b;
+  L.f = b + A;
+  L.cw = b + 2 * A;
+  L.cs = b + 3 * A;
+  L.cdt = b + 4 * A;
+  L.TW = TW;
+  return L;
+}
+
+// Down leg on a streaming level l: nu1 sweeps, residual, restriction.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t s = blockIdx.y;
+  if (!pl.state[s].active) return;
+  const int m = a.n >> l, mc = m >> 1;
+  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
+  const int H = 2 * a.nu1 + 1, TW = kTile + 2 * H;
+  const int ntx = m / kTile;
+  const int x0 = (blockIdx.x % ntx) * kTile, y0 = (blockIdx.x / ntx) * kTile;
+  const TileLds<R> L = tile_carve<R>(smem, TW);
+  R* U = (R*)pl.lv.u[l] + s * M2;
+  tile_load<R>(L, H, m, x0, y0, U, nullptr, 0, (const R*)pl.lv.f[l] + s * M2,
+               (const R*)pl.lv.cw[l] + s * M2, (const R*)pl.lv.cs[l] + s * M2,
+               (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m, u_zero != 0);
+  __syncthreads();
+  for (int st = 0; st < 2 * a.nu1; ++st) {
+    tile_half_sweep(L, H, m, x0, y0, 2 * a.nu1 - st, st & 1);
+    __syncthreads();
+  }
+  // residual and restriction of the 16 x 16 coarse cells of the tile
+  R* FC = (R*)pl.lv.f[l + 1] + s * MC2;
+  for (int e = threadIdx.x; e < (kTile / 2) * (kTile / 2); e += blockDim.x) {
+    const int J = e / (kTile / 2), I = e - J * (kTile / 2);
+    const int t00 = (H + 2 * J) * TW + H + 2 * I;
+    const R r00 = residual_value<R>(L.f[t00], L.u[t00], tile_st5(L, t00));
+    const R r01 = residual_value<R>(L.f[t00 + 1], L.u[t00 + 1], tile_st5(L, t00 + 1));
+    const R r10 = residual_value<R>(L.f[t00 + TW], L.u[t00 + TW], tile_st5(L, t00 + TW));
+    const R r11 = residual_value<R>(L.f[t00 + TW + 1], L.u[t00 + TW + 1], tile_st5(L, t00 + TW + 1));
+    FC[(int64_t)((y0 >> 1) + J) * mc + (x0 >> 1) + I] = restrict4<R>(r00, r01, r10, r11);
+  }
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int lj = e / kTile, li = e - lj * kTile;
+    U[(int64_t)(y0 + lj) * m + x0 + li] = L.u[(H + lj) * TW + H + li];
+  }
+}
+
+// Up leg on a streaming level l: prolongation of level l+1, nu2 sweeps; on the
+// finest level (final != 0) the Picard update p += dp and ||dp||_inf instead of a store.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final_) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[kBlock / 64];
+  const int64_t s = blockIdx.y;
+  if (!pl.state[s].active) return;
+  const int m = a.n >> l, mc = m >> 1;
+  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
+  const int H = 2 * a.nu2, TW = kTile + 2 * H;
+  const int ntx = m / kTile;
+  const int x0 = (blockIdx.x % ntx) * kTile, y0 = (blockIdx.x / ntx) * kTile;
+  const TileLds<R> L = tile_carve<R>(smem, TW);
+  R* U = (R*)pl.lv.u[l] + s * M2;
+  tile_load<R>(L, H, m, x0, y0, U, (const R*)pl.lv.u[l + 1] + s * MC2, mc,
+               (const R*)pl.lv.f[l] + s * M2, (const R*)pl.lv.cw[l] + s * M2,
+               (const R*)pl.lv.cs[l] + s * M2, (const R*)pl.lv.cdt[l] + s * M2,
+               (const R*)pl.lv.ctop[l] + s * m, false);
+  __syncthreads();
+  for (int st = 0; st < 2 * a.nu2; ++st) {
+    tile_half_sweep(L, H, m, x0, y0, 2 * a.nu2 - 1 - st, st & 1);
+    __syncthreads();
+  }
+  if (!final_) {
+    for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+      const int lj = e / kTile, li = e - lj * kTile;
+      U[(int64_t)(y0 + lj) * m + x0 + li] = L.u[(H + lj) * TW + H + li];
+    }
+    return;
+  }
+  double* p = a.p + s * M2;
+  double mx = 0.0, bad = 0.0;
+  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
+    const int lj = e / kTile, li = e - lj * kTile;
+    const double d = (double)L.u[(H + lj) * TW + H + li];
+    p[(int64_t)(y0 + lj) * m + x0 + li] += d;
+    mx = fmax(mx, fabs(d));
+    if (!isfinite(d)) bad = 1.0;
+  }
+  mx = block_max(mx, red);
+  bad = block_max(bad, red);
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(pl.dpmax + s, mx);
+    if (bad > 0.0) atomicOr(&pl.state[s].nanflag, 1);
+  }
+}
+
+// Levels ltop .. nlev-1 of one sample in LDS: load level ltop, coarsen, V-cycle,
+// store its correction (or, when ltop is the finest level, apply the Picard update).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero,
+                                                     int final_) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t s = blockIdx.x;
+  if (!pl.state[s].active) return;
+  const int lt = pl.ltop;
+  const int m = a.n >> lt;
+  const int nlev = a.nlev - lt;
+  const int mc = a.n >> (a.nlev - 1), NC = mc * mc;
+  const int64_t M2 = (int64_t)m * m;
+  double* A = (double*)smem;
+  double* red = A + NC * (NC + 1);
+  R* rbase = (R*)(red + kBlock / 64);
+  __shared__ LdsLevel<R> lev[kMaxLevels];
+  R* rend = lds_carve(rbase, lev, m, nlev);
+  for (R* q = rbase + threadIdx.x; q < rend; q += blockDim.x) *q = (R)0;
+  __syncthreads();
+  const LdsLevel<R>& T = lev[0];
+  const R* F = (const R*)pl.lv.f[lt] + s * M2;
+  const R* CW = (const R*)pl.lv.cw[lt] + s * M2;
+  const R* CS = (const R*)pl.lv.cs[lt] + s * M2;
+  const R* CDT = (const R*)pl.lv.cdt[lt] + s * M2;
+  const R* CT = (const R*)pl.lv.ctop[lt] + s * m;
+  R* U = (R*)pl.lv.u[lt] + s * M2;
+  for (int c = threadIdx.x; c < M2; c += blockDim.x) {
+    T.f[c] = F[c];
+    T.cw[c] = CW[c];
+    T.cs[c] = CS[c];
+    T.cdt[c] = CDT[c];
+    if (!u_zero) T.u[c] = U[c];
+  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x) T.cs[M2 + i] = CT[i];
+  __syncthreads();
+  for (int l = 0; l + 1 < nlev; ++l) {
+    lds_coarsen(lev[l], lev[l + 1]);
+    __syncthreads();
+  }
+  lds_vcycle(lev, 0, nlev, a.nu1, a.nu2, A);
+  if (lt > 0 || !final_) {
+    for (int c = threadIdx.x; c < M2; c += blockDim.x) U[c] = T.u[c];
+    return;
+  }
+  double* p = a.p + s * M2;
+  double mx = 0.0, bad = 0.0;
+  for (int c = threadIdx.x; c < M2; c += blockDim.x) {
+    const double d = (double)T.u[c];
+    p[c] += d;
+    mx = fmax(mx, fabs(d));
+    if (!isfinite(d)) bad = 1.0;
+  }
+  mx = block_max(mx, red);
+  bad = block_max(bad, red);
+  if (threadIdx.x == 0) {
+    pl.dpmax[s] = (unsigned long long)__double_as_longlong(mx);
+    if (bad > 0.0) pl.state[s].nanflag = 1;
+  }
+}
+
+// Per-sample stopping test and time-step bookkeeping after one Picard iteration.
+__global__ void k_control(SolveArgs a, StreamPlan pl) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  SampleState st = pl.state[s];
+  if (!st.active) return;
+  const rmg_problem& P = class_problem(a.cp, s);
+  const double dp = __longlong_as_double((long long)pl.dpmax[s]);
+  pl.dpmax[s] = 0ull;
+  st.it += 1;
+  st.tot_its += 1;
+  st.cycles += a.cpp;
+  st.final_dp = dp;
+  if (st.nanflag) {
+    st.status = RMG_SAMPLE_NONFINITE;
+    st.active = 0;
+  } else if (dp < a.eps) {
+    st.step += 1;
+    st.it = 0;
+    st.new_step = 1;
+    if (st.step == P.n_steps) st.active = 0;
+  } else {
+    st.new_step = 0;
+    if (st.it >= a.max_picard) {
+      st.status = RMG_SAMPLE_MAXITER;
+      st.active = 0;
+    }
+  }
+  pl.state[s] = st;
+  if (st.active) atomicAdd(pl.active_count, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPlan pl) {
+  __shared__ double red[kBlock];
+  const int64_t s = blockIdx.x;
+  const rmg_problem P = class_problem(a.cp, s);
+  const int64_t N = (int64_t)a.n * a.n;
+  const double q = mean_saturation(P, a.fields, a.F, N, s, a.p + s * N, red);
+  if (threadIdx.x == 0) {
+    const SampleState st = pl.state[s];
+    a.qoi[s] = st.status == RMG_SAMPLE_OK ? q : __longlong_as_double(0x7ff8000000000000ll);
+    a.status[s] = st.status;
+    if (a.stats) {
+      rmg_sample_stats o;
+      o.picard_its = st.tot_its;
+      o.mg_cycles = st.cycles;
+      o.steps_done = st.step;
+      o.status = st.status;
+      o.final_dp_inf = st.final_dp;
+      a.stats[s] = o;
+    }
+  }
+}
+
+size_t level_bytes(int m, int64_t S, bool fp64) {
+  const size_t es = fp64 ? 8 : 4;
+  return es * (size_t)S * (5 * (size_t)m * m + (size_t)m);
+}
+
+hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+  const int64_t tot = a.S * (int64_t)a.n * a.n;
+  int64_t blocks = (tot + kBlock - 1) / kBlock;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_stream_init, dim3((unsigned)blocks), dim3(kBlock), 0, st, a, pl.state, pl.dpmax);
+  return hipGetLastError();
+}
+
+static size_t tile_lds(int H, bool fp64) {
+  const size_t TW = kTile + 2 * H;
+  return 5 * TW * TW * (fp64 ? 8 : 4);
+}
+
+static size_t coarse_lds(int m, int nc, bool fp64) {
+  size_t relems = 0;
+  for (int mm = m; mm >= nc; mm >>= 1) relems += lds_level_elems(mm);
+  const size_t NC = (size_t)nc * nc;
+  return 8 * (NC * (NC + 1) + kBlock / 64) + relems * (fp64 ? 8 : 4);
+}
+
+template <class R>
+static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+  const bool fp64 = sizeof(R) == 8;
+  const dim3 blk(kBlock);
+  const int n = a.n;
+  {
+    const int T = n < kTile ? n : kTile;
+    const unsigned tiles = (unsigned)((n / T) * (n / T));
+    hipLaunchKernelGGL(k_fine<R>, dim3(tiles, (unsigned)a.S), blk, 0, st, a, pl);
+  }
+  const int nc = n >> (a.nlev - 1);
+  const size_t ldn = tile_lds(2 * a.nu1 + 1, fp64), lup = tile_lds(2 * a.nu2, fp64);
+  const size_t lcv = coarse_lds(n >> pl.ltop, nc, fp64);
+  for (int cyc = 0; cyc < a.cpp; ++cyc) {
+    for (int l = 0; l < pl.ltop; ++l) {
+      const int m = n >> l;
+      const unsigned tiles = (unsigned)((m / kTile) * (m / kTile));
+      hipLaunchKernelGGL(k_down<R>, dim3(tiles, (unsigned)a.S), blk, ldn, st, a, pl, l,
+                         (l > 0 || cyc == 0) ? 1 : 0);
+    }
+    hipLaunchKernelGGL(k_coarse_v<R>, dim3((unsigned)a.S), blk, lcv, st, a, pl,
+                       (pl.ltop > 0 || cyc == 0) ? 1 : 0, (cyc == a.cpp - 1) ? 1 : 0);
+    for (int l = pl.ltop - 1; l >= 0; --l) {
+      const int m = n >> l;
+      const unsigned tiles = (unsigned)((m / kTile) * (m / kTile));
+      hipLaunchKernelGGL(k_up<R>, dim3(tiles, (unsigned)a.S), blk, lup, st, a, pl, l,
+                         (l == 0 && cyc == a.cpp - 1) ? 1 : 0);
+    }
+  }
+  hipLaunchKernelGGL(k_control, dim3((unsigned)((a.S + kBlock - 1) / kBlock)), blk, 0, st, a, pl);
+  return hipGetLastError();
+}
+
+template <class R>
+static hipError_t set_stream_lds(const SolveArgs& a, const StreamPlan& pl) {
+  const bool fp64 = sizeof(R) == 8;
+  const int nc = a.n >> (a.nlev - 1);
+  hipError_t e = hipFuncSetAttribute((const void*)k_down<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)tile_lds(2 * a.nu1 + 1, fp64));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_up<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)tile_lds(2 * a.nu2, fp64));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_coarse_v<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)coarse_lds(a.n >> pl.ltop, nc, fp64));
+  return e;
+}
+
+hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+  if (pl.fp64) {
+    hipError_t e = set_stream_lds<double>(a, pl);
+    return e != hipSuccess ? e : stream_iteration<double>(a, pl, st);
+  }
+  hipError_t e = set_stream_lds<float>(a, pl);
+  return e != hipSuccess ? e : stream_iteration<float>(a, pl, st);
+}
+
+hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_finish, dim3((unsigned)a.S), dim3(kBlock), 0, st, a, pl);
+  return hipGetLastError();
+}
+
+}  // namespace rmg
