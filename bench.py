@@ -56,6 +56,70 @@ def n_solves(levels):
     return sum(lv["xi"].shape[0] * (2 if lv["n_coarse"] else 1) for lv in levels)
 
 
+# ----------------------------------------------------------------- CPU baseline
+def _oracle_job(args):
+    """One oracle solve (twin mode: the same Picard / V-cycle iteration) of a workload sample."""
+    n, level, i, max_picard, cycles, Bn = args
+    import workloads as W
+    from oracle import kl as okl, picard as opicard
+    f = W.KS_FIELD
+    xi = W.xi_draws(W.MLMC_5LEVEL["workload_id"], level, [i], 1, f["n_modes"])[0, 0]
+    Ks = okl.lognormal(okl.gaussian_field(xi, Bn), f["log_mean"], f["scale"]).reshape(n, n)
+    opts = dict(W.SOLVER, max_picard=max_picard, cycles_per_picard=cycles)
+    t0 = time.perf_counter()
+    r = opicard.solve(dict(W.GARDNER_INFILTRATION), {"Ks": Ks}, n, opts, mode="mg")
+    return n, time.perf_counter() - t0, sum(r["picard"]), r["status"]
+
+
+def cpu_baseline(max_picard, cycles, gpu_its_per_solve):
+    """Time the CPU oracle on a bounded sample of the workload, one solve per worker process.
+
+    Sample: 8 solves on 16^2, 8 on 32^2, 4 on 64^2 (the first draws of the corresponding
+    levels).  The full workload's oracle time is estimated per grid as (solves on that
+    grid) x (mean measured seconds per solve); 128^2 and 256^2 are not run (one solve
+    takes tens of seconds to minutes) and are estimated from the 64^2 time per
+    cell-iteration times the cell-iterations the GPU run performed on those grids.
+    Workers run in parallel, so the estimate is divided by the worker count.
+    """
+    import multiprocessing as mp
+    import workloads as W
+    from oracle import kl as okl
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    f = W.KS_FIELD
+    _, B = okl.basis(f["sigma2"], f["corr_len"], f["n_modes"], [16, 32, 64], ref_n=64)
+    jobs = [(16, 0, i, max_picard, cycles, B[16]) for i in range(8)]
+    jobs += [(32, 1, i, max_picard, cycles, B[32]) for i in range(8)]
+    jobs += [(64, 2, i, max_picard, cycles, B[64]) for i in range(4)]
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(min(cores, len(jobs))) as pool:
+        res = pool.map(_oracle_job, jobs)
+    wall = time.perf_counter() - t0
+    if env_threads is None:
+        os.environ.pop("OMP_NUM_THREADS", None)
+    else:
+        os.environ["OMP_NUM_THREADS"] = env_threads
+    per = {}
+    for n, t, its, st in res:
+        per.setdefault(n, []).append((t, its))
+    counts = {16: 5120, 32: 1280, 64: 320, 128: 80, 256: 16}
+    est = 0.0
+    for n, c in counts.items():
+        if n in per:
+            est += c * sum(t for t, _ in per[n]) / len(per[n])
+    sec_per_cell_it = sum(t for t, _ in per[64]) / (sum(i for _, i in per[64]) * 64 * 64)
+    for n in (128, 256):
+        est += counts[n] * gpu_its_per_solve.get(n, 0.0) * n * n * sec_per_cell_it
+    est_wall = est / cores
+    total = sum(counts.values())
+    return {"value": total / est_wall, "unit": "sample solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(jobs)} oracle solves (8x16^2, 8x32^2, 4x64^2, twin mode) in {wall:.1f}s wall on "
+                      f"{min(cores, len(jobs))} processes; full-workload time estimated per grid from the "
+                      "measured mean time per solve, 128^2 and 256^2 from the 64^2 time per cell-iteration "
+                      "and the GPU run's iteration counts on those grids, divided by the worker count"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +127,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--max-picard", type=int, default=500)
+    ap.add_argument("--cycles", type=int, default=1, help="V(2,2) cycles per Picard iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -77,6 +142,7 @@ def main():
     dev = torch.device("cuda:0")
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
     levels, opts, marg = build_levels(torch, rmg, W, precision, dev, args.max_picard)
+    opts.cycles_per_picard = args.cycles
     ctx = rmg.default_context(0)
     total = n_solves(levels)
     sums = None
@@ -85,19 +151,40 @@ def main():
         sums, _, rc = ctx.mlmc_level_estimate(levels, marg, opts)
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.time() - t0:.3f}s rc={rc}")
+    from paper_1903_08741_amd import _abi
+    ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        sums, _, rc = ctx.mlmc_level_estimate(levels, marg, opts)
+        sums, q, rc = ctx.mlmc_level_estimate(levels, marg, opts, return_qoi=True)
         log(f"step {i} done rc={rc}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1000.0 * dt / args.steps
+    kt = ctx.kernel_timing()
+    ctx.set_kernel_timing(_abi.TIME_NONE)
+    converged = sum(s["n"] * (2 if lv["n_coarse"] else 1) for s, lv in zip(sums, levels))
+    its_per_solve = {}
+    for s, lv in zip(sums, levels):
+        its_per_solve[lv["n_fine"]] = s["picard_its"] / (s["n"] + s["n_failed"]) / (2 if lv["n_coarse"] else 1)
+    for l, s in enumerate(sums):
+        log(f"level {l}: pairs {s['n']} failed {s['n_failed']} picard_its {s['picard_its']}")
     failed = sum(s["n_failed"] for s in sums)
     picard = sum(s["picard_its"] for s in sums)
+    gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_down (nu1 fused red-black sweeps + residual + restriction, level-streaming path)",
+            "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
+            "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
+    cpu = None
+    if not args.no_cpu_baseline:
+        t1 = time.time()
+        cpu = cpu_baseline(args.max_picard, args.cycles, its_per_solve)
+        log(f"cpu baseline {time.time() - t1:.1f}s")
     out = {
         "metric": METRIC,
-        "value": total / (ms / 1000.0),
+        "value": converged / (ms / 1000.0),
         "unit": "sample solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -110,10 +197,12 @@ def main():
         "data": "synthetic (seeded KL lognormal Ks fields)",
         "config": {"workload": "mlmc 5 levels 16^2..256^2, 4096/1024/256/64/16 samples, Gardner, "
                                "10 steps dt=0.01, V(2,2) per Picard, eps 1e-8",
-                   "solves_per_step": total, "cells_per_step": 6291456, "failed_pairs": failed,
-                   "picard_iterations_per_step": picard, "precision": args.precision},
-        "roofline": None,
-        "cpu_baseline": None,
+                   "solves_per_step": total, "converged_solves_per_step": converged,
+                   "cells_per_step": 6291456, "failed_pairs": failed,
+                   "picard_iterations_per_step": picard, "precision": args.precision,
+                   "cycles_per_picard": args.cycles, "max_picard": args.max_picard},
+        "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -138,6 +138,26 @@ typedef struct {
  * unknown; lets bindings check their struct layouts against this build. */
 int64_t rmg_struct_size(const char* name);
 
+/* Kernel timing (diagnostics; used by the benchmark to price the smoother
+ * against HBM bandwidth).  RMG_TIME_SMOOTHER_DOWN brackets every launch of the
+ * level-streaming down-leg kernel (nu1 fused red-black sweeps + residual +
+ * restriction, Section 4.2) with HIP events on the stream it runs on, and counts
+ * the fine cells those launches processed.  Algorithmic bytes per processed cell
+ * (each array touched once): read f, the two face coefficients and C/dt, write
+ * the iterate and a quarter of a coarse right-hand side (5.25 elements), plus
+ * one element when the initial iterate is loaded rather than zero. */
+typedef enum { RMG_TIME_NONE = 0, RMG_TIME_SMOOTHER_DOWN = 1 } rmg_timed_kernel;
+typedef struct {
+  int64_t launches;     /* timed launches */
+  int64_t cells;        /* fine cells processed by them */
+  double total_ms;      /* summed event-measured launch durations */
+  double algo_bytes;    /* algorithmic bytes of those launches */
+} rmg_kernel_timing;
+/* Select the timed kernel (RMG_TIME_NONE disables timing) and reset the totals. */
+int rmg_set_kernel_timing(rmg_ctx* ctx, int which);
+/* Totals since the last rmg_set_kernel_timing (synchronises the device). */
+int rmg_get_kernel_timing(rmg_ctx* ctx, rmg_kernel_timing* out);
+
 /* Create a context on HIP device `hip_device`; *out receives it. */
 int rmg_ctx_create(rmg_ctx** out, int hip_device);
 /* Release the context and its workspace (waits for its device to be idle). */

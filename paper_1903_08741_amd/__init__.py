@@ -123,6 +123,16 @@ class Context:
             return rc
         raise RmgError(rc, self._lib.rmg_last_error(self._h).decode())
 
+    def set_kernel_timing(self, which: int):
+        """Time every launch of the selected kernel class (``_abi.TIME_*``) and reset the totals."""
+        self._raise(self._lib.rmg_set_kernel_timing(self._h, int(which)))
+
+    def kernel_timing(self) -> dict:
+        """Totals since set_kernel_timing: launches, cells, total_ms, algo_bytes."""
+        t = _abi.KernelTiming()
+        self._raise(self._lib.rmg_get_kernel_timing(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k in ("launches", "cells", "total_ms", "algo_bytes")}
+
     # -- entry points ----------------------------------------------------------
     def sample_fields(self, n, basis, xi, marginals, out=None, stream=None):
         """KL fields [S][F][n*n] from basis [M][n*n] and standard normals xi [S][F][M] (FP64)."""

@@ -20,7 +20,8 @@ CYCLE_V, CYCLE_W = 1, 2
 FLAG_FORCE_STREAMING = 1
 
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
-            "sample_fields", "picard_mg_solve", "mlmc_level_estimate")
+            "sample_fields", "picard_mg_solve", "mlmc_level_estimate", "rmg_set_kernel_timing",
+            "rmg_get_kernel_timing")
 
 
 class Marginal(C.Structure):
@@ -61,7 +62,14 @@ class Level(C.Structure):
                 ("d_basis_coarse", C.c_void_p), ("d_xi", C.c_void_p)]
 
 
-STRUCTS = {"rmg_problem": Problem, "rmg_solver_opts": SolverOpts, "rmg_sample_stats": SampleStats,
+class KernelTiming(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("cells", C.c_int64), ("total_ms", C.c_double),
+                ("algo_bytes", C.c_double)]
+
+
+TIME_NONE, TIME_SMOOTHER_DOWN = 0, 1
+
+STRUCTS = {"rmg_kernel_timing": KernelTiming, "rmg_problem": Problem, "rmg_solver_opts": SolverOpts, "rmg_sample_stats": SampleStats,
            "rmg_level_sums": LevelSums, "rmg_level": Level, "rmg_marginal": Marginal}
 
 _lib = None
@@ -93,6 +101,10 @@ def lib():
     L.mlmc_level_estimate.argtypes = [vp, i32, C.POINTER(Level), i32, i32, C.POINTER(Marginal),
                                       C.POINTER(SolverOpts), C.POINTER(LevelSums), vp, vp]
     L.mlmc_level_estimate.restype = i32
+    L.rmg_set_kernel_timing.argtypes = [vp, i32]
+    L.rmg_set_kernel_timing.restype = i32
+    L.rmg_get_kernel_timing.argtypes = [vp, C.POINTER(KernelTiming)]
+    L.rmg_get_kernel_timing.restype = i32
     for name, cls in STRUCTS.items():
         got = L.rmg_struct_size(name.encode())
         if got != C.sizeof(cls):

@@ -18,6 +18,8 @@
 
 using namespace rmg;
 
+constexpr int kTimerPairs = 4096;
+
 struct rmg_ctx {
   int device = 0;
   void* ws = nullptr;
@@ -25,6 +27,11 @@ struct rmg_ctx {
   int32_t* h_count = nullptr;  // pinned host mirror of the active-sample counters
   hipStream_t side[8] = {};
   hipEvent_t ev[8] = {};
+  // one timer per concurrently running class (each on its own stream)
+  KernelTimer timers[8] = {};
+  int timer_es[8] = {};
+  unsigned long long* d_tcells = nullptr;  // 8 x 2 counters
+  int timing = 0;
   std::string err;
 };
 
@@ -173,6 +180,16 @@ void class_plan(ClassJob& j, const rmg_solver_opts* o) {
 // streaming classes advance k Picard iterations per launch batch and poll the
 // number of still-active samples (one 4-byte read-back per batch and class).
 int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs) {
+  int ti = 0;
+  for (auto& j : jobs) {
+    j.pl.timer = nullptr;
+    j.pl.tcells = nullptr;
+    if (ctx->timing && !j.whole && ti < 8) {
+      j.pl.timer = &ctx->timers[ti];
+      ctx->timer_es[ti] = j.fp64 ? 8 : 4;
+      ++ti;
+    }
+  }
   for (auto& j : jobs) {
     if (j.whole) {
       HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
@@ -202,6 +219,16 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs) {
     for (auto& j : jobs) {
       if (j.done) continue;
       HIP_TRY(ctx, hipStreamSynchronize(j.stream));
+      if (j.pl.timer) {
+        KernelTimer* t = j.pl.timer;
+        for (int q = 0; q < t->used; ++q) {
+          float ms = 0.f;
+          HIP_TRY(ctx, hipEventElapsedTime(&ms, t->ev[2 * q], t->ev[2 * q + 1]));
+          t->total_ms += ms;
+          ++t->launches;
+        }
+        t->used = 0;
+      }
       if (*j.h_count == 0) {
         HIP_TRY(ctx, launch_stream_finish(j.a, j.pl, j.stream));
         j.done = true;
@@ -226,6 +253,7 @@ int64_t rmg_struct_size(const char* name) {
   if (s == "rmg_level_sums") return sizeof(rmg_level_sums);
   if (s == "rmg_level") return sizeof(rmg_level);
   if (s == "rmg_marginal") return sizeof(rmg_marginal);
+  if (s == "rmg_kernel_timing") return sizeof(rmg_kernel_timing);
   return -1;
 }
 
@@ -254,7 +282,70 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device) {
       return RMG_EHIP;
     }
   }
+  if (hipMalloc((void**)&c->d_tcells, 16 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_tcells, 0, 16 * sizeof(unsigned long long)) != hipSuccess) {
+    rmg_ctx_destroy(c);
+    return RMG_EHIP;
+  }
+  for (int t = 0; t < 8; ++t) c->timers[t].d_cells = c->d_tcells + 2 * t;
   *out = c;
+  return RMG_OK;
+}
+
+static void free_timer_events(rmg_ctx* c) {
+  for (auto& t : c->timers) {
+    if (!t.ev) continue;
+    for (int q = 0; q < 2 * t.cap; ++q)
+      if (t.ev[q]) (void)hipEventDestroy(t.ev[q]);
+    delete[] t.ev;
+    t.ev = nullptr;
+    t.cap = 0;
+  }
+}
+
+int rmg_set_kernel_timing(rmg_ctx* c, int which) {
+  if (!c) return RMG_EINVAL;
+  c->err.clear();
+  if (which != RMG_TIME_NONE && which != RMG_TIME_SMOOTHER_DOWN)
+    return fail(c, RMG_EINVAL, "unknown timed kernel %d", which);
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  if (which != RMG_TIME_NONE) {
+    for (auto& t : c->timers) {
+      if (t.ev) continue;
+      t.ev = new (std::nothrow) hipEvent_t[2 * kTimerPairs]();
+      if (!t.ev) return fail(c, RMG_ENOMEM, "timer event pool");
+      t.cap = kTimerPairs;
+      for (int q = 0; q < 2 * kTimerPairs; ++q) HIP_TRY(c, hipEventCreate(&t.ev[q]));
+    }
+  }
+  for (auto& t : c->timers) {
+    t.which = which;
+    t.used = 0;
+    t.launches = 0;
+    t.total_ms = 0.0;
+  }
+  HIP_TRY(c, hipMemset(c->d_tcells, 0, 16 * sizeof(unsigned long long)));
+  c->timing = which;
+  return RMG_OK;
+}
+
+int rmg_get_kernel_timing(rmg_ctx* c, rmg_kernel_timing* out) {
+  if (!c || !out) return RMG_EINVAL;
+  c->err.clear();
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  unsigned long long cells[16];
+  HIP_TRY(c, hipMemcpy(cells, c->d_tcells, sizeof cells, hipMemcpyDeviceToHost));
+  rmg_kernel_timing r = {0, 0, 0.0, 0.0};
+  for (int t = 0; t < 8; ++t) {
+    r.launches += c->timers[t].launches;
+    r.total_ms += c->timers[t].total_ms;
+    r.cells += (int64_t)(cells[2 * t] + cells[2 * t + 1]);
+    const double es = c->timer_es[t];
+    r.algo_bytes += es * (5.25 * (double)cells[2 * t] + 6.25 * (double)cells[2 * t + 1]);
+  }
+  *out = r;
   return RMG_OK;
 }
 
@@ -262,6 +353,8 @@ void rmg_ctx_destroy(rmg_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  free_timer_events(c);
+  if (c->d_tcells) (void)hipFree(c->d_tcells);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& s : c->side)

@@ -53,6 +53,18 @@ struct SolveArgs {
 size_t whole_sample_lds_bytes(int n, int nc, bool fp64);
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st);
 
+// Optional timing of the down-leg smoother launches (fused nu1 sweeps, residual and
+// restriction): HIP events around each launch on its own stream, and device counters
+// of the cells the timed launches processed ([0]: zero initial iterate, [1]: loaded).
+struct KernelTimer {
+  int which;      // 0: off, 1: down-leg smoother
+  hipEvent_t* ev; // 2 * cap events
+  int cap, used;  // event pairs recorded since the last harvest
+  unsigned long long* d_cells;
+  int64_t launches;
+  double total_ms;
+};
+
 // Level-streaming path.
 struct StreamPlan {
   int n, nlev, ltop;  // ltop: first level handled by the coarse LDS kernel
@@ -61,6 +73,8 @@ struct StreamPlan {
   SampleState* state;
   unsigned long long* dpmax;
   int32_t* active_count;
+  KernelTimer* timer;               // host object, never dereferenced on the device
+  unsigned long long* tcells;       // device counters of a timed launch, else null
 };
 hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);

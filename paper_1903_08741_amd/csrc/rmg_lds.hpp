@@ -136,14 +136,18 @@ __device__ void lds_coarsen(const LdsLevel<R>& F, const LdsLevel<R>& C) {
 
 // Exact solve on the coarsest level in FP64: Gauss-Jordan elimination without
 // pivoting on the symmetric positive definite matrix, one barrier per pivot.
-// `A` is LDS scratch of N*(N+1) doubles, N = m*m <= 64.
+// Step k replaces every row i != k by row_i - (a_ik / a_kk) row_k on the
+// columns j > k (column k is then logically zero and never read again); the
+// reciprocal of the next pivot, final once step k is done, is formed by the
+// thread that writes it.  `A` is LDS scratch of N*(N+1) doubles and `ipiv` of N
+// doubles, N = m*m <= 16.
 template <class R>
-__device__ void lds_coarsest_solve(const LdsLevel<R>& L, double* A) {
-  const int m = L.m, N = m * m, W = N + 1;
+__device__ void lds_coarsest_solve(const LdsLevel<R>& L, double* A, double* ipiv) {
+  const int m = L.m, N = m * m, W = N + 1, lgN = 2 * L.lg;
   for (int e = threadIdx.x; e < N * W; e += blockDim.x) A[e] = 0.0;
   __syncthreads();
   for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    const int j = c / m, i = c - j * m;
+    const int j = c >> L.lg, i = c - (j << L.lg);
     const double aw = (double)L.cw[c], ae = (double)L.cw[c + 1];
     const double as = (double)L.cs[c], an = (double)L.cs[c + m];
     const St5<double> s = st5<double>((double)L.cdt[c], aw, ae, as, an, 0.0, 0.0, 0.0, 0.0);
@@ -154,33 +158,41 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L, double* A) {
     if (j > 0) row[c - m] = -as;
     if (j < m - 1) row[c + m] = -an;
     row[N] = (double)L.f[c];
+    if (c == 0) ipiv[0] = 1.0 / s.d;
   }
   __syncthreads();
   for (int k = 0; k < N; ++k) {
-    // rows i != k lose their column-k entry; only columns > k change, so the
-    // entries read in this step (column k and row k) are not written in it
-    const int cols = N - k;  // columns k+1 .. N
-    for (int e = threadIdx.x; e < (N - 1) * cols; e += blockDim.x) {
-      int i = e / cols;
-      const int jj = k + 1 + (e - i * cols);
-      if (i >= k) ++i;
-      A[i * W + jj] -= (A[i * W + k] / A[k * W + k]) * A[k * W + jj];
+    const double pk = ipiv[k];
+    for (int e = threadIdx.x; e < N * N + N; e += blockDim.x) {
+      int i, j;
+      if (e < N * N) {
+        i = e >> lgN;
+        j = e & (N - 1);
+      } else {
+        i = e - N * N;
+        j = N;
+      }
+      if (i == k || j <= k) continue;
+      const double v = A[i * W + j] - (A[i * W + k] * pk) * A[k * W + j];
+      A[i * W + j] = v;
+      if (i == k + 1 && j == k + 1) ipiv[k + 1] = 1.0 / v;
     }
     __syncthreads();
   }
-  for (int c = threadIdx.x; c < N; c += blockDim.x) L.u[c] = (R)(A[c * W + N] / A[c * W + c]);
+  for (int c = threadIdx.x; c < N; c += blockDim.x) L.u[c] = (R)(A[c * W + N] * ipiv[c]);
   __syncthreads();
 }
 
 // One V(nu1, nu2) cycle from level `top` of the LDS hierarchy (levels top .. nlev-1).
 template <class R>
-__device__ void lds_vcycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, double* A) {
+__device__ void lds_vcycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, double* A,
+                           double* ipiv) {
   for (int l = top; l < nlev - 1; ++l) {
     lds_sweeps(lev[l], nu1);
     lds_residual_restrict(lev[l], lev[l + 1]);
     __syncthreads();
   }
-  lds_coarsest_solve(lev[nlev - 1], A);
+  lds_coarsest_solve(lev[nlev - 1], A, ipiv);
   for (int l = nlev - 2; l >= top; --l) {
     lds_prolong_add(lev[l], lev[l + 1]);
     __syncthreads();

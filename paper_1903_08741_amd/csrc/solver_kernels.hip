@@ -23,22 +23,38 @@ __device__ __forceinline__ const rmg_problem& class_problem(const ClassProblems&
   return s < cp.seg_split ? cp.prob[0] : cp.prob[1];
 }
 
-// Mean effective saturation (theta - theta_r)/(theta_s - theta_r) over the cells,
-// summed by each thread over cells t, t + blockDim, ... and then in a fixed tree.
+// Mean effective saturation (theta - theta_r)/(theta_s - theta_r) over the cells.
+// The summation order is fixed independently of the block size (>= kQoiLanes):
+// lane t < kQoiLanes sums cells t, t + kQoiLanes, ..., then a fixed binary tree.
+constexpr int kQoiLanes = 256;
 __device__ double mean_saturation(const rmg_problem& P, const double* fields, int F, int64_t N,
                                   int64_t s, const double* p, double* red) {
   double acc = 0.0;
-  for (int64_t c = threadIdx.x; c < N; c += blockDim.x) {
-    const CellFields cf = load_fields(fields, F, N, s, c);
-    const Closure cl = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg);
-    acc += (cl.theta - P.theta_r) / (P.theta_s - P.theta_r);
+  if (threadIdx.x < kQoiLanes) {
+    for (int64_t c = threadIdx.x; c < N; c += kQoiLanes) {
+      const CellFields cf = load_fields(fields, F, N, s, c);
+      const Closure cl = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg);
+      acc += (cl.theta - P.theta_r) / (P.theta_s - P.theta_r);
+    }
   }
-  return block_sum(acc, red) / (double)N;
+  __syncthreads();
+  if (threadIdx.x < kQoiLanes) red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kQoiLanes >> 1; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r / (double)N;
 }
 
 // ============================================================ whole sample
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_whole_sample(SolveArgs a) {
+// LDS doubles ahead of the level arrays: coarsest matrix N(N+1), pivots, reduction lanes.
+__host__ __device__ constexpr int whole_doubles(int NC) { return NC * (NC + 1) + 16 + kQoiLanes; }
+
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.x;
   const rmg_problem P = class_problem(a.cp, s);
@@ -48,8 +64,9 @@ __global__ __launch_bounds__(kBlock) void k_whole_sample(SolveArgs a) {
 
   double* Kc = (double*)smem;
   double* A = Kc + N;
-  double* red = A + NC * (NC + 1);
-  R* rbase = (R*)(red + kBlock);
+  double* ipiv = A + NC * (NC + 1);
+  double* red = ipiv + 16;
+  R* rbase = (R*)(red + kQoiLanes);
   __shared__ LdsLevel<R> lev[kMaxLevels];
   R* rend = lds_carve(rbase, lev, n, a.nlev);
   for (R* q = rbase + threadIdx.x; q < rend; q += blockDim.x) *q = (R)0;
@@ -99,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_whole_sample(SolveArgs a) {
       lds_coarsen(lev[l], lev[l + 1]);
       __syncthreads();
     }
-    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_vcycle(lev, 0, a.nlev, a.nu1, a.nu2, A);
+    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_vcycle(lev, 0, a.nlev, a.nu1, a.nu2, A, ipiv);
     // Picard update p <- p + dp and ||dp||_inf
     double mx = 0.0, bad = 0.0;
     for (int c = threadIdx.x; c < N; c += blockDim.x) {
@@ -158,27 +175,30 @@ size_t whole_sample_lds_bytes(int n, int nc, bool fp64) {
   size_t relems = 0;
   for (int l = 0, m = n; l < nlev; ++l, m >>= 1) relems += lds_level_elems(m);
   const size_t NC = (size_t)nc * nc;
-  size_t bytes = 8 * ((size_t)n * n + NC * (NC + 1) + kBlock) + relems * (fp64 ? 8 : 4);
+  size_t bytes = 8 * ((size_t)n * n + whole_doubles((int)NC)) + relems * (fp64 ? 8 : 4);
   return bytes <= 160 * 1024 ? bytes : 0;
+}
+
+// Threads per workgroup of the whole-sample kernel: enough waves per CU to hide
+// LDS and global latency when the LDS footprint admits a single workgroup.
+int whole_sample_threads(int n) { return n >= 64 ? 1024 : 256; }
+
+template <class R, int NT>
+static hipError_t launch_ws(const SolveArgs& a, size_t lds, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_whole_sample<R, NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_whole_sample<R, NT>), dim3((unsigned)a.S), dim3(NT), lds, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
   const int nc = a.n >> (a.nlev - 1);
   const size_t lds = whole_sample_lds_bytes(a.n, nc, fp64);
   if (lds == 0) return hipErrorInvalidValue;
-  hipError_t e;
-  if (fp64) {
-    e = hipFuncSetAttribute((const void*)k_whole_sample<double>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_whole_sample<double>, dim3((unsigned)a.S), dim3(kBlock), lds, st, a);
-  } else {
-    e = hipFuncSetAttribute((const void*)k_whole_sample<float>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_whole_sample<float>, dim3((unsigned)a.S), dim3(kBlock), lds, st, a);
-  }
-  return hipGetLastError();
+  const bool big = whole_sample_threads(a.n) == 1024;
+  if (fp64) return big ? launch_ws<double, 1024>(a, lds, st) : launch_ws<double, 256>(a, lds, st);
+  return big ? launch_ws<float, 1024>(a, lds, st) : launch_ws<float, 256>(a, lds, st);
 }
 
 // ============================================================ level streaming
@@ -406,6 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.y;
   if (!pl.state[s].active) return;
+  if (pl.tcells && threadIdx.x == 0) atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)(kTile * kTile));
   const int m = a.n >> l, mc = m >> 1;
   const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
   const int H = 2 * a.nu1 + 1, TW = kTile + 2 * H;
@@ -500,7 +521,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
   const int mc = a.n >> (a.nlev - 1), NC = mc * mc;
   const int64_t M2 = (int64_t)m * m;
   double* A = (double*)smem;
-  double* red = A + NC * (NC + 1);
+  double* ipiv = A + NC * (NC + 1);
+  double* red = ipiv + 16;
   R* rbase = (R*)(red + kBlock / 64);
   __shared__ LdsLevel<R> lev[kMaxLevels];
   R* rend = lds_carve(rbase, lev, m, nlev);
@@ -526,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
     lds_coarsen(lev[l], lev[l + 1]);
     __syncthreads();
   }
-  lds_vcycle(lev, 0, nlev, a.nu1, a.nu2, A);
+  lds_vcycle(lev, 0, nlev, a.nu1, a.nu2, A, ipiv);
   if (lt > 0 || !final_) {
     for (int c = threadIdx.x; c < M2; c += blockDim.x) U[c] = T.u[c];
     return;
@@ -623,7 +645,7 @@ static size_t coarse_lds(int m, int nc, bool fp64) {
   size_t relems = 0;
   for (int mm = m; mm >= nc; mm >>= 1) relems += lds_level_elems(mm);
   const size_t NC = (size_t)nc * nc;
-  return 8 * (NC * (NC + 1) + kBlock / 64) + relems * (fp64 ? 8 : 4);
+  return 8 * (NC * (NC + 1) + 16 + kBlock / 64) + relems * (fp64 ? 8 : 4);
 }
 
 template <class R>
@@ -643,8 +665,21 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
     for (int l = 0; l < pl.ltop; ++l) {
       const int m = n >> l;
       const unsigned tiles = (unsigned)((m / kTile) * (m / kTile));
-      hipLaunchKernelGGL(k_down<R>, dim3(tiles, (unsigned)a.S), blk, ldn, st, a, pl, l,
+      KernelTimer* tm = pl.timer;
+      const bool timed = tm && tm->which == 1 && tm->used < tm->cap;
+      StreamPlan plx = pl;
+      plx.tcells = timed ? tm->d_cells : nullptr;
+      if (timed) {
+        hipError_t e = hipEventRecord(tm->ev[2 * tm->used], st);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_down<R>, dim3(tiles, (unsigned)a.S), blk, ldn, st, a, plx, l,
                          (l > 0 || cyc == 0) ? 1 : 0);
+      if (timed) {
+        hipError_t e = hipEventRecord(tm->ev[2 * tm->used + 1], st);
+        if (e != hipSuccess) return e;
+        ++tm->used;
+      }
     }
     hipLaunchKernelGGL(k_coarse_v<R>, dim3((unsigned)a.S), blk, lcv, st, a, pl,
                        (pl.ltop > 0 || cyc == 0) ? 1 : 0, (cyc == a.cpp - 1) ? 1 : 0);
