@@ -95,7 +95,14 @@ typedef struct {
   int32_t cycles_per_picard;  /* >= 1: fixed number of cycles per Picard step */
   int32_t max_picard;         /* Picard iterations allowed per time step, >= 1 */
   int32_t coarsest_n;         /* coarsest grid size (2, 4 or 8), solved exactly in FP64 */
-  int32_t flags;              /* bit 0: force the level-streaming path (no whole-sample-in-LDS kernel) */
+  int32_t flags;              /* bit 0: force the level-streaming path (no whole-sample-in-LDS kernel);
+                                 bit 1: launch the streaming Picard iterations eagerly instead of
+                                 replaying a captured HIP graph (results are identical);
+                                 bit 2: whole-sample kernel keeps the FP64 state in global memory
+                                 even where it would fit in LDS (results are identical);
+                                 bit 3: no autotuning of the streaming tile shapes (32 x 32
+                                 tiles on every level; results are identical);
+                                 bit 4: 16 x 16 streaming tiles on every level, no autotuning */
   double eps_mg;              /* reserved for a residual-controlled cycle count */
   double eps_picard;          /* stop when ||dp||_inf < eps_picard (strict) */
 } rmg_solver_opts;

@@ -9,7 +9,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librmg.so")
+LIB_PATH = os.environ.get("RMG_LIBRARY") or os.path.join(HERE, "librmg.so")
 
 RMG_OK, RMG_EINVAL, RMG_ENOMEM, RMG_EHIP, RMG_ENOTCONV = 0, -1, -2, -3, -4
 SAMPLE_OK, SAMPLE_MAXITER, SAMPLE_NONFINITE = 0, 1, 2
@@ -18,6 +18,10 @@ QOI_MEAN_SATURATION, QOI_BOTTOM_OUTFLUX = 0, 1
 FP64, MIXED = 0, 1
 CYCLE_V, CYCLE_W = 1, 2
 FLAG_FORCE_STREAMING = 1
+FLAG_EAGER = 2
+FLAG_STATE_GLOBAL = 4
+FLAG_NO_AUTOTUNE = 8
+FLAG_TILES_16 = 16
 
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
             "sample_fields", "picard_mg_solve", "mlmc_level_estimate", "rmg_set_kernel_timing",

@@ -13,6 +13,7 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -27,12 +28,15 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build(verbose: bool = False, arch: str = "gfx950") -> str:
+def build(verbose: bool = False, arch: str = "gfx950", defines=(), out: str = LIB) -> str:
+    """Compile every source and link ``out``; ``defines`` are extra -D tuning macros."""
     objs = []
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={arch}", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
+    flags += [f"-D{d}" for d in defines]
+    objdir = tempfile.mkdtemp(prefix="rmg_build_")
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
@@ -40,15 +44,16 @@ def build(verbose: bool = False, arch: str = "gfx950") -> str:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={arch}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return LIB
+    os.rmdir(objdir)
+    return out
 
 
 if __name__ == "__main__":

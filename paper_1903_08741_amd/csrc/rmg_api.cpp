@@ -32,6 +32,9 @@ struct rmg_ctx {
   int timer_es[8] = {};
   unsigned long long* d_tcells = nullptr;  // 8 x 2 counters
   int timing = 0;
+  // autotuner: tile edges (level 0, coarser streaming levels) per class signature
+  std::map<std::string, std::pair<int, int>> tune;
+  hipEvent_t tev[2] = {};
   std::string err;
 };
 
@@ -132,6 +135,7 @@ struct ClassJob {
   int32_t* d_count = nullptr;
   int32_t* h_count = nullptr;
   bool done = false;
+  bool autotune = true;
 };
 
 // Workspace bytes a class needs beyond its caller-visible outputs.
@@ -169,23 +173,93 @@ void class_carve(ClassJob& j, Arena& ar) {
 void class_plan(ClassJob& j, const rmg_solver_opts* o) {
   j.fp64 = o->precision == RMG_FP64;
   const int n = j.a.n;
-  j.whole = !(o->flags & 1) && whole_sample_lds_bytes(n, o->coarsest_n, j.fp64) > 0;
+  j.whole = !(o->flags & 1) && whole_sample_lds_bytes(n, o->coarsest_n, j.fp64, j.a.F, nullptr) > 0;
+  j.a.state_global = (o->flags & 4) != 0;
+  j.autotune = (o->flags & (8 | 16)) == 0;
   j.pl.n = n;
   j.pl.nlev = j.a.nlev;
   j.pl.fp64 = j.fp64;
   j.pl.ltop = std::max(0, ilog2i(n) - ilog2i(kCoarseTop));
+  for (int l = 0; l < kMaxLevels; ++l) j.pl.ts[l] = (o->flags & 16) ? 16 : kTile;
+}
+
+std::string tune_key(const ClassJob& j) {
+  char b[160];
+  snprintf(b, sizeof b, "n=%d S=%lld fp64=%d nu=%d,%d cpp=%d F=%d", j.a.n, (long long)j.a.S, (int)j.fp64,
+           j.a.nu1, j.a.nu2, j.a.cpp, j.a.F);
+  return b;
+}
+
+void set_tiles(ClassJob& j, int ts0, int tsr) {
+  for (int l = 0; l < kMaxLevels; ++l) j.pl.ts[l] = l == 0 ? ts0 : tsr;
+}
+
+// Pick the tile edges of the down/up kernels of a streaming class by timing a few
+// Picard iterations of the class itself for each candidate; the state is then
+// re-initialised, so the tuning run leaves no trace in the results (every tile
+// shape computes the same values).  Choices are cached per class signature.
+int autotune_class(rmg_ctx* ctx, ClassJob& j) {
+  const std::string key = tune_key(j);
+  auto it = ctx->tune.find(key);
+  if (it != ctx->tune.end()) {
+    set_tiles(j, it->second.first, it->second.second);
+    return RMG_OK;
+  }
+  KernelTimer* saved = j.pl.timer;
+  j.pl.timer = nullptr;
+  const int cand[4][2] = {{32, 32}, {32, 16}, {16, 16}, {16, 32}};
+  float best = 1e30f;
+  int b0 = kTile, b1 = kTile;
+  for (auto& c : cand) {
+    set_tiles(j, c[0], c[1]);
+    HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
+    HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->tev[0], j.stream));
+    for (int i = 0; i < 4; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream));
+    HIP_TRY(ctx, hipEventRecord(ctx->tev[1], j.stream));
+    HIP_TRY(ctx, hipEventSynchronize(ctx->tev[1]));
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]));
+    if (ms < best) {
+      best = ms;
+      b0 = c[0];
+      b1 = c[1];
+    }
+  }
+  ctx->tune[key] = {b0, b1};
+  set_tiles(j, b0, b1);
+  j.pl.timer = saved;
+  HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
+  return RMG_OK;
+}
+
+int harvest_timer(rmg_ctx* ctx, KernelTimer* t) {
+  if (!t) return RMG_OK;
+  for (int q = 0; q < t->used; ++q) {
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, t->ev[2 * q], t->ev[2 * q + 1]));
+    t->total_ms += ms;
+    ++t->launches;
+  }
+  if (!t->in_graph) t->used = 0;
+  return RMG_OK;
 }
 
 // Run every class to completion: whole-sample classes are single launches;
-// streaming classes advance k Picard iterations per launch batch and poll the
-// number of still-active samples (one 4-byte read-back per batch and class).
-int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs) {
+// streaming classes replay a HIP graph of G captured Picard iterations and poll
+// the number of still-active samples once per replay (one 4-byte read-back).
+int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
+  // events recorded by graph nodes cannot be queried, so timed runs launch eagerly
+  // (measured: graph replay and eager launch differ by ~2-3% on these kernels)
+  if (ctx->timing) use_graphs = false;
   int ti = 0;
   for (auto& j : jobs) {
     j.pl.timer = nullptr;
     j.pl.tcells = nullptr;
     if (ctx->timing && !j.whole && ti < 8) {
       j.pl.timer = &ctx->timers[ti];
+      j.pl.timer->used = 0;
+      j.pl.timer->in_graph = false;
       ctx->timer_es[ti] = j.fp64 ? 8 : 4;
       ++ti;
     }
@@ -195,49 +269,102 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs) {
       HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
       j.done = true;
     } else {
+      HIP_TRY(ctx, prepare_stream(j.a, j.pl));
       HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
+      if (j.autotune) {
+        const int rc = autotune_class(ctx, j);
+        if (rc != RMG_OK) return rc;
+      }
     }
   }
-  const int k = 8;
+  const int G = 8;
+  std::vector<hipGraphExec_t> execs(jobs.size(), nullptr);
+  std::vector<hipGraph_t> graphs(jobs.size(), nullptr);
+  auto cleanup = [&]() {
+    for (auto& e : execs)
+      if (e) (void)hipGraphExecDestroy(e);
+    for (auto& g : graphs)
+      if (g) (void)hipGraphDestroy(g);
+  };
+  if (use_graphs) {
+    for (size_t c = 0; c < jobs.size(); ++c) {
+      ClassJob& j = jobs[c];
+      if (j.done) continue;
+      if (j.pl.timer) j.pl.timer->in_graph = true;
+      const char* what = "hipStreamBeginCapture";
+      hipError_t e = hipStreamBeginCapture(j.stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) what = "captured iteration launches";
+      for (int i = 0; i < G && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, j.pl, j.stream);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(j.stream, &g);
+      graphs[c] = g;
+      if (e == hipSuccess) {
+        e = e2;
+        what = "hipStreamEndCapture";
+      }
+      if (e == hipSuccess) {
+        e = hipGraphInstantiate(&execs[c], g, nullptr, nullptr, 0);
+        what = "hipGraphInstantiate";
+      }
+      if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, RMG_EHIP, "graph capture of the Picard iteration failed in %s: %s", what,
+                    hipGetErrorString(e));
+      }
+    }
+  }
   // every sample stops after at most n_steps * max_picard iterations
   long bound = 0;
   for (auto& j : jobs) {
     const long steps = std::max(j.a.cp.prob[0].n_steps, j.a.cp.prob[1].n_steps);
-    bound = std::max(bound, steps * (long)j.a.max_picard + 2L * k);
+    bound = std::max(bound, steps * (long)j.a.max_picard + 2L * G);
   }
   long launched = 0;
+  int rc = RMG_OK;
   for (;;) {
     bool any = false;
-    for (auto& j : jobs) {
+    for (size_t c = 0; c < jobs.size() && rc == RMG_OK; ++c) {
+      ClassJob& j = jobs[c];
       if (j.done) continue;
       any = true;
-      for (int i = 0; i < k; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream));
-      HIP_TRY(ctx, hipMemcpyAsync(j.h_count, j.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                  j.stream));
-    }
-    if (!any) break;
-    for (auto& j : jobs) {
-      if (j.done) continue;
-      HIP_TRY(ctx, hipStreamSynchronize(j.stream));
-      if (j.pl.timer) {
-        KernelTimer* t = j.pl.timer;
-        for (int q = 0; q < t->used; ++q) {
-          float ms = 0.f;
-          HIP_TRY(ctx, hipEventElapsedTime(&ms, t->ev[2 * q], t->ev[2 * q + 1]));
-          t->total_ms += ms;
-          ++t->launches;
-        }
-        t->used = 0;
+      hipError_t e = hipSuccess;
+      if (use_graphs) {
+        e = hipGraphLaunch(execs[c], j.stream);
+      } else {
+        for (int i = 0; i < G && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, j.pl, j.stream);
       }
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(j.h_count, j.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, j.stream);
+      if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "iteration launch failed: %s", hipGetErrorString(e));
+    }
+    if (!any || rc != RMG_OK) break;
+    for (size_t c = 0; c < jobs.size() && rc == RMG_OK; ++c) {
+      ClassJob& j = jobs[c];
+      if (j.done) continue;
+      hipError_t e = hipStreamSynchronize(j.stream);
+      if (e != hipSuccess) {
+        rc = fail(ctx, RMG_EHIP, "stream synchronize: %s", hipGetErrorString(e));
+        break;
+      }
+      if ((rc = harvest_timer(ctx, j.pl.timer)) != RMG_OK) break;
       if (*j.h_count == 0) {
-        HIP_TRY(ctx, launch_stream_finish(j.a, j.pl, j.stream));
+        e = launch_stream_finish(j.a, j.pl, j.stream);
+        if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "finish launch: %s", hipGetErrorString(e));
         j.done = true;
       }
     }
-    launched += k;
-    if (launched > bound) return fail(ctx, RMG_EHIP, "samples still active after %ld iterations", launched);
+    launched += G;
+    if (rc == RMG_OK && launched > bound)
+      rc = fail(ctx, RMG_EHIP, "samples still active after %ld iterations", launched);
+    if (rc != RMG_OK) break;
   }
-  return RMG_OK;
+  for (auto& j : jobs)
+    if (j.pl.timer) {
+      j.pl.timer->in_graph = false;
+      j.pl.timer->used = 0;
+    }
+  cleanup();
+  return rc;
 }
 
 }  // namespace
@@ -278,6 +405,12 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device) {
   }
   for (auto& e : c->ev) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      rmg_ctx_destroy(c);
+      return RMG_EHIP;
+    }
+  }
+  for (auto& e : c->tev) {
+    if (hipEventCreate(&e) != hipSuccess) {
       rmg_ctx_destroy(c);
       return RMG_EHIP;
     }
@@ -354,6 +487,8 @@ void rmg_ctx_destroy(rmg_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   free_timer_events(c);
+  for (auto& e : c->tev)
+    if (e) (void)hipEventDestroy(e);
   if (c->d_tcells) (void)hipFree(c->d_tcells);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -416,14 +551,21 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
   j.a.status = d_status;
   j.a.stats = d_stats;
   class_plan(j, opts);
-  j.stream = stream;
+  // the solve runs on a context stream ordered after the caller's stream (a
+  // captured graph cannot be recorded on the legacy default stream)
+  j.stream = ctx->side[0];
   j.h_count = ctx->h_count;
   if ((rc = reserve(ctx, class_ws_bytes(j)))) return rc;
   Arena ar;
   ar.base = (char*)ctx->ws;
   ar.cap = ctx->ws_cap;
   class_carve(j, ar);
-  if ((rc = run_classes(ctx, jobs))) return rc;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
+  HIP_TRY(ctx, hipStreamWaitEvent(j.stream, ctx->ev[0], 0));
+  rc = run_classes(ctx, jobs, !(opts->flags & 2));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[1], j.stream));
+  HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1], 0));
+  if (rc) return rc;
   std::vector<int32_t> st(S);
   HIP_TRY(ctx, hipMemcpyAsync(st.data(), d_status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
@@ -555,7 +697,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     jobs[c].h_count = ctx->h_count + 4 * (int)(c % 16);
   }
   for (int q = 0; q < nside; ++q) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[q], ctx->ev[0], 0));
-  if ((rc = run_classes(ctx, jobs))) return rc;
+  if ((rc = run_classes(ctx, jobs, !(opts->flags & 2)))) return rc;
   for (int q = 0; q < nside; ++q) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1 + q], ctx->side[q]));
     HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1 + q], 0));

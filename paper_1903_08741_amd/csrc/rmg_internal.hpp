@@ -41,6 +41,7 @@ struct SolveArgs {
   const double* fields;
   ClassProblems cp;
   int nu1, nu2, cpp, max_picard;
+  int state_global;  // whole-sample kernel: keep the FP64 state in global memory even if LDS fits
   double eps;
   double* p;
   double* theta_old;
@@ -50,7 +51,7 @@ struct SolveArgs {
 };
 
 // LDS bytes of the whole-sample kernel for grid n (0 if it does not fit).
-size_t whole_sample_lds_bytes(int n, int nc, bool fp64);
+size_t whole_sample_lds_bytes(int n, int nc, bool fp64, int F, bool* state_in_lds);
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st);
 
 // Optional timing of the down-leg smoother launches (fused nu1 sweeps, residual and
@@ -59,7 +60,8 @@ hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st);
 struct KernelTimer {
   int which;      // 0: off, 1: down-leg smoother
   hipEvent_t* ev; // 2 * cap events
-  int cap, used;  // event pairs recorded since the last harvest
+  int cap, used;  // event pairs recorded (since the last harvest, or into the captured graph)
+  bool in_graph;  // events belong to a graph: harvest after every replay, keep `used`
   unsigned long long* d_cells;
   int64_t launches;
   double total_ms;
@@ -68,6 +70,7 @@ struct KernelTimer {
 // Level-streaming path.
 struct StreamPlan {
   int n, nlev, ltop;  // ltop: first level handled by the coarse LDS kernel
+  int ts[kMaxLevels]; // output tile edge (16 or 32) of the down/up kernels per streaming level
   bool fp64;
   LevelPtrs lv;
   SampleState* state;
@@ -77,6 +80,9 @@ struct StreamPlan {
   unsigned long long* tcells;       // device counters of a timed launch, else null
 };
 hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
+// Kernel attributes of the streaming kernels (call once before launching or capturing).
+hipError_t prepare_stream(const SolveArgs& a, const StreamPlan& pl);
+// One Picard iteration of every active sample: stream operations only, capturable.
 hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 size_t level_bytes(int m, int64_t S, bool fp64);

@@ -16,13 +16,18 @@
 
 namespace rmg {
 
+// Pointers into LDS carry address space 3 in their type, so that every access is
+// a ds_read/ds_write even when the pointer itself was stored and reloaded (a
+// generic pointer would compile to the slower flat instructions).
+#define RMG_LDS __attribute__((address_space(3)))
+
 template <class R>
 struct LdsLevel {
-  R* u;
-  R* f;
-  R* cw;
-  R* cs;
-  R* cdt;
+  RMG_LDS R* u;
+  RMG_LDS R* f;
+  RMG_LDS R* cw;
+  RMG_LDS R* cs;
+  RMG_LDS R* cdt;
   int m, lg;  // m = 1 << lg
 };
 
@@ -45,16 +50,16 @@ __device__ R* lds_carve(R* base, LdsLevel<R>* lev, int m_top, int nlev) {
     if (w) {
       lev[l].m = m;
       lev[l].lg = lg;
-      lev[l].u = p + 1 + m;
+      lev[l].u = (RMG_LDS R*)(p + 1 + m);
     }
     p += (m + 2) * m + 2;
-    if (w) lev[l].f = p;
+    if (w) lev[l].f = (RMG_LDS R*)p;
     p += m * m;
-    if (w) lev[l].cw = p;
+    if (w) lev[l].cw = (RMG_LDS R*)p;
     p += m * m + 1;
-    if (w) lev[l].cs = p;
+    if (w) lev[l].cs = (RMG_LDS R*)p;
     p += (m + 1) * m;
-    if (w) lev[l].cdt = p;
+    if (w) lev[l].cdt = (RMG_LDS R*)p;
     p += m * m;
     m >>= 1;
     --lg;
@@ -83,10 +88,52 @@ __device__ void lds_half_sweep(const LdsLevel<R>& L, int colour) {
   }
 }
 
+// Red half-sweep when the current iterate is zero: the neighbour sum vanishes, so
+// u = f / d without reading neighbours (the same operations as lds_half_sweep on a
+// zero iterate).
 template <class R>
-__device__ void lds_sweeps(const LdsLevel<R>& L, int nu) {
+__device__ void lds_half_sweep_from_zero(const LdsLevel<R>& L) {
+  const int m = L.m, hlg = L.lg - 1;
+  const int tot = (m * m) >> 1;
+  for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+    const int j = k >> hlg;
+    const int q = k - (j << hlg);
+    const int i = 2 * q + (j & 1);
+    const int c = j * m + i;
+    const St5<R> s = st5<R>(L.cdt[c], L.cw[c], L.cw[c + 1], L.cs[c], L.cs[c + m], (R)0, (R)0, (R)0, (R)0);
+    L.u[c] = gs_value<R>(L.f[c], s);
+  }
+}
+
+// Red half-sweep right after the coarse-grid correction: the black neighbours are
+// read as u + (prolongated coarse correction); the red cells' own corrected values
+// are never needed (they are overwritten), and the black cells are overwritten by
+// the following black half-sweep, so no separate prolongation pass is required.
+template <class R>
+__device__ void lds_half_sweep_prolong(const LdsLevel<R>& L, const LdsLevel<R>& C) {
+  const int m = L.m, hlg = L.lg - 1, mc = C.m;
+  const int tot = (m * m) >> 1;
+  for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+    const int j = k >> hlg;
+    const int q = k - (j << hlg);
+    const int i = 2 * q + (j & 1);
+    const int c = j * m + i;
+    const R uw = i > 0 ? L.u[c - 1] + C.u[(j >> 1) * mc + ((i - 1) >> 1)] : (R)0;
+    const R ue = i < m - 1 ? L.u[c + 1] + C.u[(j >> 1) * mc + ((i + 1) >> 1)] : (R)0;
+    const R us = j > 0 ? L.u[c - m] + C.u[((j - 1) >> 1) * mc + (i >> 1)] : (R)0;
+    const R un = j < m - 1 ? L.u[c + m] + C.u[((j + 1) >> 1) * mc + (i >> 1)] : (R)0;
+    const St5<R> s = st5<R>(L.cdt[c], L.cw[c], L.cw[c + 1], L.cs[c], L.cs[c + m], uw, ue, us, un);
+    L.u[c] = gs_value<R>(L.f[c], s);
+  }
+}
+
+template <class R>
+__device__ void lds_sweeps(const LdsLevel<R>& L, int nu, bool from_zero = false) {
   for (int s = 0; s < nu; ++s) {
-    lds_half_sweep(L, 0);
+    if (s == 0 && from_zero)
+      lds_half_sweep_from_zero(L);
+    else
+      lds_half_sweep(L, 0);
     __syncthreads();
     lds_half_sweep(L, 1);
     __syncthreads();
@@ -142,7 +189,7 @@ __device__ void lds_coarsen(const LdsLevel<R>& F, const LdsLevel<R>& C) {
 // thread that writes it.  `A` is LDS scratch of N*(N+1) doubles and `ipiv` of N
 // doubles, N = m*m <= 16.
 template <class R>
-__device__ void lds_coarsest_solve(const LdsLevel<R>& L, double* A, double* ipiv) {
+__device__ void lds_coarsest_solve(const LdsLevel<R>& L, RMG_LDS double* A, RMG_LDS double* ipiv) {
   const int m = L.m, N = m * m, W = N + 1, lgN = 2 * L.lg;
   for (int e = threadIdx.x; e < N * W; e += blockDim.x) A[e] = 0.0;
   __syncthreads();
@@ -151,7 +198,7 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L, double* A, double* ipiv
     const double aw = (double)L.cw[c], ae = (double)L.cw[c + 1];
     const double as = (double)L.cs[c], an = (double)L.cs[c + m];
     const St5<double> s = st5<double>((double)L.cdt[c], aw, ae, as, an, 0.0, 0.0, 0.0, 0.0);
-    double* row = A + c * W;
+    RMG_LDS double* row = A + c * W;
     row[c] = s.d;
     if (i > 0) row[c - 1] = -aw;
     if (i < m - 1) row[c + 1] = -ae;
@@ -184,19 +231,34 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L, double* A, double* ipiv
 }
 
 // One V(nu1, nu2) cycle from level `top` of the LDS hierarchy (levels top .. nlev-1).
+// `top_zero`: the iterate on level `top` is zero on entry (coarser levels always are).
 template <class R>
-__device__ void lds_vcycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, double* A,
-                           double* ipiv) {
+__device__ void lds_vcycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, RMG_LDS double* A,
+                           RMG_LDS double* ipiv, bool top_zero) {
+#ifndef RMG_ZERO_SWEEP
+#define RMG_ZERO_SWEEP 1
+#endif
+#ifndef RMG_FUSED_PROLONG
+#define RMG_FUSED_PROLONG 1
+#endif
   for (int l = top; l < nlev - 1; ++l) {
-    lds_sweeps(lev[l], nu1);
+    lds_sweeps(lev[l], nu1, RMG_ZERO_SWEEP && (l > top || top_zero));
     lds_residual_restrict(lev[l], lev[l + 1]);
     __syncthreads();
   }
   lds_coarsest_solve(lev[nlev - 1], A, ipiv);
   for (int l = nlev - 2; l >= top; --l) {
-    lds_prolong_add(lev[l], lev[l + 1]);
-    __syncthreads();
-    lds_sweeps(lev[l], nu2);
+    if (RMG_FUSED_PROLONG && nu2 > 0) {
+      lds_half_sweep_prolong(lev[l], lev[l + 1]);
+      __syncthreads();
+      lds_half_sweep(lev[l], 1);
+      __syncthreads();
+      lds_sweeps(lev[l], nu2 - 1);
+    } else {
+      lds_prolong_add(lev[l], lev[l + 1]);
+      __syncthreads();
+      lds_sweeps(lev[l], nu2);
+    }
   }
 }
 

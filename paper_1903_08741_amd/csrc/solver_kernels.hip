@@ -23,6 +23,28 @@ __device__ __forceinline__ const rmg_problem& class_problem(const ClassProblems&
   return s < cp.seg_split ? cp.prob[0] : cp.prob[1];
 }
 
+// Flat traversal of a w x w region of a tile without integer division: for
+// k < 2^16 and w < 2^16, floor(k / w) = umulhi(k, ceil(2^32 / w)) exactly (the
+// rounding error of the reciprocal, k (ceil(2^32/w) w - 2^32) / (w 2^32) < k / 2^32,
+// stays below 1/w).
+__device__ __forceinline__ unsigned rmg_magic(int w) {
+  return (unsigned)((0x100000000ull + (unsigned long long)w - 1ull) / (unsigned long long)w);
+}
+#define RMG_TILE_FOR(w, ri, rj)                                                                 \
+  for (int w_ = (w), once_ = 1; once_; once_ = 0)                                                 \
+    for (unsigned mg_ = rmg_magic(w_), once2_ = 1u; once2_; once2_ = 0u)                          \
+      for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < w_ * w_; k_ += (int)blockDim.x)        \
+        if ((rj = (int)__umulhi((unsigned)k_, mg_), ri = k_ - rj * w_), true)
+
+// Tile handled by this workgroup.  Workgroups are handed to the 8 XCDs round-robin
+// by linear id; when the tile count is a multiple of 8 the tiles are renumbered so
+// that each XCD receives a contiguous band of tiles and the halos its workgroups
+// share stay in that XCD's L2.
+__device__ __forceinline__ int xcd_tile() {
+  const int g = gridDim.x, b = blockIdx.x;
+  return (g & 7) ? b : (b & 7) * (g >> 3) + (b >> 3);
+}
+
 // Mean effective saturation (theta - theta_r)/(theta_s - theta_r) over the cells.
 // The summation order is fixed independently of the block size (>= kQoiLanes):
 // lane t < kQoiLanes sums cells t, t + kQoiLanes, ..., then a fixed binary tree.
@@ -53,27 +75,48 @@ __device__ double mean_saturation(const rmg_problem& P, const double* fields, in
 // LDS doubles ahead of the level arrays: coarsest matrix N(N+1), pivots, reduction lanes.
 __host__ __device__ constexpr int whole_doubles(int NC) { return NC * (NC + 1) + 16 + kQoiLanes; }
 
-template <class R, int NT>
+#ifndef RMG_WS_UNROLL
+#define RMG_WS_UNROLL 1
+#endif
+#ifndef RMG_WS_THREADS
+#define RMG_WS_THREADS 512
+#endif
+constexpr int kUnroll = RMG_WS_UNROLL;  // cells per thread whose global loads are issued together
+
+// SL: the FP64 state (pressure head, old moisture content, fields) lives in LDS
+// for the whole integration and the pressure head is written back once at the end;
+// otherwise it stays in global memory and is read kUnroll cells at a time.
+template <class R, int NT, bool SL>
 __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.x;
   const rmg_problem P = class_problem(a.cp, s);
-  const int n = a.n, lg = a.lg;
-  const int64_t N = (int64_t)n * n;
+  const int n = a.n, lg = a.lg, F = a.F;
+  const int N = n * n;
   const int mc = n >> (a.nlev - 1), NC = mc * mc;
 
-  double* Kc = (double*)smem;
-  double* A = Kc + N;
-  double* ipiv = A + NC * (NC + 1);
-  double* red = ipiv + 16;
-  R* rbase = (R*)(red + kQoiLanes);
+  RMG_LDS double* Kc = (RMG_LDS double*)smem;
+  RMG_LDS double* A = Kc + N;
+  RMG_LDS double* ipiv = A + NC * (NC + 1);
+  double* red = (double*)(ipiv + 16);
+  double* dend = red + kQoiLanes;
+  double* pS = dend;
+  double* thS = pS + (SL ? N : 0);
+  double* fS = thS + (SL ? N : 0);
+  R* rbase = (R*)(fS + (SL ? F * N : 0));
   __shared__ LdsLevel<R> lev[kMaxLevels];
   R* rend = lds_carve(rbase, lev, n, a.nlev);
   for (R* q = rbase + threadIdx.x; q < rend; q += blockDim.x) *q = (R)0;
 
-  double* p = a.p + s * N;
-  double* thold = a.theta_old + s * N;
-  for (int64_t c = threadIdx.x; c < N; c += blockDim.x) p[c] = P.h_init;
+  double* pg = a.p + s * N;
+  double* const p = SL ? pS : pg;
+  double* const thold = SL ? thS : a.theta_old + s * N;
+  const double* const fld = SL ? fS : a.fields + s * F * N;  // field f of cell c at fld[f*N + c]
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    p[c] = P.h_init;
+    if (SL)
+      for (int f = 0; f < F; ++f) fS[f * N + c] = a.fields[(s * F + f) * N + c];
+  }
   __syncthreads();
 
   int step = 0, it = 0, new_step = 1, status = RMG_SAMPLE_OK, tot_its = 0, cycles = 0;
@@ -81,49 +124,92 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   const LdsLevel<R>& L0 = lev[0];
   for (;;) {
     // conductivity at every cell (FP64)
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
-      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
-      Kc[c] = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg).K;
+    for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
+      double pv[kUnroll], k0[kUnroll], k1[kUnroll], k2[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int c = c0 + q * NT;
+        if (c < N) {
+          pv[q] = p[c];
+          k0[q] = fld[c];
+          k1[q] = F > 1 ? fld[N + c] : 0.0;
+          k2[q] = F > 2 ? fld[2 * N + c] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int c = c0 + q * NT;
+        if (c < N) Kc[c] = closure(P, pv[q], k0[q], k1[q], k2[q]).K;
+      }
     }
     __syncthreads();
     // outer residual and fine-level coefficients
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
-      const int j = c >> lg, i = c - (j << lg);
-      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
-      const Closure cl = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg);
-      double th_old;
-      if (new_step) {
-        th_old = cl.theta;
-        thold[c] = cl.theta;
-      } else {
-        th_old = thold[c];
+    for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
+      double pc[kUnroll], pw[kUnroll], pe[kUnroll], ps[kUnroll], pn[kUnroll], to[kUnroll];
+      double k0[kUnroll], k1[kUnroll], k2[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int c = c0 + q * NT;
+        if (c < N) {
+          const int j = c >> lg, i = c - (j << lg);
+          pc[q] = p[c];
+          pw[q] = i > 0 ? p[c - 1] : 0.0;
+          pe[q] = i < n - 1 ? p[c + 1] : 0.0;
+          ps[q] = j > 0 ? p[c - n] : 0.0;
+          pn[q] = j < n - 1 ? p[c + n] : 0.0;
+          to[q] = new_step ? 0.0 : thold[c];
+          k0[q] = fld[c];
+          k1[q] = F > 1 ? fld[N + c] : 0.0;
+          k2[q] = F > 2 ? fld[2 * N + c] : 0.0;
+        }
       }
-      const double pw = i > 0 ? p[c - 1] : 0.0, pe = i < n - 1 ? p[c + 1] : 0.0;
-      const double ps = j > 0 ? p[c - n] : 0.0, pn = j < n - 1 ? p[c + n] : 0.0;
-      const double Kw = i > 0 ? Kc[c - 1] : 0.0, Ke = i < n - 1 ? Kc[c + 1] : 0.0;
-      const double Ks_ = j > 0 ? Kc[c - n] : 0.0, Kn = j < n - 1 ? Kc[c + n] : 0.0;
-      const FineCell fc = fine_cell(i, j, n, p[c], pw, pe, ps, pn, Kc[c], Kw, Ke, Ks_, Kn, cl.theta,
-                                    th_old, cl.C, P.dt, P.h_bottom, P.h_top);
-      L0.f[c] = (R)fc.f;
-      L0.cw[c] = (R)fc.cw;
-      L0.cs[c] = (R)fc.cs;
-      L0.cdt[c] = (R)fc.cdt;
-      if (j == n - 1) L0.cs[c + n] = (R)fc.ctop;
-      L0.u[c] = (R)0;
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int c = c0 + q * NT;
+        if (c >= N) continue;
+        const int j = c >> lg, i = c - (j << lg);
+        const Closure cl = closure(P, pc[q], k0[q], k1[q], k2[q]);
+        double th_old = to[q];
+        if (new_step) {
+          th_old = cl.theta;
+          thold[c] = cl.theta;
+        }
+        const double Kw = i > 0 ? Kc[c - 1] : 0.0, Ke = i < n - 1 ? Kc[c + 1] : 0.0;
+        const double Ks_ = j > 0 ? Kc[c - n] : 0.0, Kn = j < n - 1 ? Kc[c + n] : 0.0;
+        const FineCell fc = fine_cell(i, j, n, pc[q], pw[q], pe[q], ps[q], pn[q], Kc[c], Kw, Ke, Ks_, Kn,
+                                      cl.theta, th_old, cl.C, P.dt, P.h_bottom, P.h_top);
+        L0.f[c] = (R)fc.f;
+        L0.cw[c] = (R)fc.cw;
+        L0.cs[c] = (R)fc.cs;
+        L0.cdt[c] = (R)fc.cdt;
+        if (j == n - 1) L0.cs[c + n] = (R)fc.ctop;
+        L0.u[c] = (R)0;
+      }
     }
     __syncthreads();
     for (int l = 0; l + 1 < a.nlev; ++l) {
       lds_coarsen(lev[l], lev[l + 1]);
       __syncthreads();
     }
-    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_vcycle(lev, 0, a.nlev, a.nu1, a.nu2, A, ipiv);
+    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_vcycle(lev, 0, a.nlev, a.nu1, a.nu2, A, ipiv, cyc == 0);
     // Picard update p <- p + dp and ||dp||_inf
     double mx = 0.0, bad = 0.0;
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
-      const double d = (double)L0.u[c];
-      p[c] += d;
-      mx = fmax(mx, fabs(d));
-      if (!isfinite(d)) bad = 1.0;
+    for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
+      double pv[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int c = c0 + q * NT;
+        if (c < N) pv[q] = p[c];
+      }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int c = c0 + q * NT;
+        if (c >= N) continue;
+        const double d = (double)L0.u[c];
+        p[c] = pv[q] + d;
+        mx = fmax(mx, fabs(d));
+        if (!isfinite(d)) bad = 1.0;
+      }
     }
     dp = block_max(mx, red);
     const double anybad = block_max(bad, red);
@@ -148,7 +234,9 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     }
   }
   __syncthreads();
-  const double q = mean_saturation(P, a.fields, a.F, N, s, p, red);
+  if (SL)
+    for (int c = threadIdx.x; c < N; c += blockDim.x) pg[c] = p[c];
+  const double q = mean_saturation(P, fld, F, N, 0, p, red);
   if (threadIdx.x == 0) {
     a.qoi[s] = status == RMG_SAMPLE_OK ? q : __longlong_as_double(0x7ff8000000000000ll);
     a.status[s] = status;
@@ -170,35 +258,46 @@ static int ilog2(int v) {
   return l;
 }
 
-size_t whole_sample_lds_bytes(int n, int nc, bool fp64) {
+// LDS bytes of the whole-sample kernel (0 if it does not fit); *state_in_lds tells
+// whether the FP64 state fits as well (preferred up to 32 x 32).
+static size_t ws_bytes(int n, int nc, bool fp64, int F, bool state) {
   const int nlev = ilog2(n) - ilog2(nc) + 1;
   size_t relems = 0;
   for (int l = 0, m = n; l < nlev; ++l, m >>= 1) relems += lds_level_elems(m);
-  const size_t NC = (size_t)nc * nc;
-  size_t bytes = 8 * ((size_t)n * n + whole_doubles((int)NC)) + relems * (fp64 ? 8 : 4);
-  return bytes <= 160 * 1024 ? bytes : 0;
+  const size_t NC = (size_t)nc * nc, N = (size_t)n * n;
+  return 8 * (N + whole_doubles((int)NC) + (state ? (2 + F) * N : 0)) + relems * (fp64 ? 8 : 4);
 }
 
-// Threads per workgroup of the whole-sample kernel: enough waves per CU to hide
-// LDS and global latency when the LDS footprint admits a single workgroup.
-int whole_sample_threads(int n) { return n >= 64 ? 1024 : 256; }
+size_t whole_sample_lds_bytes(int n, int nc, bool fp64, int F, bool* state_in_lds) {
+  const size_t cap = 160 * 1024;
+  const size_t with = ws_bytes(n, nc, fp64, F, true), without = ws_bytes(n, nc, fp64, F, false);
+  const bool st = n <= 32 && with <= cap;
+  if (state_in_lds) *state_in_lds = st;
+  const size_t b = st ? with : without;
+  return b <= cap ? b : 0;
+}
 
-template <class R, int NT>
+template <class R, int NT, bool SL>
 static hipError_t launch_ws(const SolveArgs& a, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_whole_sample<R, NT>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_whole_sample<R, NT, SL>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_whole_sample<R, NT>), dim3((unsigned)a.S), dim3(NT), lds, st, a);
+  hipLaunchKernelGGL((k_whole_sample<R, NT, SL>), dim3((unsigned)a.S), dim3(NT), lds, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
   const int nc = a.n >> (a.nlev - 1);
-  const size_t lds = whole_sample_lds_bytes(a.n, nc, fp64);
+  bool sl = false;
+  size_t lds = whole_sample_lds_bytes(a.n, nc, fp64, a.F, &sl);
   if (lds == 0) return hipErrorInvalidValue;
-  const bool big = whole_sample_threads(a.n) == 1024;
-  if (fp64) return big ? launch_ws<double, 1024>(a, lds, st) : launch_ws<double, 256>(a, lds, st);
-  return big ? launch_ws<float, 1024>(a, lds, st) : launch_ws<float, 256>(a, lds, st);
+  if (sl && a.state_global) {
+    sl = false;
+    lds = ws_bytes(a.n, nc, fp64, a.F, false);
+  }
+  constexpr int T = RMG_WS_THREADS;
+  if (fp64) return sl ? launch_ws<double, 256, true>(a, lds, st) : launch_ws<double, T, false>(a, lds, st);
+  return sl ? launch_ws<float, 256, true>(a, lds, st) : launch_ws<float, T, false>(a, lds, st);
 }
 
 // ============================================================ level streaming
@@ -242,21 +341,41 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   const int n = a.n;
   const int T = n < kTile ? n : kTile, TL = T + 2;
   const int ntx = n / T;
-  const int x0 = (blockIdx.x % ntx) * T, y0 = (blockIdx.x / ntx) * T;
+  const int tile = xcd_tile();
+  const int x0 = (tile % ntx) * T, y0 = (tile / ntx) * T;
   const int64_t N = (int64_t)n * n;
   const double* p = a.p + s * N;
-  for (int e = threadIdx.x; e < TL * TL; e += blockDim.x) {
-    const int lj = e / TL, li = e - lj * TL;
-    const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
-    double pv = 0.0, K = 0.0;
-    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
-      const int64_t c = (int64_t)gj * n + gi;
-      pv = p[c];
-      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
-      K = closure(P, pv, cf.Ks, cf.alpha, cf.nvg).K;
+  {
+    const int tot = TL * TL;
+    const unsigned mg = rmg_magic(TL);
+    constexpr int B = 4;
+    for (int k0 = threadIdx.x; k0 < tot; k0 += B * (int)blockDim.x) {
+      double pv[B], k0v[B], k1v[B], k2v[B];
+      bool in[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int k = k0 + q * (int)blockDim.x;
+        const int lj = (int)__umulhi((unsigned)k, mg), li = k - lj * TL;
+        const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
+        in[q] = k < tot && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        pv[q] = k0v[q] = k1v[q] = k2v[q] = 0.0;
+        if (in[q]) {
+          const int64_t c = (int64_t)gj * n + gi;
+          pv[q] = p[c];
+          const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+          k0v[q] = cf.Ks;
+          k1v[q] = cf.alpha;
+          k2v[q] = cf.nvg;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int k = k0 + q * (int)blockDim.x;
+        if (k >= tot) continue;
+        sp[k] = pv[q];
+        sK[k] = in[q] ? closure(P, pv[q], k0v[q], k1v[q], k2v[q]).K : 0.0;
+      }
     }
-    sp[e] = pv;
-    sK[e] = K;
   }
   __syncthreads();
   R* tcw = bufA;
@@ -268,8 +387,8 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   R* cdt0 = (R*)pl.lv.cdt[0] + s * N;
   R* ctop0 = (R*)pl.lv.ctop[0] + s * n;
   double* thold = a.theta_old + s * N;
-  for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
-    const int lj = e / T, li = e - lj * T;
+  RMG_TILE_FOR(T, li, lj) {
+    const int e = lj * T + li;
     const int gi = x0 + li, gj = y0 + lj;
     const int64_t c = (int64_t)gj * n + gi;
     const int le = (lj + 1) * TL + li + 1;
@@ -319,8 +438,8 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
     R* gcdt = (R*)pl.lv.cdt[l] + s * M2;
     R* gctop = (R*)pl.lv.ctop[l] + s * m;
     const int X0 = x0 >> l, Y0 = y0 >> l;
-    for (int e = threadIdx.x; e < tc * tc; e += blockDim.x) {
-      const int J = e / tc, I = e - J * tc;
+    RMG_TILE_FOR(tc, I, J) {
+      const int e = J * tc + I;
       const int f00 = (2 * J) * t + 2 * I;
       const R cw = coarse_face<R>(scw[f00], scw[f00 + t]);
       const R cs = coarse_face<R>(scs[f00], scs[f00 + 1]);
@@ -350,35 +469,48 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
 // cs = ctop so that the north coefficient of top cells is the Dirichlet weight.
 template <class R>
 struct TileLds {
-  R *u, *f, *cw, *cs, *cdt;
+  RMG_LDS R *u, *f, *cw, *cs, *cdt;
   int TW;
 };
+
 
 template <class R>
 __device__ void tile_load(const TileLds<R>& L, int H, int m, int x0, int y0, const R* U, const R* UC,
                           int mc, const R* F, const R* CW, const R* CS, const R* CDT, const R* CTOP,
                           bool u_zero) {
-  const int TW = L.TW;
-  for (int e = threadIdx.x; e < TW * TW; e += blockDim.x) {
-    const int lj = e / TW, li = e - lj * TW;
-    const int gi = x0 - H + li, gj = y0 - H + lj;
-    R u = (R)0, f = (R)0, cw = (R)0, cs = (R)0, cdt = (R)0;
-    if (gi >= 0 && gi < m && gj >= 0 && gj < m) {
-      const int64_t c = (int64_t)gj * m + gi;
-      if (!u_zero) u = U[c];
-      if (UC) u = u + UC[(int64_t)(gj >> 1) * mc + (gi >> 1)];
-      f = F[c];
-      cw = CW[c];
-      cs = CS[c];
-      cdt = CDT[c];
-    } else if (gj == m && gi >= 0 && gi < m) {
-      cs = CTOP[gi];
+  const int TW = L.TW, tot = TW * TW;
+  const unsigned mg = rmg_magic(TW);
+  constexpr int B = 4;  // loop iterations whose global loads are in flight together
+  for (int k0 = threadIdx.x; k0 < tot; k0 += B * (int)blockDim.x) {
+    R u[B], f[B], cw[B], cs[B], cdt[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int k = k0 + q * (int)blockDim.x;
+      const int lj = (int)__umulhi((unsigned)k, mg), li = k - lj * TW;
+      const int gi = x0 - H + li, gj = y0 - H + lj;
+      u[q] = f[q] = cw[q] = cs[q] = cdt[q] = (R)0;
+      if (k < tot && gi >= 0 && gi < m && gj >= 0 && gj < m) {
+        const int64_t c = (int64_t)gj * m + gi;
+        if (!u_zero) u[q] = U[c];
+        if (UC) u[q] = u[q] + UC[(int64_t)(gj >> 1) * mc + (gi >> 1)];
+        f[q] = F[c];
+        cw[q] = CW[c];
+        cs[q] = CS[c];
+        cdt[q] = CDT[c];
+      } else if (k < tot && gj == m && gi >= 0 && gi < m) {
+        cs[q] = CTOP[gi];
+      }
     }
-    L.u[e] = u;
-    L.f[e] = f;
-    L.cw[e] = cw;
-    L.cs[e] = cs;
-    L.cdt[e] = cdt;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int k = k0 + q * (int)blockDim.x;
+      if (k >= tot) continue;
+      L.u[k] = u[q];
+      L.f[k] = f[q];
+      L.cw[k] = cw[q];
+      L.cs[k] = cs[q];
+      L.cdt[k] = cdt[q];
+    }
   }
 }
 
@@ -391,13 +523,12 @@ __device__ __forceinline__ St5<R> tile_st5(const TileLds<R>& L, int e) {
 
 // One colour over the tile grown by `grow` cells on each side (clipped to the domain).
 template <class R>
-__device__ void tile_half_sweep(const TileLds<R>& L, int H, int m, int x0, int y0, int grow,
+__device__ void tile_half_sweep(const TileLds<R>& L, int H, int ts, int m, int x0, int y0, int grow,
                                 int colour) {
   const int TW = L.TW;
-  const int lo = H - grow, hi = H + kTile + grow;
+  const int lo = H - grow, hi = H + ts + grow;
   const int w = hi - lo;
-  for (int k = threadIdx.x; k < w * w; k += blockDim.x) {
-    const int rj = k / w, ri = k - rj * w;
+  RMG_TILE_FOR(w, ri, rj) {
     const int li = lo + ri, lj = lo + rj;
     const int gi = x0 - H + li, gj = y0 - H + lj;
     if (gi < 0 || gi >= m || gj < 0 || gj >= m || ((gi + gj) & 1) != colour) continue;
@@ -409,7 +540,7 @@ __device__ void tile_half_sweep(const TileLds<R>& L, int H, int m, int x0, int y
 template <class R>
 __device__ TileLds<R> tile_carve(unsigned char* smem, int TW) {
   TileLds<R> L;
-  R* b = (R*)smem;
+  RMG_LDS R* b = (RMG_LDS R*)smem;
   const int A = TW * TW;
   L.u = b;
   L.f = b + A;
@@ -420,18 +551,20 @@ __device__ TileLds<R> tile_carve(unsigned char* smem, int TW) {
   return L;
 }
 
-// Down leg on a streaming level l: nu1 sweeps, residual, restriction.
-template <class R>
+// Down leg on a streaming level l: nu1 sweeps, residual, restriction, on TS x TS
+// output tiles (TS = 16 or 32, chosen per level by the autotuner).
+template <class R, int TS>
 __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.y;
   if (!pl.state[s].active) return;
-  if (pl.tcells && threadIdx.x == 0) atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)(kTile * kTile));
+  if (pl.tcells && threadIdx.x == 0) atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)(TS * TS));
   const int m = a.n >> l, mc = m >> 1;
   const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
-  const int H = 2 * a.nu1 + 1, TW = kTile + 2 * H;
-  const int ntx = m / kTile;
-  const int x0 = (blockIdx.x % ntx) * kTile, y0 = (blockIdx.x / ntx) * kTile;
+  const int H = 2 * a.nu1 + 1, TW = TS + 2 * H;
+  const int ntx = m / TS;
+  const int tile = xcd_tile();
+  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   const TileLds<R> L = tile_carve<R>(smem, TW);
   R* U = (R*)pl.lv.u[l] + s * M2;
   tile_load<R>(L, H, m, x0, y0, U, nullptr, 0, (const R*)pl.lv.f[l] + s * M2,
@@ -439,13 +572,14 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
                (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m, u_zero != 0);
   __syncthreads();
   for (int st = 0; st < 2 * a.nu1; ++st) {
-    tile_half_sweep(L, H, m, x0, y0, 2 * a.nu1 - st, st & 1);
+    tile_half_sweep(L, H, TS, m, x0, y0, 2 * a.nu1 - st, st & 1);
     __syncthreads();
   }
-  // residual and restriction of the 16 x 16 coarse cells of the tile
+  // residual and restriction of the (TS/2)^2 coarse cells of the tile
+  constexpr int HC = TS / 2;
   R* FC = (R*)pl.lv.f[l + 1] + s * MC2;
-  for (int e = threadIdx.x; e < (kTile / 2) * (kTile / 2); e += blockDim.x) {
-    const int J = e / (kTile / 2), I = e - J * (kTile / 2);
+  for (int e = threadIdx.x; e < HC * HC; e += blockDim.x) {
+    const int J = e / HC, I = e - J * HC;
     const int t00 = (H + 2 * J) * TW + H + 2 * I;
     const R r00 = residual_value<R>(L.f[t00], L.u[t00], tile_st5(L, t00));
     const R r01 = residual_value<R>(L.f[t00 + 1], L.u[t00 + 1], tile_st5(L, t00 + 1));
@@ -453,15 +587,15 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
     const R r11 = residual_value<R>(L.f[t00 + TW + 1], L.u[t00 + TW + 1], tile_st5(L, t00 + TW + 1));
     FC[(int64_t)((y0 >> 1) + J) * mc + (x0 >> 1) + I] = restrict4<R>(r00, r01, r10, r11);
   }
-  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-    const int lj = e / kTile, li = e - lj * kTile;
+  for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+    const int lj = e / TS, li = e - lj * TS;
     U[(int64_t)(y0 + lj) * m + x0 + li] = L.u[(H + lj) * TW + H + li];
   }
 }
 
 // Up leg on a streaming level l: prolongation of level l+1, nu2 sweeps; on the
 // finest level (final != 0) the Picard update p += dp and ||dp||_inf instead of a store.
-template <class R>
+template <class R, int TS>
 __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final_) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kBlock / 64];
@@ -469,9 +603,10 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
   if (!pl.state[s].active) return;
   const int m = a.n >> l, mc = m >> 1;
   const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
-  const int H = 2 * a.nu2, TW = kTile + 2 * H;
-  const int ntx = m / kTile;
-  const int x0 = (blockIdx.x % ntx) * kTile, y0 = (blockIdx.x / ntx) * kTile;
+  const int H = 2 * a.nu2, TW = TS + 2 * H;
+  const int ntx = m / TS;
+  const int tile = xcd_tile();
+  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   const TileLds<R> L = tile_carve<R>(smem, TW);
   R* U = (R*)pl.lv.u[l] + s * M2;
   tile_load<R>(L, H, m, x0, y0, U, (const R*)pl.lv.u[l + 1] + s * MC2, mc,
@@ -480,22 +615,33 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
                (const R*)pl.lv.ctop[l] + s * m, false);
   __syncthreads();
   for (int st = 0; st < 2 * a.nu2; ++st) {
-    tile_half_sweep(L, H, m, x0, y0, 2 * a.nu2 - 1 - st, st & 1);
+    tile_half_sweep(L, H, TS, m, x0, y0, 2 * a.nu2 - 1 - st, st & 1);
     __syncthreads();
   }
   if (!final_) {
-    for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-      const int lj = e / kTile, li = e - lj * kTile;
+    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+      const int lj = e / TS, li = e - lj * TS;
       U[(int64_t)(y0 + lj) * m + x0 + li] = L.u[(H + lj) * TW + H + li];
     }
     return;
   }
   double* p = a.p + s * M2;
   double mx = 0.0, bad = 0.0;
-  for (int e = threadIdx.x; e < kTile * kTile; e += blockDim.x) {
-    const int lj = e / kTile, li = e - lj * kTile;
+  constexpr int PER = TS * TS / kBlock;
+  static_assert(PER * kBlock == TS * TS, "whole cells per thread");
+  double pv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    const int lj = e / TS, li = e - lj * TS;
+    pv[q] = p[(int64_t)(y0 + lj) * m + x0 + li];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    const int lj = e / TS, li = e - lj * TS;
     const double d = (double)L.u[(H + lj) * TW + H + li];
-    p[(int64_t)(y0 + lj) * m + x0 + li] += d;
+    p[(int64_t)(y0 + lj) * m + x0 + li] = pv[q] + d;
     mx = fmax(mx, fabs(d));
     if (!isfinite(d)) bad = 1.0;
   }
@@ -520,9 +666,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
   const int nlev = a.nlev - lt;
   const int mc = a.n >> (a.nlev - 1), NC = mc * mc;
   const int64_t M2 = (int64_t)m * m;
-  double* A = (double*)smem;
-  double* ipiv = A + NC * (NC + 1);
-  double* red = ipiv + 16;
+  RMG_LDS double* A = (RMG_LDS double*)smem;
+  RMG_LDS double* ipiv = A + NC * (NC + 1);
+  double* red = (double*)(ipiv + 16);
   R* rbase = (R*)(red + kBlock / 64);
   __shared__ LdsLevel<R> lev[kMaxLevels];
   R* rend = lds_carve(rbase, lev, m, nlev);
@@ -535,12 +681,30 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
   const R* CDT = (const R*)pl.lv.cdt[lt] + s * M2;
   const R* CT = (const R*)pl.lv.ctop[lt] + s * m;
   R* U = (R*)pl.lv.u[lt] + s * M2;
-  for (int c = threadIdx.x; c < M2; c += blockDim.x) {
-    T.f[c] = F[c];
-    T.cw[c] = CW[c];
-    T.cs[c] = CS[c];
-    T.cdt[c] = CDT[c];
-    if (!u_zero) T.u[c] = U[c];
+  for (int c0 = threadIdx.x; c0 < M2; c0 += 4 * (int)blockDim.x) {
+    R f[4], cw[4], cs[4], cdt[4], u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + q * (int)blockDim.x;
+      if (c < M2) {
+        f[q] = F[c];
+        cw[q] = CW[c];
+        cs[q] = CS[c];
+        cdt[q] = CDT[c];
+        u[q] = u_zero ? (R)0 : U[c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + q * (int)blockDim.x;
+      if (c < M2) {
+        T.f[c] = f[q];
+        T.cw[c] = cw[q];
+        T.cs[c] = cs[q];
+        T.cdt[c] = cdt[q];
+        T.u[c] = u[q];
+      }
+    }
   }
   for (int i = threadIdx.x; i < m; i += blockDim.x) T.cs[M2 + i] = CT[i];
   __syncthreads();
@@ -548,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
     lds_coarsen(lev[l], lev[l + 1]);
     __syncthreads();
   }
-  lds_vcycle(lev, 0, nlev, a.nu1, a.nu2, A, ipiv);
+  lds_vcycle(lev, 0, nlev, a.nu1, a.nu2, A, ipiv, u_zero != 0);
   if (lt > 0 || !final_) {
     for (int c = threadIdx.x; c < M2; c += blockDim.x) U[c] = T.u[c];
     return;
@@ -636,8 +800,8 @@ hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStrea
   return hipGetLastError();
 }
 
-static size_t tile_lds(int H, bool fp64) {
-  const size_t TW = kTile + 2 * H;
+static size_t tile_lds(int H, int ts, bool fp64) {
+  const size_t TW = ts + 2 * H;
   return 5 * TW * TW * (fp64 ? 8 : 4);
 }
 
@@ -646,6 +810,24 @@ static size_t coarse_lds(int m, int nc, bool fp64) {
   for (int mm = m; mm >= nc; mm >>= 1) relems += lds_level_elems(mm);
   const size_t NC = (size_t)nc * nc;
   return 8 * (NC * (NC + 1) + 16 + kBlock / 64) + relems * (fp64 ? 8 : 4);
+}
+
+template <class R>
+static void launch_down(int ts, dim3 grid, size_t lds, hipStream_t st, const SolveArgs& a, const StreamPlan& pl,
+                        int l, int u_zero) {
+  if (ts == 16)
+    hipLaunchKernelGGL((k_down<R, 16>), grid, dim3(kBlock), lds, st, a, pl, l, u_zero);
+  else
+    hipLaunchKernelGGL((k_down<R, 32>), grid, dim3(kBlock), lds, st, a, pl, l, u_zero);
+}
+
+template <class R>
+static void launch_up(int ts, dim3 grid, size_t lds, hipStream_t st, const SolveArgs& a, const StreamPlan& pl,
+                      int l, int final_) {
+  if (ts == 16)
+    hipLaunchKernelGGL((k_up<R, 16>), grid, dim3(kBlock), lds, st, a, pl, l, final_);
+  else
+    hipLaunchKernelGGL((k_up<R, 32>), grid, dim3(kBlock), lds, st, a, pl, l, final_);
 }
 
 template <class R>
@@ -659,12 +841,11 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
     hipLaunchKernelGGL(k_fine<R>, dim3(tiles, (unsigned)a.S), blk, 0, st, a, pl);
   }
   const int nc = n >> (a.nlev - 1);
-  const size_t ldn = tile_lds(2 * a.nu1 + 1, fp64), lup = tile_lds(2 * a.nu2, fp64);
   const size_t lcv = coarse_lds(n >> pl.ltop, nc, fp64);
   for (int cyc = 0; cyc < a.cpp; ++cyc) {
     for (int l = 0; l < pl.ltop; ++l) {
-      const int m = n >> l;
-      const unsigned tiles = (unsigned)((m / kTile) * (m / kTile));
+      const int m = n >> l, ts = pl.ts[l];
+      const unsigned tiles = (unsigned)((m / ts) * (m / ts));
       KernelTimer* tm = pl.timer;
       const bool timed = tm && tm->which == 1 && tm->used < tm->cap;
       StreamPlan plx = pl;
@@ -673,8 +854,8 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
         hipError_t e = hipEventRecord(tm->ev[2 * tm->used], st);
         if (e != hipSuccess) return e;
       }
-      hipLaunchKernelGGL(k_down<R>, dim3(tiles, (unsigned)a.S), blk, ldn, st, a, plx, l,
-                         (l > 0 || cyc == 0) ? 1 : 0);
+      launch_down<R>(ts, dim3(tiles, (unsigned)a.S), tile_lds(2 * a.nu1 + 1, ts, fp64), st, a, plx, l,
+                     (l > 0 || cyc == 0) ? 1 : 0);
       if (timed) {
         hipError_t e = hipEventRecord(tm->ev[2 * tm->used + 1], st);
         if (e != hipSuccess) return e;
@@ -684,10 +865,10 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
     hipLaunchKernelGGL(k_coarse_v<R>, dim3((unsigned)a.S), blk, lcv, st, a, pl,
                        (pl.ltop > 0 || cyc == 0) ? 1 : 0, (cyc == a.cpp - 1) ? 1 : 0);
     for (int l = pl.ltop - 1; l >= 0; --l) {
-      const int m = n >> l;
-      const unsigned tiles = (unsigned)((m / kTile) * (m / kTile));
-      hipLaunchKernelGGL(k_up<R>, dim3(tiles, (unsigned)a.S), blk, lup, st, a, pl, l,
-                         (l == 0 && cyc == a.cpp - 1) ? 1 : 0);
+      const int m = n >> l, ts = pl.ts[l];
+      const unsigned tiles = (unsigned)((m / ts) * (m / ts));
+      launch_up<R>(ts, dim3(tiles, (unsigned)a.S), tile_lds(2 * a.nu2, ts, fp64), st, a, pl, l,
+                   (l == 0 && cyc == a.cpp - 1) ? 1 : 0);
     }
   }
   hipLaunchKernelGGL(k_control, dim3((unsigned)((a.S + kBlock - 1) / kBlock)), blk, 0, st, a, pl);
@@ -698,24 +879,30 @@ template <class R>
 static hipError_t set_stream_lds(const SolveArgs& a, const StreamPlan& pl) {
   const bool fp64 = sizeof(R) == 8;
   const int nc = a.n >> (a.nlev - 1);
-  hipError_t e = hipFuncSetAttribute((const void*)k_down<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)tile_lds(2 * a.nu1 + 1, fp64));
+  const int hd = 2 * a.nu1 + 1, hu = 2 * a.nu2;
+  hipError_t e = hipFuncSetAttribute((const void*)k_down<R, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)tile_lds(hd, 16, fp64));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_up<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)tile_lds(2 * a.nu2, fp64));
+    e = hipFuncSetAttribute((const void*)k_down<R, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)tile_lds(hd, 32, fp64));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_up<R, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)tile_lds(hu, 16, fp64));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_up<R, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)tile_lds(hu, 32, fp64));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_coarse_v<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)coarse_lds(a.n >> pl.ltop, nc, fp64));
   return e;
 }
 
+hipError_t prepare_stream(const SolveArgs& a, const StreamPlan& pl) {
+  return pl.fp64 ? set_stream_lds<double>(a, pl) : set_stream_lds<float>(a, pl);
+}
+
 hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
-  if (pl.fp64) {
-    hipError_t e = set_stream_lds<double>(a, pl);
-    return e != hipSuccess ? e : stream_iteration<double>(a, pl, st);
-  }
-  hipError_t e = set_stream_lds<float>(a, pl);
-  return e != hipSuccess ? e : stream_iteration<float>(a, pl, st);
+  return pl.fp64 ? stream_iteration<double>(a, pl, st) : stream_iteration<float>(a, pl, st);
 }
 
 hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
