@@ -14,7 +14,7 @@
  *   - estimator: Section 5.1, eqs. telescope, MLMCestimator, SMC, ML_var.
  *
  * Conventions shared by every entry point
- *   Domain (0,1)^2, n x n cells, h = 1/n, n a power of two with 4 <= n <= 4096.
+ *   Domain (0,1)^2, n x n cells, h = 1/n, n a power of two (range per entry point).
  *   Cell c = j*n + i, x (index i) fastest, j = 0 the bottom row, z up.
  *   Top (z = 1) and bottom (z = 0) faces are Dirichlet, the sides are no-flux.
  *   Pointers named d_* are device memory, h_* host memory; all are owned by the
@@ -64,6 +64,8 @@ typedef struct {
 } rmg_marginal;
 
 /* One deterministic problem (closure model, boundary and initial data, time grid).
+ * qoi must be RMG_QOI_MEAN_SATURATION in this build (the outflux QoI: RMG_EINVAL);
+ * theta_s > theta_r, dt > 0 and n_steps >= 1 are required.
  * Fields per cell: Gardner and linear use field 0 = Ks; van Genuchten-Mualem uses
  * field 0 = Ks, 1 = alpha, 2 = n (so n_fields = 1 or 3).
  *   Gardner: K = Ks e^{a h}, theta = theta_r + (theta_s - theta_r) e^{a h} (h < 0);
@@ -86,15 +88,15 @@ typedef struct {
 } rmg_problem;
 
 /* Solver options.  Defaults for the benchmark workloads: MIXED, V, 2, 2, 1,
- * eps_mg 1e-5 (unused when cycles_per_picard > 0), eps_picard 1e-8,
- * max_picard 100, coarsest_n 4. */
+ * eps_mg 1e-5 (unused), eps_picard 1e-8, max_picard 100 (500 in the MLMC
+ * benchmark), coarsest_n 4. */
 typedef struct {
   int32_t precision;          /* rmg_precision: FP64 everywhere, or FP32 multigrid inside FP64 Picard */
-  int32_t cycle;              /* rmg_cycle */
-  int32_t nu1, nu2;           /* pre/post red-black Gauss-Seidel sweeps, 0..8 */
-  int32_t cycles_per_picard;  /* >= 1: fixed number of cycles per Picard step */
+  int32_t cycle;              /* rmg_cycle; this build runs RMG_CYCLE_V only (W: RMG_EINVAL) */
+  int32_t nu1, nu2;           /* pre/post red-black Gauss-Seidel sweeps, each 0..4, not both 0 */
+  int32_t cycles_per_picard;  /* fixed number of cycles per Picard step, 1..16 */
   int32_t max_picard;         /* Picard iterations allowed per time step, >= 1 */
-  int32_t coarsest_n;         /* coarsest grid size (2, 4 or 8), solved exactly in FP64 */
+  int32_t coarsest_n;         /* coarsest grid size, 2 or 4, solved exactly in FP64 */
   int32_t flags;              /* bit 0: force the level-streaming path (no whole-sample-in-LDS kernel);
                                  bit 1: launch the streaming Picard iterations eagerly instead of
                                  replaying a captured HIP graph (results are identical);
@@ -103,7 +105,7 @@ typedef struct {
                                  bit 3: no autotuning of the streaming tile shapes (32 x 32
                                  tiles on every level; results are identical);
                                  bit 4: 16 x 16 streaming tiles on every level, no autotuning */
-  double eps_mg;              /* reserved for a residual-controlled cycle count */
+  double eps_mg;              /* reserved for a residual-controlled cycle count (ignored) */
   double eps_picard;          /* stop when ||dp||_inf < eps_picard (strict) */
 } rmg_solver_opts;
 
@@ -140,7 +142,7 @@ typedef struct {
   const double* d_xi;             /* [n_samples][n_fields][n_modes] standard normals */
 } rmg_level;
 
-/* Size in bytes of the named ABI struct ("rmg_problem", "rmg_solver_opts",
+/* Size in bytes of the named ABI struct ("rmg_problem", "rmg_solver_opts", "rmg_kernel_timing",
  * "rmg_sample_stats", "rmg_level_sums", "rmg_level", "rmg_marginal"), or -1 if
  * unknown; lets bindings check their struct layouts against this build. */
 int64_t rmg_struct_size(const char* name);
@@ -178,7 +180,8 @@ const char* rmg_last_error(const rmg_ctx* ctx);
  *   d_fields[s][f][c] = h_marg[f].shift + exp(h_marg[f].log_mean + h_marg[f].scale * G[s][f][c])
  * d_basis [n_modes][n*n] holds sqrt(lambda_j) Psi_j(x_c); d_xi [S][n_fields][n_modes];
  * d_fields [S][n_fields][n*n].  All FP64.  Asynchronous on `stream`.
- * EINVAL: bad n, S < 1, n_fields not in 1..4, n_modes not in 1..1024, NULL pointer.
+ * EINVAL: n not a power of two in 4..4096, S < 1, n_fields not in 1..4, n_modes not in
+ * 1..1024, NULL pointer.
  */
 int sample_fields(rmg_ctx* ctx, int n, int n_fields, int n_modes,
                   const double* d_basis, const double* d_xi, const rmg_marginal* h_marg,
@@ -196,8 +199,10 @@ int sample_fields(rmg_ctx* ctx, int n, int n_fields, int n_modes,
  *   d_stats   [S] rmg_sample_stats, may be NULL
  * Synchronises with `stream` once per poll of the active-sample count.
  * Returns RMG_ENOTCONV if some sample failed (its outputs are flagged).
- * EINVAL: bad n or coarsest_n, S < 1, NULL pointer, unknown model/precision/cycle,
- * nu1 + nu2 == 0, max_picard < 1, eps_picard <= 0, dt <= 0, n_steps < 1.
+ * EINVAL: n not a power of two in 2..1024 or below coarsest_n, S not in 1..65535,
+ * NULL d_fields/d_h_out/d_qoi/d_status, any problem or option outside the ranges
+ * documented on rmg_problem and rmg_solver_opts.
+ * EHIP: a HIP call failed (the stream's work may be incomplete); ENOMEM: workspace.
  */
 int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
                     const double* d_fields, int64_t S,
@@ -215,8 +220,10 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
  *   d_qoi_out: optional device array [sum_l 2*n_samples_l] receiving, level by
  *   level, the fine QoIs then the coarse QoIs (NaN marks failure); may be NULL.
  * Synchronises with `stream` before returning.  Returns RMG_ENOTCONV if some
- * sample failed.  EINVAL as for picard_mg_solve, plus n_coarse != n_fine / 2 on
- * levels >= 1, or n_coarse != 0 on level 0.
+ * sample failed.  EINVAL as for picard_mg_solve, plus: n_levels not in 1..16,
+ * n_fine not a power of two in 4..1024, n_coarse != n_fine / 2 on levels >= 1 or
+ * != 0 on level 0, a grid size used by more than one fine and one coarse segment,
+ * more than 65535 solves on one grid size, NULL basis/xi pointers.
  */
 int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* h_levels,
                         int n_fields, int n_modes, const rmg_marginal* h_marg,
