@@ -74,27 +74,29 @@ def _oracle_job(args):
 def cpu_baseline(max_picard, cycles, gpu_its_per_solve):
     """Time the CPU oracle on a bounded sample of the workload, one solve per worker process.
 
-    Sample: 8 solves on 16^2, 8 on 32^2, 4 on 64^2 (the first draws of the corresponding
-    levels).  The full workload's oracle time is estimated per grid as (solves on that
-    grid) x (mean measured seconds per solve); 128^2 and 256^2 are not run (one solve
-    takes tens of seconds to minutes) and are estimated from the 64^2 time per
-    cell-iteration times the cell-iterations the GPU run performed on those grids.
-    Workers run in parallel, so the estimate is divided by the worker count.
+    Sample: the first draws of the fine member of each level, 32 solves on 16^2, 32 on
+    32^2, 16 on 64^2 and 8 on 128^2 (failing draws included, as in the workload).  The
+    full workload's oracle time is estimated per grid as (solves on that grid) x (mean
+    measured seconds per solve); 256^2 is not run (one solve takes up to minutes) and is
+    estimated from the 128^2 seconds per cell-iteration times the cell-iterations the GPU
+    run performed on 256^2.  Workers run in parallel, so the estimate is divided by the
+    worker count.
     """
     import multiprocessing as mp
     import workloads as W
     from oracle import kl as okl
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
     f = W.KS_FIELD
-    _, B = okl.basis(f["sigma2"], f["corr_len"], f["n_modes"], [16, 32, 64], ref_n=64)
-    jobs = [(16, 0, i, max_picard, cycles, B[16]) for i in range(8)]
-    jobs += [(32, 1, i, max_picard, cycles, B[32]) for i in range(8)]
-    jobs += [(64, 2, i, max_picard, cycles, B[64]) for i in range(4)]
+    grids, samples = W.MLMC_5LEVEL["grids"], W.MLMC_5LEVEL["samples"]
+    run = {16: 32, 32: 32, 64: 16, 128: 8}
+    _, B = okl.basis(f["sigma2"], f["corr_len"], f["n_modes"], list(run), ref_n=64)
+    jobs = [(n, grids.index(n), i, max_picard, cycles, B[n]) for n in sorted(run, reverse=True)
+            for i in range(run[n])]
     env_threads = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(min(cores, len(jobs))) as pool:
-        res = pool.map(_oracle_job, jobs)
+        res = list(pool.imap_unordered(_oracle_job, jobs, chunksize=1))
     wall = time.perf_counter() - t0
     if env_threads is None:
         os.environ.pop("OMP_NUM_THREADS", None)
@@ -103,21 +105,26 @@ def cpu_baseline(max_picard, cycles, gpu_its_per_solve):
     per = {}
     for n, t, its, st in res:
         per.setdefault(n, []).append((t, its))
-    counts = {16: 5120, 32: 1280, 64: 320, 128: 80, 256: 16}
+    # solves per grid: the fine members of level l and the coarse members of level l + 1
+    counts = {n: samples[l] + (samples[l + 1] if l + 1 < len(grids) else 0) for l, n in enumerate(grids)}
     est = 0.0
     for n, c in counts.items():
         if n in per:
             est += c * sum(t for t, _ in per[n]) / len(per[n])
-    sec_per_cell_it = sum(t for t, _ in per[64]) / (sum(i for _, i in per[64]) * 64 * 64)
-    for n in (128, 256):
-        est += counts[n] * gpu_its_per_solve.get(n, 0.0) * n * n * sec_per_cell_it
+    nx = max(run)
+    sec_per_cell_it = sum(t for t, _ in per[nx]) / (sum(i for _, i in per[nx]) * nx * nx)
+    for n in counts:
+        if n not in per:
+            est += counts[n] * gpu_its_per_solve.get(n, 0.0) * n * n * sec_per_cell_it
     est_wall = est / cores
     total = sum(counts.values())
+    desc = ", ".join(f"{run[n]}x{n}^2" for n in sorted(run))
     return {"value": total / est_wall, "unit": "sample solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(jobs)} oracle solves (8x16^2, 8x32^2, 4x64^2, twin mode) in {wall:.1f}s wall on "
-                      f"{min(cores, len(jobs))} processes; full-workload time estimated per grid from the "
-                      "measured mean time per solve, 128^2 and 256^2 from the 64^2 time per cell-iteration "
-                      "and the GPU run's iteration counts on those grids, divided by the worker count"}
+            "sample": f"{len(jobs)} oracle solves ({desc}; first draws of each level's fine member, "
+                      f"twin mode) in {wall:.1f}s wall on {min(cores, len(jobs))} processes; the "
+                      f"{total}-solve workload's time is estimated per grid from the measured mean "
+                      f"time per solve, 256^2 from the {nx}^2 time per cell-iteration and the GPU "
+                      "run's iteration counts on 256^2, divided by the worker count"}
 
 
 def main():

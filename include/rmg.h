@@ -148,10 +148,14 @@ typedef struct {
 int64_t rmg_struct_size(const char* name);
 
 /* Kernel timing (diagnostics; used by the benchmark to price the smoother
- * against HBM bandwidth).  RMG_TIME_SMOOTHER_DOWN brackets every launch of the
+ * against HBM bandwidth).  RMG_TIME_SMOOTHER_DOWN brackets the launches of the
  * level-streaming down-leg kernel (nu1 fused red-black sweeps + residual +
- * restriction, Section 4.2) with HIP events on the stream it runs on, and counts
- * the fine cells those launches processed.  Algorithmic bytes per processed cell
+ * restriction, Section 4.2) with HIP events on the stream they run on, and counts
+ * the fine cells those launches processed.  The streaming solver advances in
+ * batches of eight Picard iterations; the first iteration of every batch is
+ * launched eagerly and timed, the other seven replay a HIP graph (events recorded
+ * inside a graph cannot be timed), so the totals cover a uniform one-in-eight
+ * sample of the launches.  Results do not depend on timing.  Algorithmic bytes per processed cell
  * (each array touched once): read f, the two face coefficients and C/dt, write
  * the iterate and a quarter of a coarse right-hand side (5.25 elements), plus
  * one element when the initial iterate is loaded rather than zero. */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -11,6 +12,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/rmg.h"
@@ -27,6 +29,8 @@ struct rmg_ctx {
   int32_t* h_count = nullptr;  // pinned host mirror of the active-sample counters
   hipStream_t side[8] = {};
   hipEvent_t ev[8] = {};
+  // completion markers of the iteration batches in flight, per class and slot
+  hipEvent_t pev[16][4] = {};
   // one timer per concurrently running class (each on its own stream)
   KernelTimer timers[8] = {};
   int timer_es[8] = {};
@@ -144,7 +148,7 @@ size_t class_ws_bytes(const ClassJob& j) {
   const int n = j.a.n;
   size_t b = 256 + 8 * (size_t)S * n * n;  // theta_old
   if (!j.whole) {
-    for (int l = 0; l <= j.pl.ltop; ++l) b += 256 * 6 + level_bytes(n >> l, S, j.fp64);
+    for (int l = 0; l <= j.pl.ltop; ++l) b += 256 * 7 + level_bytes(n >> l, S, j.fp64);
     b += 3 * 256 + sizeof(SampleState) * S + 8 * S + 8;
   }
   return b;
@@ -159,6 +163,7 @@ void class_carve(ClassJob& j, Arena& ar) {
   for (int l = 0; l <= j.pl.ltop; ++l) {
     const size_t m = (size_t)(n >> l);
     j.pl.lv.u[l] = ar.take(es * S * m * m);
+    j.pl.lv.ub[l] = ar.take(es * S * m * m);
     j.pl.lv.f[l] = ar.take(es * S * m * m);
     j.pl.lv.cw[l] = ar.take(es * S * m * m);
     j.pl.lv.cs[l] = ar.take(es * S * m * m);
@@ -233,51 +238,61 @@ int autotune_class(rmg_ctx* ctx, ClassJob& j) {
   return RMG_OK;
 }
 
-int harvest_timer(rmg_ctx* ctx, KernelTimer* t) {
+// Add the durations of the timed launches recorded before `upto` (all complete).
+int harvest_timer(rmg_ctx* ctx, KernelTimer* t, int64_t upto) {
   if (!t) return RMG_OK;
-  for (int q = 0; q < t->used; ++q) {
+  for (; t->head < upto; ++t->head) {
+    const int q = (int)(t->head % t->cap);
     float ms = 0.f;
     HIP_TRY(ctx, hipEventElapsedTime(&ms, t->ev[2 * q], t->ev[2 * q + 1]));
     t->total_ms += ms;
     ++t->launches;
   }
-  if (!t->in_graph) t->used = 0;
   return RMG_OK;
 }
 
-// Run every class to completion: whole-sample classes are single launches;
-// streaming classes replay a HIP graph of G captured Picard iterations and poll
-// the number of still-active samples once per replay (one 4-byte read-back).
+// Run every class to completion.  Whole-sample classes are single launches.  A
+// streaming class advances in batches of G Picard iterations (a replayed HIP graph,
+// or eager launches); each batch ends with a 4-byte read-back of the class's
+// active-sample count and an event.  D batches stay in flight per class, so the
+// device never waits for the host; batches issued after the count reached zero
+// find no active sample and do nothing.  Classes are polled independently.
+// With kernel timing on, the first iteration of every batch is launched eagerly
+// with its timed launches bracketed by events (events recorded by graph nodes
+// cannot be timed) and the other G - 1 replay a graph: a uniform sample of the
+// launches, one in G, at almost no cost to the run.
 int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
-  // events recorded by graph nodes cannot be queried, so timed runs launch eagerly
-  // (measured: graph replay and eager launch differ by ~2-3% on these kernels)
-  if (ctx->timing) use_graphs = false;
+  constexpr int G = 8, D = 3;
+  const bool timing = ctx->timing != 0;
+  const int Gg = timing ? G - 1 : G;  // iterations per graph replay
+  if (jobs.size() > 16) return fail(ctx, RMG_EINVAL, "too many grid-size classes");
   int ti = 0;
   for (auto& j : jobs) {
     j.pl.timer = nullptr;
     j.pl.tcells = nullptr;
     if (ctx->timing && !j.whole && ti < 8) {
       j.pl.timer = &ctx->timers[ti];
-      j.pl.timer->used = 0;
-      j.pl.timer->in_graph = false;
+      j.pl.timer->head = j.pl.timer->tail = 0;
       ctx->timer_es[ti] = j.fp64 ? 8 : 4;
       ++ti;
     }
   }
+  // Streaming classes first: their set-up (and a first call's synchronous tile
+  // autotuning) must not wait behind, or be timed against, the whole-sample kernels.
   for (auto& j : jobs) {
-    if (j.whole) {
-      HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
-      j.done = true;
-    } else {
-      HIP_TRY(ctx, prepare_stream(j.a, j.pl));
-      HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
-      if (j.autotune) {
-        const int rc = autotune_class(ctx, j);
-        if (rc != RMG_OK) return rc;
-      }
+    if (j.whole) continue;
+    HIP_TRY(ctx, prepare_stream(j.a, j.pl));
+    HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
+    if (j.autotune) {
+      const int rc = autotune_class(ctx, j);
+      if (rc != RMG_OK) return rc;
     }
   }
-  const int G = 8;
+  for (auto& j : jobs) {
+    if (!j.whole) continue;
+    HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
+    j.done = true;
+  }
   std::vector<hipGraphExec_t> execs(jobs.size(), nullptr);
   std::vector<hipGraph_t> graphs(jobs.size(), nullptr);
   auto cleanup = [&]() {
@@ -290,11 +305,12 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     for (size_t c = 0; c < jobs.size(); ++c) {
       ClassJob& j = jobs[c];
       if (j.done) continue;
-      if (j.pl.timer) j.pl.timer->in_graph = true;
+      StreamPlan untimed = j.pl;
+      untimed.timer = nullptr;
       const char* what = "hipStreamBeginCapture";
       hipError_t e = hipStreamBeginCapture(j.stream, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) what = "captured iteration launches";
-      for (int i = 0; i < G && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, j.pl, j.stream);
+      for (int i = 0; i < Gg && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, untimed, j.stream);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(j.stream, &g);
       graphs[c] = g;
@@ -314,55 +330,80 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     }
   }
   // every sample stops after at most n_steps * max_picard iterations
-  long bound = 0;
-  for (auto& j : jobs) {
-    const long steps = std::max(j.a.cp.prob[0].n_steps, j.a.cp.prob[1].n_steps);
-    bound = std::max(bound, steps * (long)j.a.max_picard + 2L * G);
-  }
-  long launched = 0;
+  std::vector<int64_t> issued(jobs.size(), 0), retired(jobs.size(), 0);
+  std::vector<std::array<int64_t, D>> mark(jobs.size());
+  auto bound = [&](const ClassJob& j) {
+    const int64_t steps = std::max(j.a.cp.prob[0].n_steps, j.a.cp.prob[1].n_steps);
+    return steps * (int64_t)j.a.max_picard + (int64_t)(D + 1) * G;
+  };
+  auto issue = [&](size_t c) -> hipError_t {
+    ClassJob& j = jobs[c];
+    const int k = (int)(issued[c] % D);
+    StreamPlan untimed = j.pl;
+    untimed.timer = nullptr;
+    hipError_t e = hipSuccess;
+    if (timing) e = launch_stream_iteration(j.a, j.pl, j.stream);
+    if (use_graphs) {
+      if (e == hipSuccess) e = hipGraphLaunch(execs[c], j.stream);
+    } else {
+      for (int i = timing ? 1 : 0; i < G && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, untimed, j.stream);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(j.h_count + k, j.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, j.stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->pev[c][k], j.stream);
+    mark[c][k] = j.pl.timer ? j.pl.timer->tail : 0;
+    ++issued[c];
+    return e;
+  };
   int rc = RMG_OK;
-  for (;;) {
-    bool any = false;
-    for (size_t c = 0; c < jobs.size() && rc == RMG_OK; ++c) {
-      ClassJob& j = jobs[c];
-      if (j.done) continue;
-      any = true;
-      hipError_t e = hipSuccess;
-      if (use_graphs) {
-        e = hipGraphLaunch(execs[c], j.stream);
-      } else {
-        for (int i = 0; i < G && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, j.pl, j.stream);
-      }
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(j.h_count, j.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, j.stream);
+  size_t active = 0;
+  for (size_t c = 0; c < jobs.size() && rc == RMG_OK; ++c) {
+    if (jobs[c].done) continue;
+    ++active;
+    for (int k = 0; k < D && rc == RMG_OK; ++k) {
+      const hipError_t e = issue(c);
       if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "iteration launch failed: %s", hipGetErrorString(e));
     }
-    if (!any || rc != RMG_OK) break;
+  }
+  while (active > 0 && rc == RMG_OK) {
+    bool progressed = false;
     for (size_t c = 0; c < jobs.size() && rc == RMG_OK; ++c) {
       ClassJob& j = jobs[c];
       if (j.done) continue;
-      hipError_t e = hipStreamSynchronize(j.stream);
+      const int k = (int)(retired[c] % D);
+      hipError_t e = hipEventQuery(ctx->pev[c][k]);
+      if (e == hipErrorNotReady) continue;
       if (e != hipSuccess) {
-        rc = fail(ctx, RMG_EHIP, "stream synchronize: %s", hipGetErrorString(e));
+        rc = fail(ctx, RMG_EHIP, "iteration batch: %s", hipGetErrorString(e));
         break;
       }
-      if ((rc = harvest_timer(ctx, j.pl.timer)) != RMG_OK) break;
-      if (*j.h_count == 0) {
+      progressed = true;
+      if ((rc = harvest_timer(ctx, j.pl.timer, mark[c][k])) != RMG_OK) break;
+      const int32_t left = ((volatile int32_t*)j.h_count)[k];
+      ++retired[c];
+      if (left == 0) {
         e = launch_stream_finish(j.a, j.pl, j.stream);
         if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "finish launch: %s", hipGetErrorString(e));
         j.done = true;
+        --active;
+        continue;
       }
+      if (issued[c] * G > bound(j)) {
+        rc = fail(ctx, RMG_EHIP, "samples still active after %lld iterations", (long long)(issued[c] * G));
+        break;
+      }
+      e = issue(c);
+      if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "iteration launch failed: %s", hipGetErrorString(e));
     }
-    launched += G;
-    if (rc == RMG_OK && launched > bound)
-      rc = fail(ctx, RMG_EHIP, "samples still active after %ld iterations", launched);
-    if (rc != RMG_OK) break;
+    if (!progressed) std::this_thread::yield();
   }
-  for (auto& j : jobs)
-    if (j.pl.timer) {
-      j.pl.timer->in_graph = false;
-      j.pl.timer->used = 0;
-    }
+  // leave nothing of this call running on an error; collect the last timed launches
+  for (auto& j : jobs) {
+    if (j.whole) continue;
+    const hipError_t e = hipStreamSynchronize(j.stream);
+    if (e != hipSuccess && rc == RMG_OK) rc = fail(ctx, RMG_EHIP, "stream synchronize: %s", hipGetErrorString(e));
+    if (rc == RMG_OK && j.pl.timer) rc = harvest_timer(ctx, j.pl.timer, j.pl.timer->tail);
+  }
   cleanup();
   return rc;
 }
@@ -409,6 +450,12 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device) {
       return RMG_EHIP;
     }
   }
+  for (auto& row : c->pev)
+    for (auto& e : row)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        rmg_ctx_destroy(c);
+        return RMG_EHIP;
+      }
   for (auto& e : c->tev) {
     if (hipEventCreate(&e) != hipSuccess) {
       rmg_ctx_destroy(c);
@@ -454,7 +501,7 @@ int rmg_set_kernel_timing(rmg_ctx* c, int which) {
   }
   for (auto& t : c->timers) {
     t.which = which;
-    t.used = 0;
+    t.head = t.tail = 0;
     t.launches = 0;
     t.total_ms = 0.0;
   }
@@ -492,6 +539,9 @@ void rmg_ctx_destroy(rmg_ctx* c) {
   if (c->d_tcells) (void)hipFree(c->d_tcells);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& row : c->pev)
+    for (auto& e : row)
+      if (e) (void)hipEventDestroy(e);
   for (auto& s : c->side)
     if (s) (void)hipStreamDestroy(s);
   if (c->ws) (void)hipFree(c->ws);
@@ -689,12 +739,21 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
       row += v.n_samples;
     }
   }
-  // whole-sample classes on side streams, streaming classes each on their own stream
+  // Every whole-sample class runs on side stream 0, one after the other; each
+  // streaming class gets a side stream of its own.  HIP multiplexes streams onto a
+  // few hardware queues (four by default, one taken by the caller's stream), and a
+  // streaming class whose stream shares a queue with a long whole-sample kernel
+  // cannot start its chain of short launches until that kernel ends.
   HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
-  const int nside = (int)std::min<size_t>(jobs.size(), 7);
+  int nside = 1;
   for (size_t c = 0; c < jobs.size(); ++c) {
-    jobs[c].stream = ctx->side[c % 7];
-    jobs[c].h_count = ctx->h_count + 4 * (int)(c % 16);
+    if (jobs[c].whole) {
+      jobs[c].stream = ctx->side[0];
+    } else {
+      if (nside == 7) return fail(ctx, RMG_EINVAL, "more than six level-streaming grid sizes");
+      jobs[c].stream = ctx->side[nside++];
+    }
+    jobs[c].h_count = ctx->h_count + 4 * (int)c;
   }
   for (int q = 0; q < nside; ++q) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[q], ctx->ev[0], 0));
   if ((rc = run_classes(ctx, jobs, !(opts->flags & 2)))) return rc;

@@ -25,8 +25,13 @@ struct ClassProblems {
   int64_t seg_split;
 };
 
+// Per-level arrays of the streaming path.  A down or up kernel reads the iterate
+// of its level over its tile plus a halo that other workgroups of the same launch
+// own, so it never writes the array it reads: down legs write u, up legs read u and
+// write ub, and a down leg that starts from a loaded iterate reads ub.
 struct LevelPtrs {
   void* u[kMaxLevels];
+  void* ub[kMaxLevels];
   void* f[kMaxLevels];
   void* cw[kMaxLevels];
   void* cs[kMaxLevels];
@@ -59,9 +64,9 @@ hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st);
 // of the cells the timed launches processed ([0]: zero initial iterate, [1]: loaded).
 struct KernelTimer {
   int which;      // 0: off, 1: down-leg smoother
-  hipEvent_t* ev; // 2 * cap events
-  int cap, used;  // event pairs recorded (since the last harvest, or into the captured graph)
-  bool in_graph;  // events belong to a graph: harvest after every replay, keep `used`
+  hipEvent_t* ev;      // ring of cap event pairs
+  int cap;
+  int64_t head, tail;  // pairs harvested / recorded so far (tail - head <= cap in flight)
   unsigned long long* d_cells;
   int64_t launches;
   double total_ms;

@@ -567,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   const TileLds<R> L = tile_carve<R>(smem, TW);
   R* U = (R*)pl.lv.u[l] + s * M2;
-  tile_load<R>(L, H, m, x0, y0, U, nullptr, 0, (const R*)pl.lv.f[l] + s * M2,
+  tile_load<R>(L, H, m, x0, y0, (const R*)pl.lv.ub[l] + s * M2, nullptr, 0, (const R*)pl.lv.f[l] + s * M2,
                (const R*)pl.lv.cw[l] + s * M2, (const R*)pl.lv.cs[l] + s * M2,
                (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m, u_zero != 0);
   __syncthreads();
@@ -608,8 +608,9 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
   const int tile = xcd_tile();
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   const TileLds<R> L = tile_carve<R>(smem, TW);
-  R* U = (R*)pl.lv.u[l] + s * M2;
-  tile_load<R>(L, H, m, x0, y0, U, (const R*)pl.lv.u[l + 1] + s * MC2, mc,
+  R* U = (R*)pl.lv.ub[l] + s * M2;
+  const R* UC = (const R*)(l + 1 == pl.ltop ? pl.lv.u[l + 1] : pl.lv.ub[l + 1]) + s * MC2;
+  tile_load<R>(L, H, m, x0, y0, (const R*)pl.lv.u[l] + s * M2, UC, mc,
                (const R*)pl.lv.f[l] + s * M2, (const R*)pl.lv.cw[l] + s * M2,
                (const R*)pl.lv.cs[l] + s * M2, (const R*)pl.lv.cdt[l] + s * M2,
                (const R*)pl.lv.ctop[l] + s * m, false);
@@ -789,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPla
 
 size_t level_bytes(int m, int64_t S, bool fp64) {
   const size_t es = fp64 ? 8 : 4;
-  return es * (size_t)S * (5 * (size_t)m * m + (size_t)m);
+  return es * (size_t)S * (6 * (size_t)m * m + (size_t)m);
 }
 
 hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
@@ -847,19 +848,20 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
       const int m = n >> l, ts = pl.ts[l];
       const unsigned tiles = (unsigned)((m / ts) * (m / ts));
       KernelTimer* tm = pl.timer;
-      const bool timed = tm && tm->which == 1 && tm->used < tm->cap;
+      const bool timed = tm && tm->which == 1 && tm->tail - tm->head < tm->cap;
+      const int q = timed ? (int)(tm->tail % tm->cap) : 0;
       StreamPlan plx = pl;
       plx.tcells = timed ? tm->d_cells : nullptr;
       if (timed) {
-        hipError_t e = hipEventRecord(tm->ev[2 * tm->used], st);
+        hipError_t e = hipEventRecord(tm->ev[2 * q], st);
         if (e != hipSuccess) return e;
       }
       launch_down<R>(ts, dim3(tiles, (unsigned)a.S), tile_lds(2 * a.nu1 + 1, ts, fp64), st, a, plx, l,
                      (l > 0 || cyc == 0) ? 1 : 0);
       if (timed) {
-        hipError_t e = hipEventRecord(tm->ev[2 * tm->used + 1], st);
+        hipError_t e = hipEventRecord(tm->ev[2 * q + 1], st);
         if (e != hipSuccess) return e;
-        ++tm->used;
+        ++tm->tail;
       }
     }
     hipLaunchKernelGGL(k_coarse_v<R>, dim3((unsigned)a.S), blk, lcv, st, a, pl,

@@ -111,15 +111,18 @@ def test_graph_replay_equals_eager_and_timing_is_transparent(precision):
     ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN)
     c = ctx.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision))
     t = ctx.kernel_timing()
+    f = ctx.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, flags=rmg.FLAG_EAGER))
     ctx.set_kernel_timing(_abi.TIME_NONE)
     torch.cuda.synchronize()
     d = ctx.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, flags=rmg.FLAG_NO_AUTOTUNE))
     e = ctx.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, flags=rmg.FLAG_TILES_16))
-    for o in (b, c, d, e):
+    for o in (b, c, d, e, f):
         assert torch.equal(a["h"], o["h"])
         assert (a["stats"]["picard_its"] == o["stats"]["picard_its"]).all()
-    # two streaming levels (128, 64) of down-leg launches per Picard iteration, every iteration timed
-    assert t["launches"] >= 2 * int(c["stats"]["picard_its"].max())
+    # two streaming levels (128, 64) of down-leg launches per Picard iteration; the first
+    # iteration of every batch of eight is timed
+    its = int(c["stats"]["picard_its"].max())
+    assert t["launches"] % 2 == 0 and 2 * (its // 8) <= t["launches"] <= 2 * (its // 8 + 4)
     assert t["total_ms"] > 0 and t["cells"] > 0
     es = 8 if precision == rmg.FP64 else 4
     assert abs(t["algo_bytes"] - 5.25 * es * t["cells"]) < 1e-6 * t["algo_bytes"]
