@@ -610,6 +610,7 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
   ar.base = (char*)ctx->ws;
   ar.cap = ctx->ws_cap;
   class_carve(j, ar);
+  if (ar.off > ar.cap) return fail(ctx, RMG_ENOMEM, "internal error: workspace accounting (%zu > %zu)", ar.off, ar.cap);
   HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
   HIP_TRY(ctx, hipStreamWaitEvent(j.stream, ctx->ev[0], 0));
   rc = run_classes(ctx, jobs, !(opts->flags & 2));
@@ -726,6 +727,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     class_carve(j, ar);
   }
   rmg_level_sums* d_sums = (rmg_level_sums*)ar.take(sizeof(rmg_level_sums) * n_levels);
+  if (ar.off > ar.cap) return fail(ctx, RMG_ENOMEM, "internal error: workspace accounting (%zu > %zu)", ar.off, ar.cap);
 
   // fields: both members of a pair draw from the same xi row through their own basis
   for (size_t c = 0; c < jobs.size(); ++c) {

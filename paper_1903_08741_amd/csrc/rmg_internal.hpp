@@ -53,6 +53,7 @@ struct SolveArgs {
   double* qoi;
   int32_t* status;
   rmg_sample_stats* stats;
+  int64_t s0;  // whole-sample kernel: first sample of the launch (launches cover chunks of S)
 };
 
 // LDS bytes of the whole-sample kernel for grid n (0 if it does not fit).

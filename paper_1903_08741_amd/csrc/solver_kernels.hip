@@ -27,13 +27,34 @@ __device__ __forceinline__ const rmg_problem& class_problem(const ClassProblems&
 // k < 2^16 and w < 2^16, floor(k / w) = umulhi(k, ceil(2^32 / w)) exactly (the
 // rounding error of the reciprocal, k (ceil(2^32/w) w - 2^32) / (w 2^32) < k / 2^32,
 // stays below 1/w).
+// (w = 1 has no 32-bit magic number: the table holds 0, which is right only for a
+// single-element loop; the loops below use w >= 2 whenever they have several rows.)
+// Widths up to kMagicMax come from a table (a 64-bit division per loop would cost
+// a software division routine on the scalar unit).
+constexpr int kMagicMax = 128;
+struct MagicTable {
+  unsigned v[kMagicMax + 1];
+  constexpr MagicTable() : v() {
+    for (int w = 1; w <= kMagicMax; ++w)
+      v[w] = (unsigned)((0x100000000ull + (unsigned long long)w - 1ull) / (unsigned long long)w);
+  }
+};
+__constant__ constexpr MagicTable kMagic{};
 __device__ __forceinline__ unsigned rmg_magic(int w) {
+  if (w >= 1 && w <= kMagicMax) return kMagic.v[w];
   return (unsigned)((0x100000000ull + (unsigned long long)w - 1ull) / (unsigned long long)w);
 }
 #define RMG_TILE_FOR(w, ri, rj)                                                                 \
   for (int w_ = (w), once_ = 1; once_; once_ = 0)                                                 \
     for (unsigned mg_ = rmg_magic(w_), once2_ = 1u; once2_; once2_ = 0u)                          \
       for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < w_ * w_; k_ += (int)blockDim.x)        \
+        if ((rj = (int)__umulhi((unsigned)k_, mg_), ri = k_ - rj * w_), true)
+
+// Flat loop over a rows x w index space, (ri, rj) = (k mod w, k / w).
+#define RMG_ROWS_FOR(rows, w, ri, rj)                                                            \
+  for (int w_ = (w), t_ = (rows) * w_, once_ = 1; once_; once_ = 0)                              \
+    for (unsigned mg_ = rmg_magic(w_), once2_ = 1u; once2_; once2_ = 0u)                          \
+      for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < t_; k_ += (int)blockDim.x)            \
         if ((rj = (int)__umulhi((unsigned)k_, mg_), ri = k_ - rj * w_), true)
 
 // Tile handled by this workgroup.  Workgroups are handed to the 8 XCDs round-robin
@@ -83,13 +104,24 @@ __host__ __device__ constexpr int whole_doubles(int NC) { return NC * (NC + 1) +
 #endif
 constexpr int kUnroll = RMG_WS_UNROLL;  // cells per thread whose global loads are issued together
 
+#ifndef RMG_WS_PER_CU
+#define RMG_WS_PER_CU 4
+#endif
+// Workgroups per compute unit one whole-sample launch covers at most (0: the
+// whole class in one launch); larger classes go out as consecutive launches on
+// one stream.  Whole-sample workgroups run for milliseconds, and a chip filled
+// with them starves the short level-streaming launches of the large grids that
+// run beside them.
+constexpr int kWsPerCu = RMG_WS_PER_CU;
+
+// One workgroup integrates sample a.s0 + blockIdx.x.
 // SL: the FP64 state (pressure head, old moisture content, fields) lives in LDS
 // for the whole integration and the pressure head is written back once at the end;
 // otherwise it stays in global memory and is read kUnroll cells at a time.
 template <class R, int NT, bool SL>
 __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t s = blockIdx.x;
+  const int64_t s = a.s0 + blockIdx.x;
   const rmg_problem P = class_problem(a.cp, s);
   const int n = a.n, lg = a.lg, F = a.F;
   const int N = n * n;
@@ -282,8 +314,25 @@ static hipError_t launch_ws(const SolveArgs& a, size_t lds, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_whole_sample<R, NT, SL>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_whole_sample<R, NT, SL>), dim3((unsigned)a.S), dim3(NT), lds, st, a);
-  return hipGetLastError();
+  int64_t chunk = a.S;
+  if (kWsPerCu > 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_whole_sample<R, NT, SL>, NT,
+                                                          lds)) != hipSuccess)
+      return e;
+    per_cu = per_cu < 1 ? 1 : (per_cu > kWsPerCu ? kWsPerCu : per_cu);
+    if ((int64_t)cus * per_cu < chunk) chunk = (int64_t)cus * per_cu;
+  }
+  for (int64_t s0 = 0; s0 < a.S; s0 += chunk) {
+    SolveArgs b = a;
+    b.s0 = s0;
+    const int64_t g = a.S - s0 < chunk ? a.S - s0 : chunk;
+    hipLaunchKernelGGL((k_whole_sample<R, NT, SL>), dim3((unsigned)g), dim3(NT), lds, st, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
@@ -301,6 +350,17 @@ hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
 }
 
 // ============================================================ level streaming
+#ifndef RMG_STREAM_PRIO
+#define RMG_STREAM_PRIO 3
+#endif
+// Waves of the per-iteration streaming kernels issue ahead of co-resident
+// whole-sample waves on the same SIMD: the streaming kernels form each large
+// grid's critical path of short dependent launches.
+#define RMG_RAISE_PRIORITY()                                           \
+  do {                                                                 \
+    if (RMG_STREAM_PRIO > 0) __builtin_amdgcn_s_setprio(RMG_STREAM_PRIO); \
+  } while (0)
+
 __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long long* dpmax) {
   const int64_t N = (int64_t)a.n * a.n;
   const int64_t tot = a.S * N;
@@ -331,6 +391,7 @@ __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long lon
 // 32 x 32 fine tile are complete for 2^l <= 32).
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
+  RMG_RAISE_PRIORITY();
   __shared__ double sp[34 * 34], sK[34 * 34];
   __shared__ R bufA[3 * 32 * 32 + 32], bufB[3 * 16 * 16 + 16];
   const int64_t s = blockIdx.y;
@@ -526,13 +587,16 @@ template <class R>
 __device__ void tile_half_sweep(const TileLds<R>& L, int H, int ts, int m, int x0, int y0, int grow,
                                 int colour) {
   const int TW = L.TW;
-  const int lo = H - grow, hi = H + ts + grow;
-  const int w = hi - lo;
-  RMG_TILE_FOR(w, ri, rj) {
-    const int li = lo + ri, lj = lo + rj;
-    const int gi = x0 - H + li, gj = y0 - H + lj;
-    if (gi < 0 || gi >= m || gj < 0 || gj >= m || ((gi + gj) & 1) != colour) continue;
-    const int e = lj * TW + li;
+  // window of the sweep in tile coordinates, clipped to the domain
+  const int li0 = max(H - grow, H - x0), li1 = min(H + ts + grow, H - x0 + m);
+  const int lj0 = max(H - grow, H - y0), lj1 = min(H + ts + grow, H - y0 + m);
+  const int W = li1 - li0, half = (W + 1) >> 1;
+  // cells of the colour only: row rj holds ri = 2q + par(rj), par alternating by row
+  const int base = (colour + (x0 - H + li0) + (y0 - H + lj0)) & 1;
+  RMG_ROWS_FOR(lj1 - lj0, half, q, rj) {
+    const int ri = 2 * q + ((base + rj) & 1);
+    if (ri >= W) continue;
+    const int e = (lj0 + rj) * TW + li0 + ri;
     L.u[e] = gs_value<R>(L.f[e], tile_st5(L, e));
   }
 }
@@ -555,6 +619,7 @@ __device__ TileLds<R> tile_carve(unsigned char* smem, int TW) {
 // output tiles (TS = 16 or 32, chosen per level by the autotuner).
 template <class R, int TS>
 __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero) {
+  RMG_RAISE_PRIORITY();
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.y;
   if (!pl.state[s].active) return;
@@ -597,6 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
 // finest level (final != 0) the Picard update p += dp and ||dp||_inf instead of a store.
 template <class R, int TS>
 __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final_) {
+  RMG_RAISE_PRIORITY();
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kBlock / 64];
   const int64_t s = blockIdx.y;
@@ -659,6 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero,
                                                      int final_) {
+  RMG_RAISE_PRIORITY();
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.x;
   if (!pl.state[s].active) return;
@@ -736,6 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
 
 // Per-sample stopping test and time-step bookkeeping after one Picard iteration.
 __global__ void k_control(SolveArgs a, StreamPlan pl) {
+  RMG_RAISE_PRIORITY();
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= a.S) return;
   SampleState st = pl.state[s];
