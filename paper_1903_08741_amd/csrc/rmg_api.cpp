@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,6 +22,11 @@
 using namespace rmg;
 
 constexpr int kTimerPairs = 4096;
+#ifndef RMG_WHOLE_MAX_N
+#define RMG_WHOLE_MAX_N 32
+#endif
+// Largest grid solved by the whole-sample kernel (one workgroup per sample).
+constexpr int kWholeMaxN = RMG_WHOLE_MAX_N;
 
 struct rmg_ctx {
   int device = 0;
@@ -178,13 +184,13 @@ void class_carve(ClassJob& j, Arena& ar) {
 void class_plan(ClassJob& j, const rmg_solver_opts* o) {
   j.fp64 = o->precision == RMG_FP64;
   const int n = j.a.n;
-  j.whole = !(o->flags & 1) && whole_sample_lds_bytes(n, o->coarsest_n, j.fp64, j.a.F, nullptr) > 0;
+  j.whole = !(o->flags & 1) && n <= kWholeMaxN && whole_sample_lds_bytes(n, o->coarsest_n, j.fp64, j.a.F, nullptr) > 0;
   j.a.state_global = (o->flags & 4) != 0;
   j.autotune = (o->flags & (8 | 16)) == 0;
   j.pl.n = n;
   j.pl.nlev = j.a.nlev;
   j.pl.fp64 = j.fp64;
-  j.pl.ltop = std::max(0, ilog2i(n) - ilog2i(kCoarseTop));
+  j.pl.ltop = std::max(0, ilog2i(n) - ilog2i(coarse_top(j.fp64)));
   for (int l = 0; l < kMaxLevels; ++l) j.pl.ts[l] = (o->flags & 16) ? 16 : kTile;
 }
 
@@ -336,7 +342,20 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     const int64_t steps = std::max(j.a.cp.prob[0].n_steps, j.a.cp.prob[1].n_steps);
     return steps * (int64_t)j.a.max_picard + (int64_t)(D + 1) * G;
   };
+#ifdef RMG_HOST_STATS
+  double host_issue_s = 0.0;
+  long n_issue = 0, n_poll = 0;
+#endif
   auto issue = [&](size_t c) -> hipError_t {
+#ifdef RMG_HOST_STATS
+    const auto t0_ = std::chrono::steady_clock::now();
+    struct Acc {
+      double& s;
+      std::chrono::steady_clock::time_point t;
+      ~Acc() { s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count(); }
+    } acc_{host_issue_s, t0_};
+    ++n_issue;
+#endif
     ClassJob& j = jobs[c];
     const int k = (int)(issued[c] % D);
     StreamPlan untimed = j.pl;
@@ -396,7 +415,13 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
       if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "iteration launch failed: %s", hipGetErrorString(e));
     }
     if (!progressed) std::this_thread::yield();
+#ifdef RMG_HOST_STATS
+    ++n_poll;
+#endif
   }
+#ifdef RMG_HOST_STATS
+  fprintf(stderr, "[rmg host] issues %ld, %.1f us each, polls %ld\n", n_issue, 1e6 * host_issue_s / (n_issue ? n_issue : 1), n_poll);
+#endif
   // leave nothing of this call running on an error; collect the last timed launches
   for (auto& j : jobs) {
     if (j.whole) continue;
@@ -741,18 +766,19 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
       row += v.n_samples;
     }
   }
-  // Every whole-sample class runs on side stream 0, one after the other; each
-  // streaming class gets a side stream of its own.  HIP multiplexes streams onto a
-  // few hardware queues (four by default, one taken by the caller's stream), and a
-  // streaming class whose stream shares a queue with a long whole-sample kernel
-  // cannot start its chain of short launches until that kernel ends.
+  // Every whole-sample class runs on the caller's stream, one after the other
+  // (ordered after the fields); each streaming class gets a side stream of its
+  // own, in creation order.  HIP multiplexes streams onto a few hardware queues
+  // (four by default), and a streaming class whose stream shares a queue with a
+  // long whole-sample kernel cannot start its chain of short launches until that
+  // kernel ends; the caller's stream is otherwise idle until the level sums.
   HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
-  int nside = 1;
+  int nside = 0;
   for (size_t c = 0; c < jobs.size(); ++c) {
     if (jobs[c].whole) {
-      jobs[c].stream = ctx->side[0];
+      jobs[c].stream = stream;
     } else {
-      if (nside == 7) return fail(ctx, RMG_EINVAL, "more than six level-streaming grid sizes");
+      if (nside == 7) return fail(ctx, RMG_EINVAL, "more than seven level-streaming grid sizes");
       jobs[c].stream = ctx->side[nside++];
     }
     jobs[c].h_count = ctx->h_count + 4 * (int)c;

@@ -172,6 +172,12 @@ template <class R>
 __device__ __forceinline__ R gs_value(R f, const St5<R>& s) {
   return (f + s.snb) / s.d;
 }
+// FP32 (the multigrid of the mixed-precision solver): multiply by the hardware
+// reciprocal (1 ulp) instead of the correctly rounded division sequence.
+template <>
+__device__ __forceinline__ float gs_value<float>(float f, const St5<float>& s) {
+  return (f + s.snb) * __builtin_amdgcn_rcpf(s.d);
+}
 // Residual f - A u of one cell.
 template <class R>
 __device__ __forceinline__ R residual_value(R f, R u, const St5<R>& s) {

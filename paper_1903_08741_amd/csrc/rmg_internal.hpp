@@ -10,7 +10,13 @@ namespace rmg {
 
 constexpr int kMaxLevels = 12;
 constexpr int kTile = 32;       // output tile edge of the level-streaming kernels
-constexpr int kCoarseTop = 32;  // streaming levels are those finer than this
+#ifndef RMG_COARSE_TOP_F32
+#define RMG_COARSE_TOP_F32 64
+#endif
+// Finest level of the one-workgroup-per-sample coarse V-cycle kernel; the
+// level-streaming kernels handle the finer levels.  Its LDS hierarchy must fit in
+// 160 KiB: 64 x 64 and below in FP32, 32 x 32 and below in FP64.
+constexpr int coarse_top(bool fp64) { return fp64 ? 32 : RMG_COARSE_TOP_F32; }
 
 // Per-sample iteration state of the level-streaming path (device memory).
 struct SampleState {

@@ -67,24 +67,25 @@ __device__ __forceinline__ int xcd_tile() {
 }
 
 // Mean effective saturation (theta - theta_r)/(theta_s - theta_r) over the cells.
-// The summation order is fixed independently of the block size (>= kQoiLanes):
-// lane t < kQoiLanes sums cells t, t + kQoiLanes, ..., then a fixed binary tree.
+// The summation order is fixed independently of the block size: lane t <
+// kQoiLanes sums cells t, t + kQoiLanes, ... (thread k computes lanes k, k + B,
+// ... for a block of B threads), then a fixed binary tree over the lanes.
 constexpr int kQoiLanes = 256;
 __device__ double mean_saturation(const rmg_problem& P, const double* fields, int F, int64_t N,
                                   int64_t s, const double* p, double* red) {
-  double acc = 0.0;
-  if (threadIdx.x < kQoiLanes) {
-    for (int64_t c = threadIdx.x; c < N; c += kQoiLanes) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < kQoiLanes; t += blockDim.x) {
+    double acc = 0.0;
+    for (int64_t c = t; c < N; c += kQoiLanes) {
       const CellFields cf = load_fields(fields, F, N, s, c);
       const Closure cl = closure(P, p[c], cf.Ks, cf.alpha, cf.nvg);
       acc += (cl.theta - P.theta_r) / (P.theta_s - P.theta_r);
     }
+    red[t] = acc;
   }
   __syncthreads();
-  if (threadIdx.x < kQoiLanes) red[threadIdx.x] = acc;
-  __syncthreads();
   for (int w = kQoiLanes >> 1; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+    for (int t = threadIdx.x; t < w; t += blockDim.x) red[t] = red[t] + red[t + w];
     __syncthreads();
   }
   const double r = red[0];
@@ -103,16 +104,6 @@ __host__ __device__ constexpr int whole_doubles(int NC) { return NC * (NC + 1) +
 #define RMG_WS_THREADS 512
 #endif
 constexpr int kUnroll = RMG_WS_UNROLL;  // cells per thread whose global loads are issued together
-
-#ifndef RMG_WS_PER_CU
-#define RMG_WS_PER_CU 4
-#endif
-// Workgroups per compute unit one whole-sample launch covers at most (0: the
-// whole class in one launch); larger classes go out as consecutive launches on
-// one stream.  Whole-sample workgroups run for milliseconds, and a chip filled
-// with them starves the short level-streaming launches of the large grids that
-// run beside them.
-constexpr int kWsPerCu = RMG_WS_PER_CU;
 
 // One workgroup integrates sample a.s0 + blockIdx.x.
 // SL: the FP64 state (pressure head, old moisture content, fields) lives in LDS
@@ -314,25 +305,33 @@ static hipError_t launch_ws(const SolveArgs& a, size_t lds, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_whole_sample<R, NT, SL>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  int64_t chunk = a.S;
-  if (kWsPerCu > 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_whole_sample<R, NT, SL>, NT,
-                                                          lds)) != hipSuccess)
-      return e;
-    per_cu = per_cu < 1 ? 1 : (per_cu > kWsPerCu ? kWsPerCu : per_cu);
-    if ((int64_t)cus * per_cu < chunk) chunk = (int64_t)cus * per_cu;
-  }
-  for (int64_t s0 = 0; s0 < a.S; s0 += chunk) {
+  // grid dimension x holds at most 2^31 - 1 workgroups: larger classes go out in parts
+  constexpr int64_t kMaxGrid = 1 << 30;
+  for (int64_t s0 = 0; s0 < a.S; s0 += kMaxGrid) {
     SolveArgs b = a;
     b.s0 = s0;
-    const int64_t g = a.S - s0 < chunk ? a.S - s0 : chunk;
+    const int64_t g = a.S - s0 < kMaxGrid ? a.S - s0 : kMaxGrid;
     hipLaunchKernelGGL((k_whole_sample<R, NT, SL>), dim3((unsigned)g), dim3(NT), lds, st, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+#ifndef RMG_WS_NT16
+#define RMG_WS_NT16 128
+#endif
+#ifndef RMG_WS_NT32
+#define RMG_WS_NT32 256
+#endif
+// Threads per whole-sample workgroup (state in LDS) for grids up to 16 x 16 and
+// 32 x 32.  The small-grid classes hold thousands of samples, so throughput is set
+// by how many samples a compute unit keeps in flight, and one or two waves per
+// sample turn most barriers into wave barriers.
+template <class R>
+static hipError_t launch_ws_sl(const SolveArgs& a, size_t lds, hipStream_t st) {
+  if (a.n <= 16) return launch_ws<R, RMG_WS_NT16, true>(a, lds, st);
+  if (a.n <= 32) return launch_ws<R, RMG_WS_NT32, true>(a, lds, st);
+  return launch_ws<R, 256, true>(a, lds, st);
 }
 
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
@@ -345,22 +344,11 @@ hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
     lds = ws_bytes(a.n, nc, fp64, a.F, false);
   }
   constexpr int T = RMG_WS_THREADS;
-  if (fp64) return sl ? launch_ws<double, 256, true>(a, lds, st) : launch_ws<double, T, false>(a, lds, st);
-  return sl ? launch_ws<float, 256, true>(a, lds, st) : launch_ws<float, T, false>(a, lds, st);
+  if (fp64) return sl ? launch_ws_sl<double>(a, lds, st) : launch_ws<double, T, false>(a, lds, st);
+  return sl ? launch_ws_sl<float>(a, lds, st) : launch_ws<float, T, false>(a, lds, st);
 }
 
 // ============================================================ level streaming
-#ifndef RMG_STREAM_PRIO
-#define RMG_STREAM_PRIO 3
-#endif
-// Waves of the per-iteration streaming kernels issue ahead of co-resident
-// whole-sample waves on the same SIMD: the streaming kernels form each large
-// grid's critical path of short dependent launches.
-#define RMG_RAISE_PRIORITY()                                           \
-  do {                                                                 \
-    if (RMG_STREAM_PRIO > 0) __builtin_amdgcn_s_setprio(RMG_STREAM_PRIO); \
-  } while (0)
-
 __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long long* dpmax) {
   const int64_t N = (int64_t)a.n * a.n;
   const int64_t tot = a.S * N;
@@ -391,7 +379,6 @@ __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long lon
 // 32 x 32 fine tile are complete for 2^l <= 32).
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
-  RMG_RAISE_PRIORITY();
   __shared__ double sp[34 * 34], sK[34 * 34];
   __shared__ R bufA[3 * 32 * 32 + 32], bufB[3 * 16 * 16 + 16];
   const int64_t s = blockIdx.y;
@@ -590,14 +577,24 @@ __device__ void tile_half_sweep(const TileLds<R>& L, int H, int ts, int m, int x
   // window of the sweep in tile coordinates, clipped to the domain
   const int li0 = max(H - grow, H - x0), li1 = min(H + ts + grow, H - x0 + m);
   const int lj0 = max(H - grow, H - y0), lj1 = min(H + ts + grow, H - y0 + m);
-  const int W = li1 - li0, half = (W + 1) >> 1;
-  // cells of the colour only: row rj holds ri = 2q + par(rj), par alternating by row
-  const int base = (colour + (x0 - H + li0) + (y0 - H + lj0)) & 1;
-  RMG_ROWS_FOR(lj1 - lj0, half, q, rj) {
-    const int ri = 2 * q + ((base + rj) & 1);
-    if (ri >= W) continue;
-    const int e = (lj0 + rj) * TW + li0 + ri;
-    L.u[e] = gs_value<R>(L.f[e], tile_st5(L, e));
+  const int W = li1 - li0, rows = lj1 - lj0, half = (W + 1) >> 1;
+  // Cells of the colour only: row rj holds ri = 2q + par(rj), q < half, with the
+  // parity alternating by row.  Thread t keeps column q = t mod half and walks rows
+  // r0 = t / half, r0 + rp, ... (rp = rows covered per pass), so the loop carries
+  // one address increment instead of a division per cell.
+  const unsigned mg = rmg_magic(half);
+  const int rp = (int)__umulhi((unsigned)kBlock, mg);
+  const int t = (int)threadIdx.x;
+  const int r0 = (int)__umulhi((unsigned)t, mg);
+  if (r0 >= rp) return;
+  const int q = t - r0 * half;
+  int par = (colour + (x0 - H + li0) + (y0 - H + lj0) + r0) & 1;
+  const int flip = rp & 1, step = rp * TW;
+  int e = (lj0 + r0) * TW + li0 + 2 * q;
+  for (int rj = r0; rj < rows; rj += rp, e += step, par ^= flip) {
+    if (2 * q + par >= W) continue;
+    const int c = e + par;
+    L.u[c] = gs_value<R>(L.f[c], tile_st5(L, c));
   }
 }
 
@@ -619,7 +616,6 @@ __device__ TileLds<R> tile_carve(unsigned char* smem, int TW) {
 // output tiles (TS = 16 or 32, chosen per level by the autotuner).
 template <class R, int TS>
 __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero) {
-  RMG_RAISE_PRIORITY();
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.y;
   if (!pl.state[s].active) return;
@@ -662,7 +658,6 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
 // finest level (final != 0) the Picard update p += dp and ||dp||_inf instead of a store.
 template <class R, int TS>
 __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final_) {
-  RMG_RAISE_PRIORITY();
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kBlock / 64];
   const int64_t s = blockIdx.y;
@@ -722,10 +717,20 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
 
 // Levels ltop .. nlev-1 of one sample in LDS: load level ltop, coarsen, V-cycle,
 // store its correction (or, when ltop is the finest level, apply the Picard update).
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero,
-                                                     int final_) {
-  RMG_RAISE_PRIORITY();
+#ifndef RMG_COARSE_THREADS
+#define RMG_COARSE_THREADS 512
+#endif
+// One wave per sample: the coarse V-cycle is a long chain of small sweeps, and
+// with a single-wave workgroup every __syncthreads() compiles to a wave barrier
+// (the backend drops s_barrier when the workgroup fits one wave).
+constexpr int kCoarseThreads = RMG_COARSE_THREADS;
+// 16-byte vectors for the global loads and stores of the coarse kernel.
+template <class R> struct Vec16;
+template <> struct Vec16<float> { using T = float4; };
+template <> struct Vec16<double> { using T = double2; };
+
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero, int final_) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.x;
   if (!pl.state[s].active) return;
@@ -733,48 +738,60 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
   const int m = a.n >> lt;
   const int nlev = a.nlev - lt;
   const int mc = a.n >> (a.nlev - 1), NC = mc * mc;
-  const int64_t M2 = (int64_t)m * m;
+  const int M2 = m * m;
   RMG_LDS double* A = (RMG_LDS double*)smem;
   RMG_LDS double* ipiv = A + NC * (NC + 1);
   double* red = (double*)(ipiv + 16);
-  R* rbase = (R*)(red + kBlock / 64);
+  R* rbase = (R*)(red + NT / 64 + 1);
   __shared__ LdsLevel<R> lev[kMaxLevels];
   R* rend = lds_carve(rbase, lev, m, nlev);
-  for (R* q = rbase + threadIdx.x; q < rend; q += blockDim.x) *q = (R)0;
+  for (R* q = rbase + threadIdx.x; q < rend; q += NT) *q = (R)0;
   __syncthreads();
   const LdsLevel<R>& T = lev[0];
-  const R* F = (const R*)pl.lv.f[lt] + s * M2;
-  const R* CW = (const R*)pl.lv.cw[lt] + s * M2;
-  const R* CS = (const R*)pl.lv.cs[lt] + s * M2;
-  const R* CDT = (const R*)pl.lv.cdt[lt] + s * M2;
+  using V = typename Vec16<R>::T;
+  constexpr int E = 16 / sizeof(R);  // elements per vector; M2 is a multiple of E
+  const V* F = (const V*)((const R*)pl.lv.f[lt] + s * M2);
+  const V* CW = (const V*)((const R*)pl.lv.cw[lt] + s * M2);
+  const V* CS = (const V*)((const R*)pl.lv.cs[lt] + s * M2);
+  const V* CDT = (const V*)((const R*)pl.lv.cdt[lt] + s * M2);
   const R* CT = (const R*)pl.lv.ctop[lt] + s * m;
   R* U = (R*)pl.lv.u[lt] + s * M2;
-  for (int c0 = threadIdx.x; c0 < M2; c0 += 4 * (int)blockDim.x) {
-    R f[4], cw[4], cs[4], cdt[4], u[4];
+  const int nv = M2 / E;
+  constexpr int VB = 4;  // vectors per array and lane whose loads are in flight together
+  for (int v0 = threadIdx.x; v0 < nv; v0 += VB * NT) {
+    V f[VB], cw[VB], cs[VB], cdt[VB], u[VB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + q * (int)blockDim.x;
-      if (c < M2) {
-        f[q] = F[c];
-        cw[q] = CW[c];
-        cs[q] = CS[c];
-        cdt[q] = CDT[c];
-        u[q] = u_zero ? (R)0 : U[c];
+    for (int q = 0; q < VB; ++q) {
+      const int v = v0 + q * NT;
+      if (v < nv) {
+        f[q] = F[v];
+        cw[q] = CW[v];
+        cs[q] = CS[v];
+        cdt[q] = CDT[v];
+        if (!u_zero) u[q] = ((const V*)U)[v];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + q * (int)blockDim.x;
-      if (c < M2) {
-        T.f[c] = f[q];
-        T.cw[c] = cw[q];
-        T.cs[c] = cs[q];
-        T.cdt[c] = cdt[q];
-        T.u[c] = u[q];
+    for (int q = 0; q < VB; ++q) {
+      const int v = v0 + q * NT;
+      if (v >= nv) continue;
+      const R* fe = (const R*)&f[q];
+      const R* cwe = (const R*)&cw[q];
+      const R* cse = (const R*)&cs[q];
+      const R* cde = (const R*)&cdt[q];
+      const R* ue = (const R*)&u[q];
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int c = v * E + k;
+        T.f[c] = fe[k];
+        T.cw[c] = cwe[k];
+        T.cs[c] = cse[k];
+        T.cdt[c] = cde[k];
+        T.u[c] = u_zero ? (R)0 : ue[k];
       }
     }
   }
-  for (int i = threadIdx.x; i < m; i += blockDim.x) T.cs[M2 + i] = CT[i];
+  for (int i = threadIdx.x; i < m; i += NT) T.cs[M2 + i] = CT[i];
   __syncthreads();
   for (int l = 0; l + 1 < nlev; ++l) {
     lds_coarsen(lev[l], lev[l + 1]);
@@ -782,12 +799,18 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
   }
   lds_vcycle(lev, 0, nlev, a.nu1, a.nu2, A, ipiv, u_zero != 0);
   if (lt > 0 || !final_) {
-    for (int c = threadIdx.x; c < M2; c += blockDim.x) U[c] = T.u[c];
+    for (int v = threadIdx.x; v < nv; v += NT) {
+      V o;
+      R* oe = (R*)&o;
+#pragma unroll
+      for (int k = 0; k < E; ++k) oe[k] = T.u[v * E + k];
+      ((V*)U)[v] = o;
+    }
     return;
   }
   double* p = a.p + s * M2;
   double mx = 0.0, bad = 0.0;
-  for (int c = threadIdx.x; c < M2; c += blockDim.x) {
+  for (int c = threadIdx.x; c < M2; c += NT) {
     const double d = (double)T.u[c];
     p[c] += d;
     mx = fmax(mx, fabs(d));
@@ -803,7 +826,6 @@ __global__ __launch_bounds__(kBlock) void k_coarse_v(SolveArgs a, StreamPlan pl,
 
 // Per-sample stopping test and time-step bookkeeping after one Picard iteration.
 __global__ void k_control(SolveArgs a, StreamPlan pl) {
-  RMG_RAISE_PRIORITY();
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= a.S) return;
   SampleState st = pl.state[s];
@@ -878,7 +900,7 @@ static size_t coarse_lds(int m, int nc, bool fp64) {
   size_t relems = 0;
   for (int mm = m; mm >= nc; mm >>= 1) relems += lds_level_elems(mm);
   const size_t NC = (size_t)nc * nc;
-  return 8 * (NC * (NC + 1) + 16 + kBlock / 64) + relems * (fp64 ? 8 : 4);
+  return 8 * (NC * (NC + 1) + 16 + kCoarseThreads / 64 + 1) + relems * (fp64 ? 8 : 4);
 }
 
 template <class R>
@@ -932,7 +954,7 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
         ++tm->tail;
       }
     }
-    hipLaunchKernelGGL(k_coarse_v<R>, dim3((unsigned)a.S), blk, lcv, st, a, pl,
+    hipLaunchKernelGGL((k_coarse_v<R, kCoarseThreads>), dim3((unsigned)a.S), dim3(kCoarseThreads), lcv, st, a, pl,
                        (pl.ltop > 0 || cyc == 0) ? 1 : 0, (cyc == a.cpp - 1) ? 1 : 0);
     for (int l = pl.ltop - 1; l >= 0; --l) {
       const int m = n >> l, ts = pl.ts[l];
@@ -962,7 +984,7 @@ static hipError_t set_stream_lds(const SolveArgs& a, const StreamPlan& pl) {
     e = hipFuncSetAttribute((const void*)k_up<R, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)tile_lds(hu, 32, fp64));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_coarse_v<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void*)k_coarse_v<R, kCoarseThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)coarse_lds(a.n >> pl.ltop, nc, fp64));
   return e;
 }

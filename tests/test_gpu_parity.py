@@ -119,10 +119,12 @@ def test_graph_replay_equals_eager_and_timing_is_transparent(precision):
     for o in (b, c, d, e, f):
         assert torch.equal(a["h"], o["h"])
         assert (a["stats"]["picard_its"] == o["stats"]["picard_its"]).all()
-    # two streaming levels (128, 64) of down-leg launches per Picard iteration; the first
-    # iteration of every batch of eight is timed
+    # one or two streaming levels (the coarse kernel starts at 64^2 in FP32, at 32^2 in
+    # FP64) of down-leg launches per Picard iteration; the first iteration of every
+    # batch of eight is timed
     its = int(c["stats"]["picard_its"].max())
-    assert t["launches"] % 2 == 0 and 2 * (its // 8) <= t["launches"] <= 2 * (its // 8 + 4)
+    k = 2 if precision == rmg.FP64 else 1
+    assert t["launches"] % k == 0 and k * (its // 8) <= t["launches"] <= k * (its // 8 + 4)
     assert t["total_ms"] > 0 and t["cells"] > 0
     es = 8 if precision == rmg.FP64 else 4
     assert abs(t["algo_bytes"] - 5.25 * es * t["cells"]) < 1e-6 * t["algo_bytes"]
