@@ -29,6 +29,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_down_mlmc5_mixed.md")
+KERNEL_SOURCES = ["solver_kernels.hip", "rmg_device.hpp", "rmg_lds.hpp", "rmg_internal.hpp"]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1903_08741_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per k_down launch from the committed PMC profile (FETCH_SIZE and WRITE_SIZE,
+    each scaled by a plain copy's reading), or None when the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            lines = [ln for ln in fh if ln.startswith("traffic-record:")]
+    except OSError:
+        return None
+    if not lines:
+        return None
+    rec = dict(kv.split("=", 1) for kv in lines[-1].split()[1:])
+    if rec.get("source_digest") != kernel_source_digest():
+        return None
+    return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+
+
 def build_levels(torch, rmg, W, precision, dev, max_picard):
     from paper_1903_08741_amd import kl_setup
     cfg = W.MLMC_5LEVEL
@@ -180,7 +209,7 @@ def main():
     picard = sum(s["picard_its"] for s in sums)
     gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "frac": gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(),
             "kernel": "k_down (nu1 fused red-black sweeps + residual + restriction, level-streaming path)",
             "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
             "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
