@@ -85,6 +85,83 @@ def n_solves(levels):
     return sum(lv["xi"].shape[0] * (2 if lv["n_coarse"] else 1) for lv in levels)
 
 
+# ------------------------------------------------------- supplementary figures
+def grid_classes(levels):
+    """Per grid size: the xi rows and basis of every solve on it (fine members of level l,
+    coarse members of level l + 1), as the batched call groups them."""
+    out = {}
+    for l, lv in enumerate(levels):
+        out.setdefault(lv["n_fine"], {"basis": lv["basis_fine"], "xi": []})["xi"].append(lv["xi"])
+        if lv["n_coarse"]:
+            out.setdefault(lv["n_coarse"], {"basis": lv["basis_coarse"], "xi": []})["xi"].append(lv["xi"])
+    return out
+
+
+def per_grid(torch, rmg, ctx, levels, opts, marg):
+    """Each grid's solves alone (one picard_mg_solve call per grid, after one untimed call)."""
+    res = {}
+    prob = levels[0]["fine"]
+    for n, c in sorted(grid_classes(levels).items()):
+        xi = torch.cat(c["xi"]).contiguous()
+        fields = ctx.sample_fields(n, c["basis"], xi, marg)
+        ctx.picard_mg_solve(n, fields, prob, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.picard_mg_solve(n, fields, prob, opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = out["stats"]["picard_its"]
+        ok = int((out["status"] == 0).sum().item())
+        res[str(n)] = {"solves": int(xi.shape[0]), "converged": ok, "ms": 1e3 * dt,
+                       "solves_per_s": xi.shape[0] / dt, "max_picard_its": int(its.max()),
+                       "cell_iterations_per_s": float(its.sum()) * n * n / dt}
+        log(f"grid {n}: {1e3 * dt:.1f} ms, max Picard its {int(its.max())}")
+    return res
+
+
+def fp64_path(torch, rmg, ctx, levels, marg, max_picard, cycles, steps=2):
+    """The same workload with the multigrid in FP64 too (1 untimed call, `steps` timed)."""
+    opts = rmg.SolverOpts(precision=rmg.FP64, max_picard=max_picard, cycles_per_picard=cycles)
+    ctx.mlmc_level_estimate(levels, marg, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sums, _, _ = ctx.mlmc_level_estimate(levels, marg, opts)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    failed = sum(s["n_failed"] for s in sums)
+    log(f"fp64 path: {ms:.1f} ms per step, failed pairs {failed}")
+    return ms, failed
+
+
+def large_batch_roofline(torch, rmg, ctx, W, levels, marg):
+    """The down-leg smoother on a batch large enough to stream from HBM: 64 samples of a
+    512 x 512 grid (16.8 M cells, FP32 multigrid arrays ~0.5 GB), 64 Picard iterations of
+    one step.  Fields: the 256^2 KL fields of the first 64 draws of the roofline workload,
+    each cell repeated on a 2 x 2 block."""
+    from paper_1903_08741_amd import _abi
+    cfg = W.SMOOTHER_ROOF
+    n, S = cfg["n"], cfg["n_samples"]
+    c = grid_classes(levels)[n // 2]
+    xi = torch.from_numpy(W.xi_draws(cfg["workload_id"], 0, range(S), 1, W.KS_FIELD["n_modes"])).to(c["basis"].device)
+    f2 = ctx.sample_fields(n // 2, c["basis"], xi, marg).view(S, 1, n // 2, n // 2)
+    fields = f2.repeat_interleave(2, dim=2).repeat_interleave(2, dim=3).reshape(S, 1, n * n).contiguous()
+    prob = rmg.Problem(n_steps=1)
+    opts = rmg.SolverOpts(precision=rmg.MIXED, max_picard=64)
+    ctx.picard_mg_solve(n, fields, prob, opts)
+    ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN)
+    torch.cuda.synchronize()
+    ctx.picard_mg_solve(n, fields, prob, opts)
+    kt = ctx.kernel_timing()
+    ctx.set_kernel_timing(_abi.TIME_NONE)
+    gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
+    log(f"large-batch smoother: {gbs:.0f} GB/s over {kt['launches']} timed launches")
+    return {"workload": f"{S} samples of {n}^2, 64 Picard iterations, mixed precision", "bound": "hbm",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
+            "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
+
+
 # ----------------------------------------------------------------- CPU baseline
 def _oracle_job(args):
     """One oracle solve (twin mode: the same Picard / V-cycle iteration) of a workload sample."""
@@ -165,6 +242,8 @@ def main():
     ap.add_argument("--max-picard", type=int, default=500)
     ap.add_argument("--cycles", type=int, default=1, help="V(2,2) cycles per Picard iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-grid, FP64-path and large-batch figures (outside the timed region)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sample-parallel "
@@ -213,6 +292,13 @@ def main():
             "kernel": "k_down (nu1 fused red-black sweeps + residual + restriction, level-streaming path)",
             "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
             "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
+    extras = {}
+    if not args.no_extras:
+        extras["per_grid"] = per_grid(torch, rmg, ctx, levels, opts, marg)
+        if precision == rmg.MIXED:
+            fms, ffail = fp64_path(torch, rmg, ctx, levels, marg, args.max_picard, args.cycles)
+            extras["fp64_path"] = {"ms_per_step": fms, "failed_pairs": ffail, "mixed_speedup": fms / ms}
+        extras["roofline_large_batch"] = large_batch_roofline(torch, rmg, ctx, W, levels, marg)
     cpu = None
     if not args.no_cpu_baseline:
         t1 = time.time()
@@ -240,6 +326,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 
