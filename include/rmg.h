@@ -104,7 +104,11 @@ typedef struct {
                                  even where it would fit in LDS (results are identical);
                                  bit 3: no autotuning of the streaming tile shapes (32 x 32
                                  tiles on every level; results are identical);
-                                 bit 4: 16 x 16 streaming tiles on every level, no autotuning */
+                                 bit 4: 16 x 16 streaming tiles on every level, no autotuning;
+                                 bit 5: use the whole-sample kernel on every grid whose levels fit in
+                                 LDS (64 x 64 in FP32), not only up to 32 x 32;
+                                 bit 6: start the one-workgroup coarse V-cycle at 32 x 32 in FP32
+                                 too (more level-streaming levels; results are identical) */
   double eps_mg;              /* reserved for a residual-controlled cycle count (ignored) */
   double eps_picard;          /* stop when ||dp||_inf < eps_picard (strict) */
 } rmg_solver_opts;

@@ -22,6 +22,8 @@ FLAG_EAGER = 2
 FLAG_STATE_GLOBAL = 4
 FLAG_NO_AUTOTUNE = 8
 FLAG_TILES_16 = 16
+FLAG_WHOLE_WHERE_FITS = 32
+FLAG_COARSE_TOP_32 = 64
 
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
             "sample_fields", "picard_mg_solve", "mlmc_level_estimate", "rmg_set_kernel_timing",

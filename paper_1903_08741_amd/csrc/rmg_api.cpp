@@ -184,13 +184,14 @@ void class_carve(ClassJob& j, Arena& ar) {
 void class_plan(ClassJob& j, const rmg_solver_opts* o) {
   j.fp64 = o->precision == RMG_FP64;
   const int n = j.a.n;
-  j.whole = !(o->flags & 1) && n <= kWholeMaxN && whole_sample_lds_bytes(n, o->coarsest_n, j.fp64, j.a.F, nullptr) > 0;
+  j.whole = !(o->flags & 1) && (n <= kWholeMaxN || (o->flags & 32)) &&
+            whole_sample_lds_bytes(n, o->coarsest_n, j.fp64, j.a.F, nullptr) > 0;
   j.a.state_global = (o->flags & 4) != 0;
   j.autotune = (o->flags & (8 | 16)) == 0;
   j.pl.n = n;
   j.pl.nlev = j.a.nlev;
   j.pl.fp64 = j.fp64;
-  j.pl.ltop = std::max(0, ilog2i(n) - ilog2i(coarse_top(j.fp64)));
+  j.pl.ltop = std::max(0, ilog2i(n) - ilog2i((o->flags & 64) ? 32 : coarse_top(j.fp64)));
   for (int l = 0; l < kMaxLevels; ++l) j.pl.ts[l] = (o->flags & 16) ? 16 : kTile;
 }
 

@@ -74,19 +74,32 @@ def test_plain_mc_32_matches_twin_oracle(precision, tol):
         assert st["steps_done"][s] == 10
 
 
+STREAMING_VARIANTS = {
+    "coarse-kernel-only": rmg.FLAG_FORCE_STREAMING,
+    "streaming-levels": rmg.FLAG_FORCE_STREAMING | rmg.FLAG_COARSE_TOP_32,
+    "streaming-levels-tiles16": rmg.FLAG_FORCE_STREAMING | rmg.FLAG_COARSE_TOP_32 | rmg.FLAG_TILES_16,
+}
+
+
+@pytest.mark.parametrize("variant", sorted(STREAMING_VARIANTS))
 @pytest.mark.parametrize("n", [4, 8, 16, 32, 64])
 @pytest.mark.parametrize("precision", [rmg.FP64, rmg.MIXED])
-def test_streaming_equals_whole_sample_bitwise(n, precision):
-    whole_ok = not (precision == rmg.FP64 and n == 64)
-    if not whole_ok:
+def test_streaming_equals_whole_sample_bitwise(n, precision, variant):
+    """The level-streaming path (tile kernels on the levels finer than the coarse kernel's
+    top, one-workgroup coarse V-cycle below) and the whole-sample LDS kernel compute the
+    same iterates bit for bit."""
+    if precision == rmg.FP64 and n == 64:
         pytest.skip("FP64 64x64 does not fit the whole-sample LDS kernel")
+    flags = STREAMING_VARIANTS[variant]
+    if flags & rmg.FLAG_COARSE_TOP_32 and n <= 32:
+        pytest.skip("no level finer than 32x32 to stream")
     S = 5
-    say(f"streaming vs whole-sample n={n} precision={precision}")
+    say(f"streaming vs whole-sample n={n} precision={precision} variant={variant}")
     _, _, fields = _fields(n, S, wid=4)
     prob = rmg.Problem(n_steps=3)
-    a = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, max_picard=300))
-    b = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, max_picard=300,
-                                                            flags=rmg.FLAG_FORCE_STREAMING))
+    a = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, max_picard=300,
+                                                            flags=rmg.FLAG_WHOLE_WHERE_FITS))
+    b = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, max_picard=300, flags=flags))
     torch.cuda.synchronize()
     assert torch.equal(a["h"], b["h"])
     assert torch.equal(a["status"], b["status"])
