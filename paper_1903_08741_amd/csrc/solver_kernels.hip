@@ -705,8 +705,11 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.y;
   if (!pl.state[s].active) return;
-  if (pl.tcells && threadIdx.x == 0) atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)(TS * TS));
   const int m = a.n >> l, mc = m >> 1;
+  // timed launches count the cells they process: once per active sample (one
+  // counter update per workgroup would serialise thousands of atomics on one address)
+  if (pl.tcells && blockIdx.x == 0 && threadIdx.x == 0)
+    atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)m * (unsigned long long)m);
   const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
   const int ntx = m / TS;
   const int tile = xcd_tile();
