@@ -30,7 +30,7 @@ def log(*a):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_down_mlmc5_mixed.md")
-KERNEL_SOURCES = ["solver_kernels.hip", "rmg_device.hpp", "rmg_lds.hpp", "rmg_internal.hpp"]
+KERNEL_SOURCES = ["rmg_smoother.hpp", "rmg_device.hpp", "rmg_internal.hpp"]
 
 
 def kernel_source_digest():
@@ -242,6 +242,9 @@ def main():
     ap.add_argument("--max-picard", type=int, default=500)
     ap.add_argument("--cycles", type=int, default=1, help="V(2,2) cycles per Picard iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="32 x 32 streaming tiles on every level (profiling runs: timing under a counter "
+                         "profiler is distorted, so an autotuner could pick other tiles there)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-grid, FP64-path and large-batch figures (outside the timed region)")
     args = ap.parse_args()
@@ -258,6 +261,8 @@ def main():
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
     levels, opts, marg = build_levels(torch, rmg, W, precision, dev, args.max_picard)
     opts.cycles_per_picard = args.cycles
+    if args.no_autotune:
+        opts.flags |= rmg.FLAG_NO_AUTOTUNE
     ctx = rmg.default_context(0)
     total = n_solves(levels)
     sums = None

@@ -219,9 +219,12 @@ int autotune_class(rmg_ctx* ctx, ClassJob& j) {
   }
   KernelTimer* saved = j.pl.timer;
   j.pl.timer = nullptr;
+  // The first candidate is the default; another one replaces it only when it is
+  // at least 5 % faster, so that timing noise does not flip the choice from run to run.
   const int cand[4][2] = {{32, 32}, {32, 16}, {16, 16}, {16, 32}};
   float best = 1e30f;
   int b0 = kTile, b1 = kTile;
+  bool first = true;
   for (auto& c : cand) {
     set_tiles(j, c[0], c[1]);
     HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
@@ -232,6 +235,8 @@ int autotune_class(rmg_ctx* ctx, ClassJob& j) {
     HIP_TRY(ctx, hipEventSynchronize(ctx->tev[1]));
     float ms = 0.f;
     HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->tev[0], ctx->tev[1]));
+    if (first) ms = ms * 0.95f;
+    first = false;
     if (ms < best) {
       best = ms;
       b0 = c[0];

@@ -16,10 +16,6 @@
 
 namespace rmg {
 
-// Pointers into LDS carry address space 3 in their type, so that every access is
-// a ds_read/ds_write even when the pointer itself was stored and reloaded (a
-// generic pointer would compile to the slower flat instructions).
-#define RMG_LDS __attribute__((address_space(3)))
 
 template <class R>
 struct LdsLevel {

@@ -3,19 +3,20 @@
 // Two execution shapes share the per-cell arithmetic of rmg_device.hpp and
 // therefore produce bit-identical iterates:
 //   * whole-sample kernel: one workgroup owns one sample for its whole time
-//     integration; every multigrid level lives in LDS (n <= 64 in FP32,
-//     n <= 32 in FP64), the FP64 state p, theta_old, fields stay in global memory;
+//     integration; every multigrid level lives in LDS (used up to 32 x 32, where
+//     the FP64 state p, theta_old and the fields live in LDS as well);
 //   * level-streaming kernels: one launch per phase of a Picard iteration over
-//     all samples of a grid size, 32 x 32 output tiles staged in LDS with a halo
-//     wide enough to fuse nu red-black sweeps with the residual/restriction
-//     (down leg) or with the prolongation (up leg); levels of 32 x 32 and
-//     coarser are handled by one workgroup per sample in LDS.
+//     all samples of a grid size: the fine residual (k_fine), the down and up
+//     legs of the levels finer than the coarse kernel's top (rmg_smoother.hpp),
+//     the one-workgroup-per-sample coarse V-cycle in LDS (k_coarse_v) and the
+//     per-sample control (k_control).
 // Section 4.1 (modified Picard) and Section 4.2 (cell-centred multigrid).
 #include <math.h>
 
 #include "rmg_device.hpp"
 #include "rmg_internal.hpp"
 #include "rmg_lds.hpp"
+#include "rmg_smoother.hpp"
 
 namespace rmg {
 
@@ -23,48 +24,11 @@ __device__ __forceinline__ const rmg_problem& class_problem(const ClassProblems&
   return s < cp.seg_split ? cp.prob[0] : cp.prob[1];
 }
 
-// Flat traversal of a w x w region of a tile without integer division: for
-// k < 2^16 and w < 2^16, floor(k / w) = umulhi(k, ceil(2^32 / w)) exactly (the
-// rounding error of the reciprocal, k (ceil(2^32/w) w - 2^32) / (w 2^32) < k / 2^32,
-// stays below 1/w).
-// (w = 1 has no 32-bit magic number: the table holds 0, which is right only for a
-// single-element loop; the loops below use w >= 2 whenever they have several rows.)
-// Widths up to kMagicMax come from a table (a 64-bit division per loop would cost
-// a software division routine on the scalar unit).
-constexpr int kMagicMax = 128;
-struct MagicTable {
-  unsigned v[kMagicMax + 1];
-  constexpr MagicTable() : v() {
-    for (int w = 1; w <= kMagicMax; ++w)
-      v[w] = (unsigned)((0x100000000ull + (unsigned long long)w - 1ull) / (unsigned long long)w);
-  }
-};
-__constant__ constexpr MagicTable kMagic{};
-__device__ __forceinline__ unsigned rmg_magic(int w) {
-  if (w >= 1 && w <= kMagicMax) return kMagic.v[w];
-  return (unsigned)((0x100000000ull + (unsigned long long)w - 1ull) / (unsigned long long)w);
-}
 #define RMG_TILE_FOR(w, ri, rj)                                                                 \
   for (int w_ = (w), once_ = 1; once_; once_ = 0)                                                 \
     for (unsigned mg_ = rmg_magic(w_), once2_ = 1u; once2_; once2_ = 0u)                          \
       for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < w_ * w_; k_ += (int)blockDim.x)        \
         if ((rj = (int)__umulhi((unsigned)k_, mg_), ri = k_ - rj * w_), true)
-
-// Flat loop over a rows x w index space, (ri, rj) = (k mod w, k / w).
-#define RMG_ROWS_FOR(rows, w, ri, rj)                                                            \
-  for (int w_ = (w), t_ = (rows) * w_, once_ = 1; once_; once_ = 0)                              \
-    for (unsigned mg_ = rmg_magic(w_), once2_ = 1u; once2_; once2_ = 0u)                          \
-      for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < t_; k_ += (int)blockDim.x)            \
-        if ((rj = (int)__umulhi((unsigned)k_, mg_), ri = k_ - rj * w_), true)
-
-// Tile handled by this workgroup.  Workgroups are handed to the 8 XCDs round-robin
-// by linear id; when the tile count is a multiple of 8 the tiles are renumbered so
-// that each XCD receives a contiguous band of tiles and the halos its workgroups
-// share stay in that XCD's L2.
-__device__ __forceinline__ int xcd_tile() {
-  const int g = gridDim.x, b = blockIdx.x;
-  return (g & 7) ? b : (b & 7) * (g >> 3) + (b >> 3);
-}
 
 // Mean effective saturation (theta - theta_r)/(theta_s - theta_r) over the cells.
 // The summation order is fixed independently of the block size: lane t <
@@ -509,323 +473,6 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
     src = dst;
     dst = tmp;
     t = tc;
-  }
-}
-
-// ------------------------------------------------------------ streaming smoother
-// A down or up kernel works on a TS x TS output tile of one level plus a halo,
-// both made of 2 x 2 cell blocks aligned with the coarse grid.  Each thread owns
-// whole blocks for the whole kernel and keeps their right-hand side, face
-// coefficients, diagonal and iterate in registers; LDS mirrors only the iterate,
-// for the neighbours.  A red-black update of a block cell then reads two
-// neighbours from LDS (the other two are cells of its own block); the residual
-// restriction of a block and the prolongation of its coarse cell need no
-// exchange at all.  Per cell the arithmetic is that of st5 / gs_value /
-// residual_value, in the same order, so the result equals the whole-level LDS
-// path bit for bit.
-//
-// Cell k = 2 cy + cx of a block: 0 = (0,0) red, 1 = (1,0) black, 2 = (0,1) black,
-// 3 = (1,1) red ((i + j) even is red; blocks start at even coordinates).
-template <class R>
-struct Blk {
-  R f[4], d[4], rd[4];  // right-hand side, diagonal, reciprocal of the diagonal (FP32)
-  R vx[2][3];           // x-face coefficients of row r at local x = 0, 1, 2
-  R vy[2][3];           // y-face coefficients of column c at local y = 0, 1, 2
-  R u[4];
-};
-
-template <class R> struct Vec2;
-template <> struct Vec2<float> { using T = float2; };
-template <> struct Vec2<double> { using T = double2; };
-
-// Smoother update of one cell from its neighbour sum (gs_value with d precomputed).
-__device__ __forceinline__ float blk_gs(float f, float snb, float d, float rd) { return (f + snb) * rd; }
-__device__ __forceinline__ double blk_gs(double f, double snb, double d, double) { return (f + snb) / d; }
-template <class R>
-__device__ __forceinline__ R blk_snb(R aw, R ae, R as, R an, R uw, R ue, R us, R un) {
-  R t1 = aw * uw;
-  t1 = t1 + ae * ue;
-  R t2 = as * us;
-  t2 = t2 + an * un;
-  return t1 + t2;
-}
-
-// Region of a kernel: BW x BW blocks, the output tile's TS/2 x TS/2 blocks plus hb
-// halo blocks on each side.  LDS holds the iterate of the region's cells with a
-// ring of zero cells around it (UW = 2 BW + 2 cells per row).
-struct BlkRegion {
-  int BW, hb, UW;
-  int gbx0, gby0;  // coarse (block) coordinates of region block (0, 0)
-  int mb;          // blocks per side of the level (m / 2)
-};
-
-__device__ __forceinline__ int blk_lds(const BlkRegion& g, int lx, int ly) { return (ly + 1) * g.UW + lx + 1; }
-
-// Load block (bx, by) of the region (inside the domain) into registers.
-template <class R>
-__device__ __forceinline__ void blk_load(Blk<R>& b, const BlkRegion& g, int bx, int by, int m, const R* F,
-                                         const R* CW, const R* CS, const R* CDT, const R* CTOP, const R* U,
-                                         const R* UC, int mc, bool u_zero) {
-  using V = typename Vec2<R>::T;
-  const int gx = 2 * (g.gbx0 + bx), gy = 2 * (g.gby0 + by);
-  const int64_t c0 = (int64_t)gy * m + gx, c2 = c0 + m;
-  const V f0 = *(const V*)(F + c0), f1 = *(const V*)(F + c2);
-  const V t0 = *(const V*)(CDT + c0), t1 = *(const V*)(CDT + c2);
-  const V w0 = *(const V*)(CW + c0), w1 = *(const V*)(CW + c2);
-  const V s0 = *(const V*)(CS + c0), s1 = *(const V*)(CS + c2);
-  const bool east = gx + 2 < m, north = gy + 2 < m;
-  const R e0 = east ? CW[c0 + 2] : (R)0, e1 = east ? CW[c2 + 2] : (R)0;
-  const V n0 = north ? *(const V*)(CS + c2 + m) : *(const V*)(CTOP + gx);
-  V u0, u1;
-  if (u_zero) {
-    u0.x = u0.y = u1.x = u1.y = (R)0;
-  } else {
-    u0 = *(const V*)(U + c0);
-    u1 = *(const V*)(U + c2);
-  }
-  if (UC) {
-    const R uc = UC[(int64_t)(g.gby0 + by) * mc + g.gbx0 + bx];
-    u0.x = u0.x + uc;
-    u0.y = u0.y + uc;
-    u1.x = u1.x + uc;
-    u1.y = u1.y + uc;
-  }
-  b.f[0] = f0.x; b.f[1] = f0.y; b.f[2] = f1.x; b.f[3] = f1.y;
-  b.u[0] = u0.x; b.u[1] = u0.y; b.u[2] = u1.x; b.u[3] = u1.y;
-  b.vx[0][0] = w0.x; b.vx[0][1] = w0.y; b.vx[0][2] = e0;
-  b.vx[1][0] = w1.x; b.vx[1][1] = w1.y; b.vx[1][2] = e1;
-  b.vy[0][0] = s0.x; b.vy[0][1] = s1.x; b.vy[0][2] = n0.x;
-  b.vy[1][0] = s0.y; b.vy[1][1] = s1.y; b.vy[1][2] = n0.y;
-  const R cdt[4] = {t0.x, t0.y, t1.x, t1.y};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int cx = k & 1, cy = k >> 1;
-    R d = cdt[k];
-    d = d + b.vx[cy][cx];
-    d = d + b.vx[cy][cx + 1];
-    d = d + b.vy[cx][cy];
-    d = d + b.vy[cx][cy + 1];
-    b.d[k] = d;
-    b.rd[k] = sizeof(R) == 4 ? (R)__builtin_amdgcn_rcpf((float)d) : (R)0;
-  }
-}
-
-// Neighbour sums of the four cells of block (bx, by) from the current iterate.
-template <class R>
-__device__ __forceinline__ R blk_cell_snb(const Blk<R>& b, const BlkRegion& g, const RMG_LDS R* L, int bx, int by,
-                                          int k) {
-  const int cx = k & 1, cy = k >> 1;
-  const int lx = 2 * bx + cx, ly = 2 * by + cy;
-  const R uw = cx ? b.u[k - 1] : L[blk_lds(g, lx - 1, ly)];
-  const R ue = cx ? L[blk_lds(g, lx + 1, ly)] : b.u[k + 1];
-  const R us = cy ? b.u[k - 2] : L[blk_lds(g, lx, ly - 1)];
-  const R un = cy ? L[blk_lds(g, lx, ly + 1)] : b.u[k + 2];
-  return blk_snb<R>(b.vx[cy][cx], b.vx[cy][cx + 1], b.vy[cx][cy], b.vy[cx][cy + 1], uw, ue, us, un);
-}
-
-// One colour of a red-black sweep over the thread's blocks (cells 0, 3 or 1, 2).
-template <class R, int NB, int COLOUR>
-__device__ __forceinline__ void blk_half_sweep(Blk<R> (&b)[NB], const bool (&live)[NB], const int (&bx)[NB],
-                                               const int (&by)[NB], const BlkRegion& g, RMG_LDS R* L) {
-  constexpr int ka = COLOUR ? 1 : 0, kb = COLOUR ? 2 : 3;
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    if (!live[q]) continue;
-    const R sa = blk_cell_snb(b[q], g, L, bx[q], by[q], ka);
-    const R sb = blk_cell_snb(b[q], g, L, bx[q], by[q], kb);
-    b[q].u[ka] = blk_gs(b[q].f[ka], sa, b[q].d[ka], b[q].rd[ka]);
-    b[q].u[kb] = blk_gs(b[q].f[kb], sb, b[q].d[kb], b[q].rd[kb]);
-    L[blk_lds(g, 2 * bx[q] + (ka & 1), 2 * by[q] + (ka >> 1))] = b[q].u[ka];
-    L[blk_lds(g, 2 * bx[q] + (kb & 1), 2 * by[q] + (kb >> 1))] = b[q].u[kb];
-  }
-}
-
-// Common set-up: the thread's blocks, their registers, the LDS iterate (zero outside
-// the domain and on the ring).  Returns after the barrier that publishes the iterate.
-template <class R, int TS, int NB>
-__device__ __forceinline__ void blk_setup(Blk<R> (&b)[NB], bool (&live)[NB], bool (&own)[NB], int (&bx)[NB],
-                                          int (&by)[NB], BlkRegion& g, RMG_LDS R* L, int hb, int m, int x0,
-                                          int y0, const R* F, const R* CW, const R* CS, const R* CDT,
-                                          const R* CTOP, const R* U, const R* UC, int mc, bool u_zero) {
-  g.hb = hb;
-  g.BW = TS / 2 + 2 * hb;
-  g.UW = 2 * g.BW + 2;
-  g.gbx0 = x0 / 2 - hb;
-  g.gby0 = y0 / 2 - hb;
-  g.mb = m / 2;
-  const int nblk = g.BW * g.BW;
-  const unsigned mg = rmg_magic(g.BW);
-  const int t = (int)threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    const int k = t + q * kBlock;
-    by[q] = (int)__umulhi((unsigned)k, mg);
-    bx[q] = k - by[q] * g.BW;
-    const int gbx = g.gbx0 + bx[q], gby = g.gby0 + by[q];
-    live[q] = k < nblk && gbx >= 0 && gbx < g.mb && gby >= 0 && gby < g.mb;
-    own[q] = live[q] && bx[q] >= hb && bx[q] < hb + TS / 2 && by[q] >= hb && by[q] < hb + TS / 2;
-  }
-#pragma unroll
-  for (int q = 0; q < NB; ++q)
-    if (live[q]) blk_load(b[q], g, bx[q], by[q], m, F, CW, CS, CDT, CTOP, U, UC, mc, u_zero);
-  // LDS iterate: every block of the region (zero outside the domain) and the zero ring
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    if (t + q * kBlock >= nblk) continue;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      L[blk_lds(g, 2 * bx[q] + (k & 1), 2 * by[q] + (k >> 1))] = live[q] ? b[q].u[k] : (R)0;
-  }
-  const int W2 = 2 * g.BW;
-  for (int e = t; e < 4 * (W2 + 1); e += kBlock) {
-    const int side = e / (W2 + 1), i = e - side * (W2 + 1);
-    int lx, ly;
-    if (side == 0) { lx = i - 1; ly = -1; }        // bottom ring row, from the corner
-    else if (side == 1) { lx = i; ly = W2; }       // top ring row
-    else if (side == 2) { lx = -1; ly = i; }       // left ring column
-    else { lx = W2; ly = i - 1; }                  // right ring column
-    L[blk_lds(g, lx, ly)] = (R)0;
-  }
-  __syncthreads();
-}
-
-constexpr int blk_nb(int ts, int hb) {
-  return ((ts / 2 + 2 * hb) * (ts / 2 + 2 * hb) + kBlock - 1) / kBlock;
-}
-template <class R>
-constexpr size_t blk_lds_bytes(int ts, int hb) {
-  return sizeof(R) * (size_t)(2 * (ts / 2 + 2 * hb) + 2) * (size_t)(2 * (ts / 2 + 2 * hb) + 2);
-}
-
-// Down leg on a streaming level l: nu1 red-black sweeps, residual, restriction.
-// Halo: nu1 + 1 blocks (2 nu1 + 2 >= 2 nu1 + 1 cells: the residual of a tile cell
-// depends on data up to 2 nu1 + 1 cells away).
-template <class R, int TS, int NB>
-__global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t s = blockIdx.y;
-  if (!pl.state[s].active) return;
-  const int m = a.n >> l, mc = m >> 1;
-  // timed launches count the cells they process: once per active sample (one
-  // counter update per workgroup would serialise thousands of atomics on one address)
-  if (pl.tcells && blockIdx.x == 0 && threadIdx.x == 0)
-    atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)m * (unsigned long long)m);
-  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
-  const int ntx = m / TS;
-  const int tile = xcd_tile();
-  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
-  RMG_LDS R* L = (RMG_LDS R*)smem;
-  Blk<R> b[NB];
-  bool live[NB], own[NB];
-  int bx[NB], by[NB];
-  BlkRegion g;
-  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, a.nu1 + 1, m, x0, y0, (const R*)pl.lv.f[l] + s * M2,
-                       (const R*)pl.lv.cw[l] + s * M2, (const R*)pl.lv.cs[l] + s * M2,
-                       (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m,
-                       (const R*)pl.lv.ub[l] + s * M2, nullptr, mc, u_zero != 0);
-  for (int st = 0; st < 2 * a.nu1; ++st) {
-    if (st & 1)
-      blk_half_sweep<R, NB, 1>(b, live, bx, by, g, L);
-    else
-      blk_half_sweep<R, NB, 0>(b, live, bx, by, g, L);
-    __syncthreads();
-  }
-  using V = typename Vec2<R>::T;
-  R* U = (R*)pl.lv.u[l] + s * M2;
-  R* FC = (R*)pl.lv.f[l + 1] + s * MC2;
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    if (!own[q]) continue;
-    R r[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const R snb = blk_cell_snb(b[q], g, L, bx[q], by[q], k);
-      r[k] = (b[q].f[k] + snb) - b[q].d[k] * b[q].u[k];
-    }
-    const int gbx = g.gbx0 + bx[q], gby = g.gby0 + by[q];
-    FC[(int64_t)gby * mc + gbx] = restrict4<R>(r[0], r[1], r[2], r[3]);
-    const int64_t c0 = (int64_t)(2 * gby) * m + 2 * gbx;
-    V o0, o1;
-    o0.x = b[q].u[0];
-    o0.y = b[q].u[1];
-    o1.x = b[q].u[2];
-    o1.y = b[q].u[3];
-    *(V*)(U + c0) = o0;
-    *(V*)(U + c0 + m) = o1;
-  }
-}
-
-// Up leg on a streaming level l: prolongation of level l+1 (one coarse value per
-// block), nu2 sweeps; on the finest level (final != 0) the Picard update p += dp
-// and ||dp||_inf instead of a store.  Halo: nu2 blocks (2 nu2 cells).
-template <class R, int TS, int NB>
-__global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final_) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[kBlock / 64];
-  const int64_t s = blockIdx.y;
-  if (!pl.state[s].active) return;
-  const int m = a.n >> l, mc = m >> 1;
-  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
-  const int ntx = m / TS;
-  const int tile = xcd_tile();
-  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
-  RMG_LDS R* L = (RMG_LDS R*)smem;
-  Blk<R> b[NB];
-  bool live[NB], own[NB];
-  int bx[NB], by[NB];
-  BlkRegion g;
-  const R* UC = (const R*)(l + 1 == pl.ltop ? pl.lv.u[l + 1] : pl.lv.ub[l + 1]) + s * MC2;
-  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, a.nu2, m, x0, y0, (const R*)pl.lv.f[l] + s * M2,
-                       (const R*)pl.lv.cw[l] + s * M2, (const R*)pl.lv.cs[l] + s * M2,
-                       (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m,
-                       (const R*)pl.lv.u[l] + s * M2, UC, mc, false);
-  for (int st = 0; st < 2 * a.nu2; ++st) {
-    if (st & 1)
-      blk_half_sweep<R, NB, 1>(b, live, bx, by, g, L);
-    else
-      blk_half_sweep<R, NB, 0>(b, live, bx, by, g, L);
-    __syncthreads();
-  }
-  if (!final_) {
-    using V = typename Vec2<R>::T;
-    R* U = (R*)pl.lv.ub[l] + s * M2;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      if (!own[q]) continue;
-      const int64_t c0 = (int64_t)(2 * (g.gby0 + by[q])) * m + 2 * (g.gbx0 + bx[q]);
-      V o0, o1;
-      o0.x = b[q].u[0];
-      o0.y = b[q].u[1];
-      o1.x = b[q].u[2];
-      o1.y = b[q].u[3];
-      *(V*)(U + c0) = o0;
-      *(V*)(U + c0 + m) = o1;
-    }
-    return;
-  }
-  double* p = a.p + s * M2;
-  double mx = 0.0, bad = 0.0;
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    if (!own[q]) continue;
-    const int64_t c0 = (int64_t)(2 * (g.gby0 + by[q])) * m + 2 * (g.gbx0 + bx[q]);
-    const double2 p0 = *(const double2*)(p + c0), p1 = *(const double2*)(p + c0 + m);
-    const double d0 = (double)b[q].u[0], d1 = (double)b[q].u[1], d2 = (double)b[q].u[2], d3 = (double)b[q].u[3];
-    double2 o0, o1;
-    o0.x = p0.x + d0;
-    o0.y = p0.y + d1;
-    o1.x = p1.x + d2;
-    o1.y = p1.y + d3;
-    *(double2*)(p + c0) = o0;
-    *(double2*)(p + c0 + m) = o1;
-    mx = fmax(fmax(mx, fabs(d0)), fmax(fabs(d1), fmax(fabs(d2), fabs(d3))));
-    if (!isfinite(d0) || !isfinite(d1) || !isfinite(d2) || !isfinite(d3)) bad = 1.0;
-  }
-  mx = block_max(mx, red);
-  bad = block_max(bad, red);
-  if (threadIdx.x == 0) {
-    atomic_max_nonneg(pl.dpmax + s, mx);
-    if (bad > 0.0) atomicOr(&pl.state[s].nanflag, 1);
   }
 }
 
