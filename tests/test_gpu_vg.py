@@ -1,0 +1,159 @@
+"""GPU parity for the van Genuchten-Mualem model with three random fields and
+parametric continuation (Section 2.1 eqs. Sw, sc_van, Krw; Section 5.2).
+
+Fields: Ks, alpha and n from independent 128-term KL expansions (correlation
+length 0.2) with the marginals of the vG workload (Ks = exp(G), sigma^2 = 1.5;
+alpha lognormal with mean 2; n = 1 + lognormal with mean 1.6).  The oracle takes
+the effective fields alpha + alpha_shift and n + n_shift, which is how a level's
+continuation offsets enter the closure.  Tolerances as for Gardner: 1e-10 for the
+FP64 path with equal Picard counts, 1e-8 for the mixed path.
+"""
+from __future__ import annotations
+
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import kl as okl, picard as opicard, qoi as oqoi
+from gpu_common import rel_inf, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1903_08741_amd as rmg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+VF = W.VG_FIELDS
+N_STEPS = 3
+
+
+@functools.lru_cache(maxsize=None)
+def vg_basis(grids=(8, 16, 32, 64, 128)):
+    _, B = okl.basis(1.0, VF["corr_len"], VF["n_modes"], list(grids), ref_n=32)
+    return B
+
+
+def vg_problem(n_shift=0.0, alpha_shift=0.0, n_steps=N_STEPS):
+    g = W.VG_INFILTRATION
+    gpu = rmg.Problem(model=rmg.VGM, n_steps=n_steps, theta_r=g["theta_r"], theta_s=g["theta_s"],
+                      h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"], dt=g["dt"],
+                      vg_n_shift=n_shift, vg_alpha_shift=alpha_shift)
+    orc = dict(g, n_steps=n_steps)
+    return gpu, orc
+
+
+def oracle_fields(B, xi_sample, n, n_shift=0.0, alpha_shift=0.0):
+    """Effective closure fields of one sample (xi_sample [3][M]) on an n x n grid."""
+    out = []
+    for f, (shift, mu, scale) in enumerate(VF["marginals"]):
+        out.append(shift + okl.lognormal(okl.gaussian_field(xi_sample[f], B), mu, scale))
+    Ks, alpha, nv = (a.reshape(n, n) for a in out)
+    return {"Ks": Ks, "alpha": alpha + alpha_shift, "n": nv + n_shift}
+
+
+def oracle_solve(n, fields, prob, max_picard=100):
+    r = opicard.solve(prob, fields, n, dict(W.SOLVER, max_picard=max_picard), mode="mg")
+    r["qoi"] = oqoi.mean_saturation(prob, fields, r["p"]) if r["status"] == 0 else np.nan
+    return r
+
+
+def gpu_fields(n, xi):
+    B = vg_basis()[n]
+    return rmg.sample_fields(n, torch.from_numpy(B).to(DEV), torch.from_numpy(xi).to(DEV),
+                             list(VF["marginals"]))
+
+
+@pytest.mark.parametrize("n,precision,flags,tol", [
+    (16, rmg.FP64, 0, 1e-10), (16, rmg.MIXED, 0, 1e-8),
+    (64, rmg.FP64, 0, 1e-10), (64, rmg.MIXED, 0, 1e-8),
+    (64, rmg.MIXED, rmg.FLAG_FORCE_STREAMING | rmg.FLAG_COARSE_TOP_32, 1e-8),
+])
+def test_vg_three_fields_match_twin_oracle(n, precision, flags, tol):
+    S = 3
+    say(f"vG n={n} precision={precision} flags={flags}")
+    xi = W.xi_draws(W.MLMC_VG["workload_id"], 0, range(S), 3, VF["n_modes"])
+    fields = gpu_fields(n, xi)
+    prob, oprob = vg_problem(n_shift=0.2)
+    out = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, flags=flags))
+    torch.cuda.synchronize()
+    assert out["rc"] == 0
+    h = out["h"].cpu().numpy()
+    B = vg_basis()[n]
+    for i in range(S):
+        r = oracle_solve(n, oracle_fields(B, xi[i], n, n_shift=0.2), oprob)
+        assert r["status"] == 0
+        assert rel_inf(h[i], r["p"].reshape(-1)) < tol, i
+        assert abs(out["qoi"][i].item() - r["qoi"]) <= tol * abs(r["qoi"])
+        if precision == rmg.FP64:
+            assert int(out["stats"]["picard_its"][i]) == sum(r["picard"])
+
+
+def test_vg_fields_marginals_are_the_workloads():
+    """The device fields are the workload's marginals of the KL sums (n = 1 + lognormal)."""
+    n, S = 16, 4
+    xi = W.xi_draws(W.MLMC_VG["workload_id"], 1, range(S), 3, VF["n_modes"])
+    got = gpu_fields(n, xi).cpu().numpy()
+    B = vg_basis()[n]
+    for i in range(S):
+        ref = oracle_fields(B, xi[i], n)
+        for f, key in enumerate(("Ks", "alpha", "n")):
+            assert rel_inf(got[i, f], ref[key].reshape(-1)) < 1e-13
+    assert got[:, 2].min() > 1.0
+
+
+def test_vg_mlmc_with_continuation_matches_oracle():
+    """Three levels 16/32/64 with n shifted by (L - l) * 0.1 on level l; the coarse member
+    of a level-l pair solves with level l - 1's shift.  FP64 (the oracle's iteration, so
+    the failure decisions coincide): every QoI against the oracle (a sample the oracle
+    fails on must fail on the GPU too: one unshifted 64^2 draw does), and the level sums
+    against the exactly rounded sums of the returned QoIs over the successful pairs."""
+    grids, samples, L = (16, 32, 64), (4, 3, 2), 2
+    grad = W.MLMC_VG["n_shift_grad"]
+    B = vg_basis()
+    wid = W.MLMC_VG["workload_id"]
+    levels, xis = [], []
+    for l, (n, S) in enumerate(zip(grids, samples)):
+        xi = W.xi_draws(wid, 10 + l, range(S), 3, VF["n_modes"])
+        xis.append(xi)
+        fine, _ = vg_problem(n_shift=(L - l) * grad)
+        coarse, _ = vg_problem(n_shift=(L - l + 1) * grad)
+        levels.append(dict(n_fine=n, n_coarse=n // 2 if l else 0, fine=fine, coarse=coarse,
+                           basis_fine=torch.from_numpy(B[n]).to(DEV),
+                           basis_coarse=torch.from_numpy(B[n // 2]).to(DEV) if l else None,
+                           xi=torch.from_numpy(xi).to(DEV)))
+    say("vG MLMC with continuation")
+    sums, q, rc = rmg.mlmc_level_estimate(levels, list(VF["marginals"]), rmg.SolverOpts(precision=rmg.FP64),
+                                          return_qoi=True)
+    q = q.cpu().numpy()
+    n_failed_total = 0
+    off = 0
+    for l, (n, S) in enumerate(zip(grids, samples)):
+        qf, qc = q[off:off + S], q[off + S:off + 2 * S]
+        off += 2 * S
+        _, ofine = vg_problem(n_shift=(L - l) * grad)
+        def check(got, ref, where):
+            if np.isnan(ref):
+                assert np.isnan(got), where
+            else:
+                assert abs(got - ref) <= 1e-10 * abs(ref), where
+        for i in range(S):
+            r = oracle_solve(n, oracle_fields(B[n], xis[l][i], n, n_shift=(L - l) * grad), ofine)
+            check(qf[i], r["qoi"], (l, i, "fine"))
+            if l:
+                rc_ = oracle_solve(n // 2, oracle_fields(B[n // 2], xis[l][i], n // 2,
+                                                         n_shift=(L - l + 1) * grad), ofine)
+                check(qc[i], rc_["qoi"], (l, i, "coarse"))
+        y = qf - (qc if l else 0.0)
+        ok = ~np.isnan(y)
+        exact = math.fsum(y[ok])
+        hi, lo = sums[l]["sY"]
+        assert abs((hi + lo) - exact) <= 2 * np.spacing(abs(exact))
+        assert sums[l]["n"] == int(ok.sum()) and sums[l]["n_failed"] == S - int(ok.sum())
+        n_failed_total += S - int(ok.sum())
+    assert rc == (rmg.RMG_ENOTCONV if n_failed_total else 0)

@@ -55,6 +55,38 @@ MLMC_5LEVEL = dict(workload_id=1, grids=(16, 32, 64, 128, 256),
 # Working set for the smoother roofline (larger than the 256 MB last-level cache).
 SMOOTHER_ROOF = dict(workload_id=9, n=512, n_samples=64)
 
+# van Genuchten-Mualem workload with three random fields and parametric
+# continuation (Section 2.1 eqs. Sw, sc_van, Krw; Section 3; Section 5.2):
+#   Ks    = exp(G_K),                 G_K a KL field of sigma^2 = 1.5;
+#   alpha = exp(mu_a + s_a G_a),      mean 2;
+#   n     = 1 + exp(mu_n + s_n G_n),  mean 1.6;
+# every G a unit-variance KL field of the exponential kernel with correlation
+# length 0.2, 128 terms, independent draws per field.  The spreads of alpha and
+# n - 1 match the standard deviations of the paper's uniform perturbations
+# (+-0.2 and +-0.05) with lognormal laws.  Continuation: level l of L + 1 solves
+# with n shifted by (L - l) * 0.1 (milder on coarse levels); the coarse member of
+# a level-l pair uses level l - 1's shift, as the fine member of pair l - 1 does.
+VG_SA2 = 0.003328
+VG_SN2 = 0.002312
+VG_FIELDS = dict(
+    corr_len=0.2, n_modes=128,
+    marginals=((0.0, 0.0, float(np.sqrt(1.5))),                                   # Ks
+               (0.0, float(np.log(2.0) - VG_SA2 / 2), float(np.sqrt(VG_SA2))),    # alpha
+               (1.0, float(np.log(0.6) - VG_SN2 / 2), float(np.sqrt(VG_SN2)))),   # n
+)
+VG_INFILTRATION = dict(
+    model="vg",
+    theta_r=0.05,
+    theta_s=0.5,
+    h_top=0.0,
+    h_bottom=-10.0,
+    h_init=-10.0,
+    dt=0.005,
+    n_steps=50,
+)
+MLMC_VG = dict(workload_id=2, grids=(32, 64, 128, 256, 512), samples=(2048, 512, 128, 32, 8),
+               n_shift_grad=0.1)
+
 
 def xi_draws(workload_id: int, level: int, sample_ids, n_fields: int, n_modes: int) -> np.ndarray:
     """Standard-normal KL coefficients, shape [len(sample_ids)][n_fields][n_modes], float64."""
