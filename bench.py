@@ -81,6 +81,33 @@ def build_levels(torch, rmg, W, precision, dev, max_picard):
     return levels, opts, marg
 
 
+def build_vg_levels(torch, rmg, W, precision, dev, max_picard):
+    """The van Genuchten workload: 5 levels 32^2..512^2 with 2048/512/128/32/8 pairs, three
+    KL fields (128 modes each), 50 steps of dt = 0.005, n shifted by (L - l) * 0.1 on level l
+    (the coarse member of a pair uses level l - 1's shift)."""
+    from paper_1903_08741_amd import kl_setup
+    cfg, vf, g = W.MLMC_VG, W.VG_FIELDS, W.VG_INFILTRATION
+    grids = cfg["grids"]
+    L = len(grids) - 1
+    t0 = time.time()
+    _, tables = kl_setup.kl_tables(1.0, vf["corr_len"], vf["n_modes"], list(grids) + [grids[0] // 2])
+    log(f"kl basis set-up {time.time() - t0:.1f}s")
+
+    def prob(shift):
+        return rmg.Problem(model=rmg.VGM, n_steps=g["n_steps"], theta_r=g["theta_r"], theta_s=g["theta_s"],
+                           h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"], dt=g["dt"],
+                           vg_n_shift=shift)
+    levels = []
+    for l, (n, S) in enumerate(zip(grids, cfg["samples"])):
+        xi = torch.from_numpy(W.xi_draws(cfg["workload_id"], l, range(S), 3, vf["n_modes"])).to(dev)
+        levels.append(dict(n_fine=n, n_coarse=n // 2 if l else 0, fine=prob((L - l) * cfg["n_shift_grad"]),
+                           coarse=prob((L - l + 1) * cfg["n_shift_grad"]),
+                           basis_fine=torch.from_numpy(tables[n]).to(dev),
+                           basis_coarse=torch.from_numpy(tables[n // 2]).to(dev) if l else None, xi=xi))
+    opts = rmg.SolverOpts(precision=precision, max_picard=max_picard)
+    return levels, opts, list(vf["marginals"])
+
+
 def n_solves(levels):
     return sum(lv["xi"].shape[0] * (2 if lv["n_coarse"] else 1) for lv in levels)
 
@@ -236,6 +263,9 @@ def cpu_baseline(max_picard, cycles, gpu_its_per_solve):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("gardner", "vg"), default="gardner",
+                    help="gardner: the 5-level Gardner MLMC workload (default); vg: the van Genuchten "
+                         "workload with three fields and continuation (5 levels 32^2..512^2)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
@@ -259,7 +289,9 @@ def main():
 
     dev = torch.device("cuda:0")
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
-    levels, opts, marg = build_levels(torch, rmg, W, precision, dev, args.max_picard)
+    vg = args.workload == "vg"
+    build = build_vg_levels if vg else build_levels
+    levels, opts, marg = build(torch, rmg, W, precision, dev, args.max_picard)
     opts.cycles_per_picard = args.cycles
     if args.no_autotune:
         opts.flags |= rmg.FLAG_NO_AUTOTUNE
@@ -293,19 +325,19 @@ def main():
     picard = sum(s["picard_its"] for s in sums)
     gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": recorded_traffic(),
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None if vg else recorded_traffic(),
             "kernel": "k_down (nu1 fused red-black sweeps + residual + restriction, level-streaming path)",
             "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
             "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
     extras = {}
-    if not args.no_extras:
+    if not args.no_extras and not vg:
         extras["per_grid"] = per_grid(torch, rmg, ctx, levels, opts, marg)
         if precision == rmg.MIXED:
             fms, ffail = fp64_path(torch, rmg, ctx, levels, marg, args.max_picard, args.cycles)
             extras["fp64_path"] = {"ms_per_step": fms, "failed_pairs": ffail, "mixed_speedup": fms / ms}
         extras["roofline_large_batch"] = large_batch_roofline(torch, rmg, ctx, W, levels, marg)
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not vg:
         t1 = time.time()
         cpu = cpu_baseline(args.max_picard, args.cycles, its_per_solve)
         log(f"cpu baseline {time.time() - t1:.1f}s")
@@ -321,11 +353,17 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 multigrid in f64 Picard" if precision == rmg.MIXED else "f64",
-        "data": "synthetic (seeded KL lognormal Ks fields)",
-        "config": {"workload": "mlmc 5 levels 16^2..256^2, 4096/1024/256/64/16 samples, Gardner, "
-                               "10 steps dt=0.01, V(2,2) per Picard, eps 1e-8",
+        "data": ("synthetic (seeded KL fields: lognormal Ks, alpha, 1 + lognormal n)" if vg
+                 else "synthetic (seeded KL lognormal Ks fields)"),
+        "config": {"workload": ("mlmc 5 levels 32^2..512^2, 2048/512/128/32/8 samples, van Genuchten-Mualem "
+                                "with 3 KL fields (128 modes), n shifted by (L-l)*0.1, 50 steps dt=0.005, "
+                                "V(2,2) per Picard, eps 1e-8" if vg else
+                                "mlmc 5 levels 16^2..256^2, 4096/1024/256/64/16 samples, Gardner, "
+                                "10 steps dt=0.01, V(2,2) per Picard, eps 1e-8"),
                    "solves_per_step": total, "converged_solves_per_step": converged,
-                   "cells_per_step": 6291456, "failed_pairs": failed,
+                   "cells_per_step": sum(lv["xi"].shape[0] * (lv["n_fine"] ** 2 + lv["n_coarse"] ** 2)
+                                         for lv in levels),
+                   "failed_pairs": failed,
                    "picard_iterations_per_step": picard, "precision": args.precision,
                    "cycles_per_picard": args.cycles, "max_picard": args.max_picard},
         "roofline": roof,
