@@ -92,7 +92,7 @@ typedef struct {
  * benchmark), coarsest_n 4. */
 typedef struct {
   int32_t precision;          /* rmg_precision: FP64 everywhere, or FP32 multigrid inside FP64 Picard */
-  int32_t cycle;              /* rmg_cycle; this build runs RMG_CYCLE_V only (W: RMG_EINVAL) */
+  int32_t cycle;              /* rmg_cycle: V (one coarse cycle per level visit) or W (two) */
   int32_t nu1, nu2;           /* pre/post red-black Gauss-Seidel sweeps, each 0..4, not both 0 */
   int32_t cycles_per_picard;  /* fixed number of cycles per Picard step, 1..16 */
   int32_t max_picard;         /* Picard iterations allowed per time step, >= 1 */

@@ -122,7 +122,7 @@ int check_opts(rmg_ctx* ctx, const rmg_solver_opts* o, int n) {
   if (!o) return fail(ctx, RMG_EINVAL, "opts is NULL");
   if (o->precision != RMG_FP64 && o->precision != RMG_MIXED)
     return fail(ctx, RMG_EINVAL, "unknown precision %d", o->precision);
-  if (o->cycle != RMG_CYCLE_V) return fail(ctx, RMG_EINVAL, "only the V-cycle is built (cycle=%d)", o->cycle);
+  if (o->cycle != RMG_CYCLE_V && o->cycle != RMG_CYCLE_W) return fail(ctx, RMG_EINVAL, "unknown cycle %d", o->cycle);
   if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 4 || o->nu2 > 4 || o->nu1 + o->nu2 == 0)
     return fail(ctx, RMG_EINVAL, "nu1, nu2 must be in 0..4 and not both 0");
   if (o->cycles_per_picard < 1 || o->cycles_per_picard > 16)
@@ -624,6 +624,7 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
   j.a.cp.seg_split = S;
   j.a.nu1 = opts->nu1;
   j.a.nu2 = opts->nu2;
+  j.a.gamma = opts->cycle == RMG_CYCLE_W ? 2 : 1;
   j.a.cpp = opts->cycles_per_picard;
   j.a.max_picard = opts->max_picard;
   j.a.eps = opts->eps_picard;
@@ -721,6 +722,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     }
     j.a.nu1 = opts->nu1;
     j.a.nu2 = opts->nu2;
+  j.a.gamma = opts->cycle == RMG_CYCLE_W ? 2 : 1;
     j.a.cpp = opts->cycles_per_picard;
     j.a.max_picard = opts->max_picard;
     j.a.eps = opts->eps_picard;

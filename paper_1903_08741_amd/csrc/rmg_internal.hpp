@@ -52,6 +52,7 @@ struct SolveArgs {
   const double* fields;
   ClassProblems cp;
   int nu1, nu2, cpp, max_picard;
+  int gamma;  // coarse cycles per level visit: 1 = V-cycle, 2 = W-cycle
   int state_global;  // whole-sample kernel: keep the FP64 state in global memory even if LDS fits
   double eps;
   double* p;

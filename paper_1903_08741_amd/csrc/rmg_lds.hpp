@@ -226,35 +226,65 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L, RMG_LDS double* A, RMG_
   __syncthreads();
 }
 
-// One V(nu1, nu2) cycle from level `top` of the LDS hierarchy (levels top .. nlev-1).
-// `top_zero`: the iterate on level `top` is zero on entry (coarser levels always are).
-template <class R>
-__device__ void lds_vcycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, RMG_LDS double* A,
-                           RMG_LDS double* ipiv, bool top_zero) {
 #ifndef RMG_ZERO_SWEEP
 #define RMG_ZERO_SWEEP 1
 #endif
 #ifndef RMG_FUSED_PROLONG
 #define RMG_FUSED_PROLONG 1
 #endif
-  for (int l = top; l < nlev - 1; ++l) {
-    lds_sweeps(lev[l], nu1, RMG_ZERO_SWEEP && (l > top || top_zero));
-    lds_residual_restrict(lev[l], lev[l + 1]);
+
+// Post-smoothing of level l after its coarse correction (prolongation fused into the
+// first red half-sweep when nu2 > 0).
+template <class R>
+__device__ void lds_up_leg(const LdsLevel<R>* lev, int l, int nu2) {
+  if (RMG_FUSED_PROLONG && nu2 > 0) {
+    lds_half_sweep_prolong(lev[l], lev[l + 1]);
     __syncthreads();
+    lds_half_sweep(lev[l], 1);
+    __syncthreads();
+    lds_sweeps(lev[l], nu2 - 1);
+  } else {
+    lds_prolong_add(lev[l], lev[l + 1]);
+    __syncthreads();
+    lds_sweeps(lev[l], nu2);
   }
-  lds_coarsest_solve(lev[nlev - 1], A, ipiv);
-  for (int l = nlev - 2; l >= top; --l) {
-    if (RMG_FUSED_PROLONG && nu2 > 0) {
-      lds_half_sweep_prolong(lev[l], lev[l + 1]);
+}
+
+// One multigrid cycle from level `top` of the LDS hierarchy (levels top .. nlev-1;
+// gamma = 1: V-cycle, gamma = 2: W-cycle; Section 4.2), written as a loop: descend
+// with pre-smoothing and restriction to the coarsest level, solve it exactly, then
+// ascend with prolongation and post-smoothing; a W-cycle descends once more from
+// every level before ascending past it.  A level's first visit starts from a zero
+// iterate (its restriction set it to zero), a second visit from the current
+// iterate.  `top_zero`: the iterate on level `top` is zero on entry.
+template <class R>
+__device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, int gamma,
+                          RMG_LDS double* A, RMG_LDS double* ipiv, bool top_zero) {
+  int l = top;
+  bool zero = top_zero;
+  unsigned again = 0;  // bit l: level l owes one more coarse cycle (W-cycle)
+  for (;;) {
+    for (; l < nlev - 1; ++l) {
+      lds_sweeps(lev[l], nu1, RMG_ZERO_SWEEP && zero);
+      lds_residual_restrict(lev[l], lev[l + 1]);
       __syncthreads();
-      lds_half_sweep(lev[l], 1);
-      __syncthreads();
-      lds_sweeps(lev[l], nu2 - 1);
-    } else {
-      lds_prolong_add(lev[l], lev[l + 1]);
-      __syncthreads();
-      lds_sweeps(lev[l], nu2);
+      if (gamma == 2) again |= 1u << l;
+      zero = true;
     }
+    lds_coarsest_solve(lev[nlev - 1], A, ipiv);
+    bool descend = false;
+    while (l > top) {
+      --l;
+      if (again & (1u << l)) {
+        again &= ~(1u << l);
+        ++l;
+        zero = false;
+        descend = true;
+        break;
+      }
+      lds_up_leg(lev, l, nu2);
+    }
+    if (!descend) return;
   }
 }
 

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
       lds_coarsen(lev[l], lev[l + 1]);
       __syncthreads();
     }
-    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_vcycle(lev, 0, a.nlev, a.nu1, a.nu2, A, ipiv, cyc == 0);
+    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_cycle(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, A, ipiv, cyc == 0);
     // Picard update p <- p + dp and ||dp||_inf
     double mx = 0.0, bad = 0.0;
     for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
     lds_coarsen(lev[l], lev[l + 1]);
     __syncthreads();
   }
-  lds_vcycle(lev, 0, nlev, a.nu1, a.nu2, A, ipiv, u_zero != 0);
+  lds_cycle(lev, 0, nlev, a.nu1, a.nu2, a.gamma, A, ipiv, u_zero != 0);
   if (lt > 0 || !final_) {
     for (int v = threadIdx.x; v < nv; v += NT) {
       V o;
@@ -710,34 +710,35 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
   }
   const int nc = n >> (a.nlev - 1);
   const size_t lcv = coarse_lds(n >> pl.ltop, nc, fp64);
-  for (int cyc = 0; cyc < a.cpp; ++cyc) {
-    for (int l = 0; l < pl.ltop; ++l) {
-      const int m = n >> l, ts = pl.ts[l];
-      const unsigned tiles = (unsigned)((m / ts) * (m / ts));
-      KernelTimer* tm = pl.timer;
-      const bool timed = tm && tm->which == 1 && tm->tail - tm->head < tm->cap;
-      const int q = timed ? (int)(tm->tail % tm->cap) : 0;
-      StreamPlan plx = pl;
-      plx.tcells = timed ? tm->d_cells : nullptr;
-      if (timed) {
-        hipError_t e = hipEventRecord(tm->ev[2 * q], st);
-        if (e != hipSuccess) return e;
-      }
-      launch_down<R>(ts, dim3(tiles, (unsigned)a.S), st, a, plx, l, (l > 0 || cyc == 0) ? 1 : 0);
-      if (timed) {
-        hipError_t e = hipEventRecord(tm->ev[2 * q + 1], st);
-        if (e != hipSuccess) return e;
-        ++tm->tail;
-      }
+  hipError_t err = hipSuccess;
+  // One cycle from level l (its iterate zero on entry if `zero`): the down leg, gamma
+  // coarse cycles (the coarse kernel below ltop), the up leg; `last`: the final cycle of
+  // the Picard iteration, whose finest up leg applies the Picard update.
+  auto cycle = [&](auto&& self, int l, bool zero, bool last) -> void {
+    if (err != hipSuccess) return;
+    if (l == pl.ltop) {
+      hipLaunchKernelGGL((k_coarse_v<R, kCoarseThreads>), dim3((unsigned)a.S), dim3(kCoarseThreads), lcv, st, a,
+                         pl, zero ? 1 : 0, last ? 1 : 0);
+      return;
     }
-    hipLaunchKernelGGL((k_coarse_v<R, kCoarseThreads>), dim3((unsigned)a.S), dim3(kCoarseThreads), lcv, st, a, pl,
-                       (pl.ltop > 0 || cyc == 0) ? 1 : 0, (cyc == a.cpp - 1) ? 1 : 0);
-    for (int l = pl.ltop - 1; l >= 0; --l) {
-      const int m = n >> l, ts = pl.ts[l];
-      const unsigned tiles = (unsigned)((m / ts) * (m / ts));
-      launch_up<R>(ts, dim3(tiles, (unsigned)a.S), st, a, pl, l, (l == 0 && cyc == a.cpp - 1) ? 1 : 0);
+    const int m = n >> l, ts = pl.ts[l];
+    const unsigned tiles = (unsigned)((m / ts) * (m / ts));
+    KernelTimer* tm = pl.timer;
+    const bool timed = tm && tm->which == 1 && tm->tail - tm->head < tm->cap;
+    const int q = timed ? (int)(tm->tail % tm->cap) : 0;
+    StreamPlan plx = pl;
+    plx.tcells = timed ? tm->d_cells : nullptr;
+    if (timed && (err = hipEventRecord(tm->ev[2 * q], st)) != hipSuccess) return;
+    launch_down<R>(ts, dim3(tiles, (unsigned)a.S), st, a, plx, l, zero ? 1 : 0);
+    if (timed) {
+      if ((err = hipEventRecord(tm->ev[2 * q + 1], st)) != hipSuccess) return;
+      ++tm->tail;
     }
-  }
+    for (int k = 0; k < a.gamma; ++k) self(self, l + 1, k == 0, last);
+    launch_up<R>(ts, dim3(tiles, (unsigned)a.S), st, a, pl, l, (l == 0 && last) ? 1 : 0);
+  };
+  for (int cyc = 0; cyc < a.cpp; ++cyc) cycle(cycle, 0, cyc == 0, cyc == a.cpp - 1);
+  if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_control, dim3((unsigned)((a.S + kBlock - 1) / kBlock)), blk, 0, st, a, pl);
   return hipGetLastError();
 }

@@ -163,6 +163,46 @@ def test_streaming_levels_match_twin_oracle(n, precision, tol):
 
 # V(0, nu2) is excluded: without pre-smoothing this coarse-grid correction (piecewise-constant
 # prolongation, direct coarse discretisation) diverges, in the oracle as well.
+@pytest.mark.parametrize("n,precision,flags,tol", [
+    (16, rmg.FP64, 0, 1e-10), (32, rmg.MIXED, 0, 1e-8),
+    (64, rmg.FP64, 0, 1e-10), (64, rmg.MIXED, rmg.FLAG_COARSE_TOP_32, 1e-8), (128, rmg.MIXED, 0, 1e-8),
+])
+def test_w_cycle_matches_twin_oracle(n, precision, flags, tol):
+    """W(2,2), one cycle per Picard step (Section 4.2: the paper's cycle): whole-sample
+    (16^2, 32^2) and level-streaming grids (64^2, 128^2; the coarse kernel runs its own
+    W-cycle below its top level) against the oracle's recursive W-cycle."""
+    S = 3
+    say(f"W-cycle n={n} precision={precision} flags={flags}")
+    B, xi, fields = _fields(n, S, wid=13)
+    prob = rmg.Problem(n_steps=3)
+    out = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(precision=precision, cycle=rmg.CYCLE_W, flags=flags))
+    torch.cuda.synchronize()
+    h = out["h"].cpu().numpy()
+    opts = dict(W.SOLVER, cycle="W")
+    for i in range(S):
+        r = oracle_solve(n, oracle_fields(B, xi[i, 0]), dict(W.GARDNER_INFILTRATION, n_steps=3), opts)
+        assert (out["status"][i].item() == 0) == (r["status"] == 0)
+        if r["status"] != 0:
+            continue
+        assert rel_inf(h[i], r["p"].reshape(-1)) < tol, i
+        if precision == rmg.FP64:
+            assert int(out["stats"]["picard_its"][i]) == sum(r["picard"])
+            assert int(out["stats"]["mg_cycles"][i]) == sum(r["picard"])
+
+
+def test_w_cycle_streaming_equals_whole_sample_bitwise():
+    n, S = 64, 4
+    say("W-cycle streaming vs whole-sample n=64")
+    _, _, fields = _fields(n, S, wid=14)
+    prob = rmg.Problem(n_steps=2)
+    a = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(cycle=rmg.CYCLE_W, flags=rmg.FLAG_WHOLE_WHERE_FITS))
+    b = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(cycle=rmg.CYCLE_W,
+                                                            flags=rmg.FLAG_FORCE_STREAMING | rmg.FLAG_COARSE_TOP_32))
+    torch.cuda.synchronize()
+    assert torch.equal(a["h"], b["h"])
+    assert (a["stats"]["picard_its"] == b["stats"]["picard_its"]).all()
+
+
 @pytest.mark.parametrize("nu1,nu2,cpp,nc", [(1, 1, 1, 4), (2, 1, 2, 2), (1, 2, 1, 4), (3, 3, 1, 2)])
 def test_solver_options_match_twin_oracle(nu1, nu2, cpp, nc):
     n, S = 64, 2
@@ -215,7 +255,7 @@ def test_invalid_arguments_raise():
     _, _, fields = _fields(16, 2, wid=9)
     ctx = rmg.default_context()
     for kw in (dict(nu1=0, nu2=0), dict(coarsest_n=8), dict(max_picard=0), dict(eps_picard=0.0),
-               dict(cycle=rmg.CYCLE_W)):
+               dict(cycle=3), dict(cycles_per_picard=-1)):
         with pytest.raises(rmg.RmgError) as e:
             ctx.picard_mg_solve(16, fields, rmg.Problem(), rmg.SolverOpts(**kw))
         assert e.value.code == -1
