@@ -88,13 +88,16 @@ typedef struct {
 } rmg_problem;
 
 /* Solver options.  Defaults for the benchmark workloads: MIXED, V, 2, 2, 1,
- * eps_mg 1e-5 (unused), eps_picard 1e-8, max_picard 100 (500 in the MLMC
- * benchmark), coarsest_n 4. */
+ * eps_mg 1e-5 (used when cycles_per_picard = 0), eps_picard 1e-8, max_picard 100
+ * (500 in the MLMC benchmark), coarsest_n 4.  The paper's own setting is W, 2, 2,
+ * cycles_per_picard 0, eps_mg 1e-5. */
 typedef struct {
   int32_t precision;          /* rmg_precision: FP64 everywhere, or FP32 multigrid inside FP64 Picard */
   int32_t cycle;              /* rmg_cycle: V (one coarse cycle per level visit) or W (two) */
   int32_t nu1, nu2;           /* pre/post red-black Gauss-Seidel sweeps, each 0..4, not both 0 */
-  int32_t cycles_per_picard;  /* fixed number of cycles per Picard step, 1..16 */
+  int32_t cycles_per_picard;  /* fixed number of cycles per Picard step, 1..16; 0: cycle until
+                                 max_c |f - A dp| < eps_mg (at most 200 cycles; the residual in the
+                                 smoother precision; whole-sample grids only, otherwise RMG_EINVAL) */
   int32_t max_picard;         /* Picard iterations allowed per time step, >= 1 */
   int32_t coarsest_n;         /* coarsest grid size, 2 or 4, solved exactly in FP64 */
   int32_t flags;              /* bit 0: force the level-streaming path (no whole-sample-in-LDS kernel);
@@ -109,7 +112,7 @@ typedef struct {
                                  LDS (64 x 64 in FP32), not only up to 32 x 32;
                                  bit 6: start the one-workgroup coarse V-cycle at 32 x 32 in FP32
                                  too (more level-streaming levels; results are identical) */
-  double eps_mg;              /* reserved for a residual-controlled cycle count (ignored) */
+  double eps_mg;              /* residual tolerance of cycles_per_picard = 0 (Section 4.2: 1e-5) */
   double eps_picard;          /* stop when ||dp||_inf < eps_picard (strict) */
 } rmg_solver_opts;
 

@@ -125,8 +125,10 @@ int check_opts(rmg_ctx* ctx, const rmg_solver_opts* o, int n) {
   if (o->cycle != RMG_CYCLE_V && o->cycle != RMG_CYCLE_W) return fail(ctx, RMG_EINVAL, "unknown cycle %d", o->cycle);
   if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 4 || o->nu2 > 4 || o->nu1 + o->nu2 == 0)
     return fail(ctx, RMG_EINVAL, "nu1, nu2 must be in 0..4 and not both 0");
-  if (o->cycles_per_picard < 1 || o->cycles_per_picard > 16)
-    return fail(ctx, RMG_EINVAL, "cycles_per_picard must be in 1..16");
+  if (o->cycles_per_picard < 0 || o->cycles_per_picard > 16)
+    return fail(ctx, RMG_EINVAL, "cycles_per_picard must be in 0..16");
+  if (o->cycles_per_picard == 0 && !(o->eps_mg > 0.0))
+    return fail(ctx, RMG_EINVAL, "cycles_per_picard = 0 needs eps_mg > 0");
   if (o->max_picard < 1) return fail(ctx, RMG_EINVAL, "max_picard must be >= 1");
   if (!(o->eps_picard > 0.0)) return fail(ctx, RMG_EINVAL, "eps_picard must be > 0");
   if (o->coarsest_n != 2 && o->coarsest_n != 4)
@@ -628,11 +630,15 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
   j.a.cpp = opts->cycles_per_picard;
   j.a.max_picard = opts->max_picard;
   j.a.eps = opts->eps_picard;
+  j.a.eps_mg = opts->eps_mg;
   j.a.p = d_h_out;
   j.a.qoi = d_qoi;
   j.a.status = d_status;
   j.a.stats = d_stats;
   class_plan(j, opts);
+  if (!j.whole && opts->cycles_per_picard == 0)
+    return fail(ctx, RMG_EINVAL, "grid %d: the residual-controlled cycle count (cycles_per_picard = 0) is built "
+                "for the whole-sample kernel only (grids up to 32 x 32, or 64 x 64 with flag bit 5)", j.a.n);
   // the solve runs on a context stream ordered after the caller's stream (a
   // captured graph cannot be recorded on the legacy default stream)
   j.stream = ctx->side[0];
@@ -726,7 +732,11 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     j.a.cpp = opts->cycles_per_picard;
     j.a.max_picard = opts->max_picard;
     j.a.eps = opts->eps_picard;
+  j.a.eps_mg = opts->eps_mg;
     class_plan(j, opts);
+    if (!j.whole && opts->cycles_per_picard == 0)
+      return fail(ctx, RMG_EINVAL, "grid %d: the residual-controlled cycle count (cycles_per_picard = 0) is "
+                  "built for the whole-sample kernel only (grids up to 32 x 32, or 64 x 64 with flag bit 5)", n);
     jobs.push_back(j);
     jn.push_back(n);
   }

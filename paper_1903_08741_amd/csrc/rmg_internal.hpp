@@ -9,6 +9,7 @@
 namespace rmg {
 
 constexpr int kMaxLevels = 12;
+constexpr int kMaxMgCycles = 200;  // cap of the residual-controlled cycle count
 constexpr int kTile = 32;       // output tile edge of the level-streaming kernels
 #ifndef RMG_COARSE_TOP_F32
 #define RMG_COARSE_TOP_F32 64
@@ -54,7 +55,8 @@ struct SolveArgs {
   int nu1, nu2, cpp, max_picard;
   int gamma;  // coarse cycles per level visit: 1 = V-cycle, 2 = W-cycle
   int state_global;  // whole-sample kernel: keep the FP64 state in global memory even if LDS fits
-  double eps;
+  double eps;     // Picard stopping tolerance on ||dp||_inf
+  double eps_mg;  // cycles_per_picard == 0: cycle until max |f - A dp| < eps_mg
   double* p;
   double* theta_old;
   double* qoi;

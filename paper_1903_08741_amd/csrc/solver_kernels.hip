@@ -178,7 +178,22 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
       lds_coarsen(lev[l], lev[l + 1]);
       __syncthreads();
     }
-    for (int cyc = 0; cyc < a.cpp; ++cyc) lds_cycle(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, A, ipiv, cyc == 0);
+    // a fixed number of cycles, or (cpp == 0) cycles until the correction equation's
+    // residual max_c |f - A dp| (level 0, smoother precision) is below eps_mg
+    int ncyc = 0;
+    for (;;) {
+      lds_cycle(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, A, ipiv, ncyc == 0);
+      ++ncyc;
+      if (a.cpp > 0) {
+        if (ncyc == a.cpp) break;
+        continue;
+      }
+      double rmax = 0.0;
+      for (int c = threadIdx.x; c < N; c += NT)
+        rmax = fmax(rmax, fabs((double)residual_value<R>(L0.f[c], L0.u[c], lds_st5(L0, c))));
+      rmax = block_max(rmax, red);
+      if (rmax < a.eps_mg || ncyc == kMaxMgCycles) break;
+    }
     // Picard update p <- p + dp and ||dp||_inf
     double mx = 0.0, bad = 0.0;
     for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
@@ -202,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     const double anybad = block_max(bad, red);
     ++it;
     ++tot_its;
-    cycles += a.cpp;
+    cycles += ncyc;
     if (anybad > 0.0) {
       status = RMG_SAMPLE_NONFINITE;
       break;

@@ -190,6 +190,37 @@ def test_w_cycle_matches_twin_oracle(n, precision, flags, tol):
             assert int(out["stats"]["mg_cycles"][i]) == sum(r["picard"])
 
 
+@pytest.mark.parametrize("n,precision,tol", [(16, rmg.FP64, 1e-10), (32, rmg.FP64, 1e-10), (32, rmg.MIXED, 1e-8)])
+def test_paper_mode_w_cycles_to_eps_mg_match_twin_oracle(n, precision, tol):
+    """The paper's multigrid setting (Section 4.2): W(2,2) cycles repeated until the
+    correction equation's residual max |f - A dp| is below eps_mg = 1e-5.  FP64: the same
+    cycle count as the oracle in every Picard step (summed over the solve)."""
+    S = 3
+    say(f"paper mode W + eps_mg n={n} precision={precision}")
+    B, xi, fields = _fields(n, S, wid=15)
+    prob = rmg.Problem(n_steps=3)
+    opts = rmg.SolverOpts(precision=precision, cycle=rmg.CYCLE_W, cycles_per_picard=0, eps_mg=1e-5)
+    out = rmg.picard_mg_solve(n, fields, prob, opts)
+    torch.cuda.synchronize()
+    h = out["h"].cpu().numpy()
+    oopts = dict(W.SOLVER, cycle="W", cycles_per_picard=0, eps_mg=1e-5)
+    for i in range(S):
+        r = oracle_solve(n, oracle_fields(B, xi[i, 0]), dict(W.GARDNER_INFILTRATION, n_steps=3), oopts)
+        assert r["status"] == 0 and out["status"][i].item() == 0
+        assert rel_inf(h[i], r["p"].reshape(-1)) < tol, i
+        if precision == rmg.FP64:
+            assert int(out["stats"]["picard_its"][i]) == sum(r["picard"])
+            assert int(out["stats"]["mg_cycles"][i]) == r["cycles"]
+        assert int(out["stats"]["mg_cycles"][i]) > int(out["stats"]["picard_its"][i])
+
+
+def test_eps_mg_mode_is_rejected_on_streaming_grids():
+    _, _, fields = _fields(128, 1, wid=16)
+    with pytest.raises(rmg.RmgError) as e:
+        rmg.picard_mg_solve(128, fields, rmg.Problem(n_steps=1), rmg.SolverOpts(cycles_per_picard=0))
+    assert e.value.code == -1
+
+
 def test_w_cycle_streaming_equals_whole_sample_bitwise():
     n, S = 64, 4
     say("W-cycle streaming vs whole-sample n=64")
@@ -255,7 +286,7 @@ def test_invalid_arguments_raise():
     _, _, fields = _fields(16, 2, wid=9)
     ctx = rmg.default_context()
     for kw in (dict(nu1=0, nu2=0), dict(coarsest_n=8), dict(max_picard=0), dict(eps_picard=0.0),
-               dict(cycle=3), dict(cycles_per_picard=-1)):
+               dict(cycle=3), dict(cycles_per_picard=-1), dict(cycles_per_picard=0, eps_mg=0.0)):
         with pytest.raises(rmg.RmgError) as e:
             ctx.picard_mg_solve(16, fields, rmg.Problem(), rmg.SolverOpts(**kw))
         assert e.value.code == -1
