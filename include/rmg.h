@@ -131,26 +131,32 @@ typedef struct {
 } rmg_dd;
 
 /* Sums over the successful pairs of one MLMC level (Section 5.1, eqs. SMC, MC_var):
- * Y = Q_fine - Q_coarse (Q_coarse = 0 on level 0). */
+ * Y = Q_fine - Q_coarse (Q_coarse = 0 on a base level, one with n_coarse = 0). */
 typedef struct {
-  int64_t n, n_failed, picard_its, mg_cycles;
+  int64_t n, n_failed;          /* successful pairs (the sums run over these), failed pairs */
+  int64_t picard_its;           /* Picard iterations of both members of every pair, failed included */
+  int64_t mg_cycles;            /* multigrid cycles, likewise */
+  int64_t mg_cycles_coarse;     /* the part of mg_cycles spent by the coarse members */
   rmg_dd sY, sY2, sQf, sQf2, sQc, sQc2;
 } rmg_level_sums;
 
-/* One MLMC level: fine grid n_fine, coarse partner n_coarse = n_fine / 2
- * (0 on level 0), n_samples pairs sharing their KL draws (Section 5.1: the two
+/* One MLMC level: fine grid n_fine, coarse partner n_coarse = n_fine / 2 for a
+ * correction level or 0 for a base level (the coarsest level of the hierarchy;
+ * any entry of a call may be either, so samples can be added to one correction
+ * level alone), n_samples pairs sharing their KL draws (Section 5.1: the two
  * members of a correction use the same random input). */
 typedef struct {
   int32_t n_fine, n_coarse;
   int64_t n_samples;
   rmg_problem fine, coarse;       /* per-level problems (continuation may differ) */
   const double* d_basis_fine;     /* [n_modes][n_fine^2] */
-  const double* d_basis_coarse;   /* [n_modes][n_coarse^2], NULL on level 0 */
+  const double* d_basis_coarse;   /* [n_modes][n_coarse^2], NULL when n_coarse = 0 */
   const double* d_xi;             /* [n_samples][n_fields][n_modes] standard normals */
 } rmg_level;
 
 /* Size in bytes of the named ABI struct ("rmg_problem", "rmg_solver_opts", "rmg_kernel_timing",
- * "rmg_sample_stats", "rmg_level_sums", "rmg_level", "rmg_marginal"), or -1 if
+ * "rmg_sample_stats", "rmg_level_sums", "rmg_level", "rmg_marginal", "rmg_pc_level",
+ * "rmg_pc_opts", "rmg_pc_level_out", "rmg_pc_result"), or -1 if
  * unknown; lets bindings check their struct layouts against this build. */
 int64_t rmg_struct_size(const char* name);
 
@@ -232,14 +238,108 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
  *   level, the fine QoIs then the coarse QoIs (NaN marks failure); may be NULL.
  * Synchronises with `stream` before returning.  Returns RMG_ENOTCONV if some
  * sample failed.  EINVAL as for picard_mg_solve, plus: n_levels not in 1..16,
- * n_fine not a power of two in 4..1024, n_coarse != n_fine / 2 on levels >= 1 or
- * != 0 on level 0, a grid size used by more than one fine and one coarse segment,
+ * n_fine not a power of two in 4..1024, n_coarse neither 0 nor n_fine / 2,
+ * a grid size used by more than one fine and one coarse segment,
  * more than 65535 solves on one grid size, NULL basis/xi pointers.
  */
 int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* h_levels,
                         int n_fields, int n_modes, const rmg_marginal* h_marg,
                         const rmg_solver_opts* opts, rmg_level_sums* h_out,
                         double* d_qoi_out, hipStream_t stream);
+
+/*
+ * Adaptive multilevel estimator with parametric continuation (PC_MLMC,
+ * Section 5.1: Algorithm 1, eqs. errMLMC, MLMCopt and MLMCSAMP; bias estimate
+ * eq. discErr of Section 6).
+ *
+ * Level l of the hierarchy has a grid D_l (n_fine), a time grid and a
+ * nonlinearity parameter set Theta_l (its rmg_problem).  Level 0 is the base
+ * level (n_coarse = 0); level l >= 1 pairs its fine solve with a coarse solve on
+ * n_coarse = n_fine / 2 under the problem of level l - 1, which must equal level
+ * l - 1's fine problem byte for byte (the telescoping sum, eq. telescope).
+ */
+typedef struct {
+  int32_t n_fine, n_coarse;     /* as rmg_level */
+  int64_t n_warmup;             /* warm-up pairs N*_l, >= 2 */
+  rmg_problem fine, coarse;     /* Theta_l, and Theta_{l-1} (ignored on level 0) */
+  const double* d_basis_fine;   /* [n_modes][n_fine^2] */
+  const double* d_basis_coarse; /* [n_modes][n_coarse^2], NULL on level 0 */
+} rmg_pc_level;
+
+/* Cost per pair W_l (Algorithm 1 lets it be estimated from the warm-up):
+ *   RMG_COST_WORK: multigrid cycles times cells per pair (fine and coarse member),
+ *     the paper's own cost unit (Section 4.3 counts cycles), scaled by grid size;
+ *   RMG_COST_TIME: wall milliseconds per pair of the level's warm-up batch, run
+ *     alone (on a batched GPU a small batch measures latency more than cost). */
+typedef enum { RMG_COST_WORK = 0, RMG_COST_TIME = 1 } rmg_cost_model;
+
+typedef struct {
+  double eps;                   /* sampling tolerance: stop once sum_l V_l / N_l <= eps^2 */
+  double bias_rate;             /* a of eq. numErr, > 0, for the eq. discErr bias estimate */
+  int32_t cost_model;           /* rmg_cost_model */
+  int32_t max_rounds;           /* updates of N_l (Algorithm 1 steps 3-4) allowed, 1..10000 */
+  int64_t max_pairs;            /* pairs that may be drawn on one level in total, >= n_warmup */
+  int64_t max_pairs_per_call;   /* pairs of one level per batched solve, 0..32767 (0: sized
+                                   from the device's free memory) */
+} rmg_pc_opts;
+
+/* Source of the random input: write the standard normals of pairs first ..
+ * first + count - 1 of level `level` to h_xi [count][n_fields][n_modes] (host
+ * memory owned by the library).  Pairs are numbered per level from 0 and never
+ * reused; a failed pair's number is not drawn again.  Return 0, or nonzero to
+ * abort the run (pc_mlmc then returns RMG_EINVAL). */
+typedef int (*rmg_xi_source)(void* user, int level, int64_t first, int64_t count, double* h_xi);
+
+typedef struct {
+  int64_t drawn;                /* pairs drawn: numbers 0 .. drawn - 1 */
+  int64_t target;               /* N_l from the last update of eq. MLMCSAMP (N*_l before it) */
+  double W;                     /* cost per drawn pair (unit of the cost model) */
+  double V;                     /* sample variance of Y_l over the successful pairs (eq. level_var) */
+  double mean;                  /* E^MC_{N_l}[Y_l] (eq. SMC) */
+  rmg_level_sums sums;          /* accumulated over every batch of the run */
+} rmg_pc_level_out;
+
+typedef struct {
+  double mean;                  /* multilevel estimate of E[Q_L] (eq. MLMCestimator) */
+  double var;                   /* multilevel estimate of V[Q_L] (eq. ML_var) */
+  double sampling_err2;         /* sum_l V_l / N_l with N_l the successful pairs (eq. MLMCVar) */
+  double bias;                  /* sqrt(mean over pairs of Y_L^2) / (2^a - 1) (eq. discErr, s = 2) */
+  double total_cost;            /* sum_l drawn_l W_l */
+  double wall_ms;               /* wall time of the whole call */
+  int32_t rounds;               /* updates of N_l performed */
+  int32_t converged;            /* 1 if sampling_err2 <= eps^2 with no pair left to draw */
+  int64_t calls;                /* batched mlmc_level_estimate calls made */
+} rmg_pc_result;
+
+/*
+ * pc_mlmc - Algorithm 1 on the device: warm-up N*_l pairs on every level, then
+ * repeatedly set N_l by eq. MLMCSAMP from the current V_l and the warm-up W_l,
+ * draw the missing pairs of every level in one batched mlmc_level_estimate call
+ * (several if a level needs more than max_pairs_per_call), and update the sums,
+ * until no level needs more pairs.  Failed pairs are excluded from the sums and
+ * replaced by new draws.  The random input comes from `xi`, in host memory; the
+ * library copies it to the device (it allocates a staging buffer of
+ * max_pairs_per_call pairs per level for the call and frees it on return).
+ *   h_levels, h_level_out [n_levels], h_marg [n_fields], h_result: host.
+ * Returns RMG_OK once converged; RMG_ENOTCONV if max_rounds or max_pairs ended
+ * the run first (outputs hold the state reached) or a level's warm-up left fewer
+ * than two successful pairs within max_pairs (outputs not filled); EINVAL for
+ * arguments outside the ranges above or those of mlmc_level_estimate, a
+ * hierarchy whose level l coarse member differs from level l - 1's fine member,
+ * or a nonzero return of `xi`.  Other errors of mlmc_level_estimate pass through.
+ */
+int pc_mlmc(rmg_ctx* ctx, int n_levels, const rmg_pc_level* h_levels, int n_fields, int n_modes,
+            const rmg_marginal* h_marg, const rmg_solver_opts* opts, const rmg_pc_opts* pc,
+            rmg_xi_source xi, void* user, rmg_pc_level_out* h_level_out, rmg_pc_result* h_result,
+            hipStream_t stream);
+
+/*
+ * Eq. MLMCSAMP: N_l = ceil(eps^-2 (sum_k sqrt(V_k W_k)) sqrt(V_l / W_l)), the
+ * sample counts minimising sum_l N_l W_l subject to sum_l V_l / N_l = eps^2
+ * (eq. MLMCopt).  Host arithmetic only (no device needed).  V_l >= 0, W_l > 0,
+ * eps > 0, 1..16 levels, else RMG_EINVAL; a count above 2^62 is RMG_EINVAL too.
+ */
+int rmg_mlmc_optimal_samples(int n_levels, const double* V, const double* W, double eps, int64_t* N_out);
 
 #ifdef __cplusplus
 }

@@ -8,6 +8,8 @@ enqueued on the current torch stream.
     sample_fields(n, basis, xi, marginals)           KL fields (Section 3)
     picard_mg_solve(n, fields, problem, opts)        S samples on one grid (Sections 4.1-4.2)
     mlmc_level_estimate(levels, marginals, opts)     batched MLMC level sums (Section 5.1)
+    pc_mlmc(levels, marginals, opts, eps, xi_source) adaptive PC_MLMC (Section 5.1, Algorithm 1)
+    optimal_samples(eps, V, W)                       eq. MLMCSAMP (host)
 """
 from __future__ import annotations
 
@@ -15,13 +17,13 @@ import ctypes as C
 from dataclasses import dataclass, field, fields as dc_fields
 
 from . import _abi
-from ._abi import (CYCLE_V, CYCLE_W, FLAG_COARSE_TOP_32, FLAG_EAGER, FLAG_FORCE_STREAMING, FLAG_NO_AUTOTUNE,  # noqa: F401
+from ._abi import (COST_TIME, COST_WORK, CYCLE_V, CYCLE_W, FLAG_COARSE_TOP_32, FLAG_EAGER, FLAG_FORCE_STREAMING, FLAG_NO_AUTOTUNE,  # noqa: F401
                    FLAG_STATE_GLOBAL, FLAG_TILES_16, FLAG_WHOLE_WHERE_FITS, FP64, GARDNER, LINEAR, MIXED,
                    QOI_MEAN_SATURATION, RMG_ENOTCONV, RMG_OK, SAMPLE_MAXITER, SAMPLE_NONFINITE,
                    SAMPLE_OK, VGM)
 
 __all__ = ["Problem", "SolverOpts", "Context", "RmgError", "sample_fields", "picard_mg_solve",
-           "mlmc_level_estimate", "default_context"]
+           "mlmc_level_estimate", "pc_mlmc", "optimal_samples", "default_context"]
 
 
 class RmgError(RuntimeError):
@@ -203,14 +205,80 @@ class Context:
                                            C.c_void_p(q.data_ptr()) if q is not None else None,
                                            _stream_ptr(stream))
         self._raise(rc, allow_notconv=True)
-        sums = []
-        for s in out:
-            d = {k: getattr(s, k) for k in ("n", "n_failed", "picard_its", "mg_cycles")}
-            for k in ("sY", "sY2", "sQf", "sQf2", "sQc", "sQc2"):
-                v = getattr(s, k)
-                d[k] = (v.hi, v.lo)
-            sums.append(d)
-        return sums, q, rc
+        return [_decode_sums(s) for s in out], q, rc
+
+    def pc_mlmc(self, levels, marginals, opts: SolverOpts, eps: float, xi_source, bias_rate=1.0,
+                cost_model=_abi.COST_WORK, max_rounds=50, max_pairs=1 << 40, max_pairs_per_call=0,
+                stream=None):
+        """Adaptive PC_MLMC (Algorithm 1).  levels: list of dict(n_fine, n_coarse, n_warmup,
+        fine: Problem, coarse: Problem|None, basis_fine, basis_coarse); xi_source(level, first,
+        count) returns a float64 array [count][n_fields][n_modes] of standard normals.
+        Returns dict(levels=[per-level dicts], mean, var, sampling_err2, bias, total_cost,
+        wall_ms, rounds, converged, calls, rc)."""
+        import numpy as np
+        torch = _torch()
+        L = len(levels)
+        F = len(marginals)
+        M = levels[0]["basis_fine"].shape[0]
+        arr = (_abi.PcLevel * L)()
+        for i, lv in enumerate(levels):
+            _check_dev(lv["basis_fine"], f"levels[{i}].basis_fine", torch.float64, (M, lv["n_fine"] ** 2))
+            bc = lv.get("basis_coarse")
+            if lv["n_coarse"]:
+                _check_dev(bc, f"levels[{i}].basis_coarse", torch.float64, (M, lv["n_coarse"] ** 2))
+            coarse = lv.get("coarse") or lv["fine"]
+            arr[i] = _abi.PcLevel(lv["n_fine"], lv["n_coarse"], int(lv["n_warmup"]), lv["fine"].c(), coarse.c(),
+                                  C.c_void_p(lv["basis_fine"].data_ptr()),
+                                  C.c_void_p(bc.data_ptr()) if bc is not None else None)
+        failure = []
+
+        def _src(_user, level, first, count, h_xi):
+            try:
+                x = np.ascontiguousarray(xi_source(level, first, count), dtype=np.float64)
+                if x.shape != (count, F, M):
+                    raise ValueError(f"xi_source returned shape {x.shape}, expected {(count, F, M)}")
+                C.memmove(h_xi, x.ctypes.data, x.nbytes)
+                return 0
+            except BaseException as e:  # reported after the call returns
+                failure.append(e)
+                return 1
+
+        cb = _abi.XiSource(_src)
+        marg = (_abi.Marginal * F)(*[_abi.Marginal(*m) for m in marginals])
+        po = _abi.PcOpts(float(eps), float(bias_rate), int(cost_model), int(max_rounds), int(max_pairs),
+                         int(max_pairs_per_call))
+        lout = (_abi.PcLevelOut * L)()
+        res = _abi.PcResult()
+        op = opts.c()
+        rc = self._lib.pc_mlmc(self._h, L, arr, F, M, marg, C.byref(op), C.byref(po), cb, None, lout,
+                               C.byref(res), _stream_ptr(stream))
+        if failure:
+            raise failure[0]
+        self._raise(rc, allow_notconv=True)
+        out = {k: getattr(res, k) for k in ("mean", "var", "sampling_err2", "bias", "total_cost", "wall_ms",
+                                            "rounds", "converged", "calls")}
+        out["levels"] = [dict(drawn=o.drawn, target=o.target, W=o.W, V=o.V, mean=o.mean,
+                              sums=_decode_sums(o.sums)) for o in lout]
+        out["rc"] = rc
+        return out
+
+
+def _decode_sums(s) -> dict:
+    d = {k: getattr(s, k) for k in ("n", "n_failed", "picard_its", "mg_cycles", "mg_cycles_coarse")}
+    for k in ("sY", "sY2", "sQf", "sQf2", "sQc", "sQc2"):
+        v = getattr(s, k)
+        d[k] = (v.hi, v.lo)
+    return d
+
+
+def optimal_samples(eps, V, W):
+    """Eq. MLMCSAMP evaluated by the library (host arithmetic; no device needed)."""
+    L = len(V)
+    Va, Wa, N = (C.c_double * L)(*V), (C.c_double * L)(*W), (C.c_int64 * L)()
+    rc = _abi.lib().rmg_mlmc_optimal_samples(L, Va, Wa, float(eps), N)
+    if rc != RMG_OK:
+        raise RmgError(rc, "rmg_mlmc_optimal_samples: invalid arguments")
+    return list(N)
 
 
 def _decode_stats(raw):
@@ -241,3 +309,8 @@ def picard_mg_solve(n, fields, problem: Problem, opts: SolverOpts, stream=None):
 def mlmc_level_estimate(levels, marginals, opts: SolverOpts, return_qoi=False, stream=None):
     dev = levels[0]["xi"].device.index or 0
     return default_context(dev).mlmc_level_estimate(levels, marginals, opts, return_qoi, stream)
+
+
+def pc_mlmc(levels, marginals, opts: SolverOpts, eps: float, xi_source, **kw):
+    dev = levels[0]["basis_fine"].device.index or 0
+    return default_context(dev).pc_mlmc(levels, marginals, opts, eps, xi_source, **kw)

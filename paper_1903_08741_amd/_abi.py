@@ -25,9 +25,11 @@ FLAG_TILES_16 = 16
 FLAG_WHOLE_WHERE_FITS = 32
 FLAG_COARSE_TOP_32 = 64
 
+COST_WORK, COST_TIME = 0, 1
+
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
             "sample_fields", "picard_mg_solve", "mlmc_level_estimate", "rmg_set_kernel_timing",
-            "rmg_get_kernel_timing")
+            "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples")
 
 
 class Marginal(C.Structure):
@@ -58,7 +60,7 @@ class DD(C.Structure):
 
 class LevelSums(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_failed", C.c_int64), ("picard_its", C.c_int64),
-                ("mg_cycles", C.c_int64), ("sY", DD), ("sY2", DD), ("sQf", DD), ("sQf2", DD),
+                ("mg_cycles", C.c_int64), ("mg_cycles_coarse", C.c_int64), ("sY", DD), ("sY2", DD), ("sQf", DD), ("sQf2", DD),
                 ("sQc", DD), ("sQc2", DD)]
 
 
@@ -66,6 +68,32 @@ class Level(C.Structure):
     _fields_ = [("n_fine", C.c_int32), ("n_coarse", C.c_int32), ("n_samples", C.c_int64),
                 ("fine", Problem), ("coarse", Problem), ("d_basis_fine", C.c_void_p),
                 ("d_basis_coarse", C.c_void_p), ("d_xi", C.c_void_p)]
+
+
+class PcLevel(C.Structure):
+    _fields_ = [("n_fine", C.c_int32), ("n_coarse", C.c_int32), ("n_warmup", C.c_int64),
+                ("fine", Problem), ("coarse", Problem), ("d_basis_fine", C.c_void_p),
+                ("d_basis_coarse", C.c_void_p)]
+
+
+class PcOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("bias_rate", C.c_double), ("cost_model", C.c_int32),
+                ("max_rounds", C.c_int32), ("max_pairs", C.c_int64), ("max_pairs_per_call", C.c_int64)]
+
+
+class PcLevelOut(C.Structure):
+    _fields_ = [("drawn", C.c_int64), ("target", C.c_int64), ("W", C.c_double), ("V", C.c_double),
+                ("mean", C.c_double), ("sums", LevelSums)]
+
+
+class PcResult(C.Structure):
+    _fields_ = [("mean", C.c_double), ("var", C.c_double), ("sampling_err2", C.c_double),
+                ("bias", C.c_double), ("total_cost", C.c_double), ("wall_ms", C.c_double),
+                ("rounds", C.c_int32), ("converged", C.c_int32), ("calls", C.c_int64)]
+
+
+# int (*rmg_xi_source)(void* user, int level, int64_t first, int64_t count, double* h_xi)
+XiSource = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.POINTER(C.c_double))
 
 
 class KernelTiming(C.Structure):
@@ -76,7 +104,9 @@ class KernelTiming(C.Structure):
 TIME_NONE, TIME_SMOOTHER_DOWN = 0, 1
 
 STRUCTS = {"rmg_kernel_timing": KernelTiming, "rmg_problem": Problem, "rmg_solver_opts": SolverOpts, "rmg_sample_stats": SampleStats,
-           "rmg_level_sums": LevelSums, "rmg_level": Level, "rmg_marginal": Marginal}
+           "rmg_level_sums": LevelSums, "rmg_level": Level, "rmg_marginal": Marginal,
+           "rmg_pc_level": PcLevel, "rmg_pc_opts": PcOpts, "rmg_pc_level_out": PcLevelOut,
+           "rmg_pc_result": PcResult}
 
 _lib = None
 
@@ -107,6 +137,12 @@ def lib():
     L.mlmc_level_estimate.argtypes = [vp, i32, C.POINTER(Level), i32, i32, C.POINTER(Marginal),
                                       C.POINTER(SolverOpts), C.POINTER(LevelSums), vp, vp]
     L.mlmc_level_estimate.restype = i32
+    L.pc_mlmc.argtypes = [vp, i32, C.POINTER(PcLevel), i32, i32, C.POINTER(Marginal), C.POINTER(SolverOpts),
+                          C.POINTER(PcOpts), XiSource, vp, C.POINTER(PcLevelOut), C.POINTER(PcResult), vp]
+    L.pc_mlmc.restype = i32
+    L.rmg_mlmc_optimal_samples.argtypes = [i32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                                           C.POINTER(C.c_int64)]
+    L.rmg_mlmc_optimal_samples.restype = i32
     L.rmg_set_kernel_timing.argtypes = [vp, i32]
     L.rmg_set_kernel_timing.restype = i32
     L.rmg_get_kernel_timing.argtypes = [vp, C.POINTER(KernelTiming)]

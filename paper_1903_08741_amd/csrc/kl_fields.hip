@@ -86,10 +86,11 @@ __global__ void k_level_sums(const double* qf, const double* qc, int64_t n, cons
                              const rmg_sample_stats* sc, rmg_level_sums* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Neu y = {0, 0}, y2 = {0, 0}, f = {0, 0}, f2 = {0, 0}, c = {0, 0}, c2 = {0, 0};
-  int64_t ok = 0, bad = 0, its = 0, cyc = 0;
+  int64_t ok = 0, bad = 0, its = 0, cyc = 0, cyc_c = 0;
   for (int64_t i = 0; i < n; ++i) {
     its += sf[i].picard_its + (sc ? sc[i].picard_its : 0);
     cyc += sf[i].mg_cycles + (sc ? sc[i].mg_cycles : 0);
+    cyc_c += sc ? sc[i].mg_cycles : 0;
     const bool good = stf[i] == RMG_SAMPLE_OK && (!stc || stc[i] == RMG_SAMPLE_OK);
     if (!good) {
       ++bad;
@@ -109,6 +110,7 @@ __global__ void k_level_sums(const double* qf, const double* qc, int64_t n, cons
   o.n_failed = bad;
   o.picard_its = its;
   o.mg_cycles = cyc;
+  o.mg_cycles_coarse = cyc_c;
   o.sY = {y.s, y.c};
   o.sY2 = {y2.s, y2.c};
   o.sQf = {f.s, f.c};

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/rmg.h"
+#include "rmg_host.hpp"
 #include "rmg_internal.hpp"
 
 using namespace rmg;
@@ -443,6 +444,13 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
 
 }  // namespace
 
+int rmg::set_error(rmg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int rmg::device_of(const rmg_ctx* c) { return c->device; }
+
 extern "C" {
 
 int64_t rmg_struct_size(const char* name) {
@@ -455,6 +463,10 @@ int64_t rmg_struct_size(const char* name) {
   if (s == "rmg_level") return sizeof(rmg_level);
   if (s == "rmg_marginal") return sizeof(rmg_marginal);
   if (s == "rmg_kernel_timing") return sizeof(rmg_kernel_timing);
+  if (s == "rmg_pc_level") return sizeof(rmg_pc_level);
+  if (s == "rmg_pc_opts") return sizeof(rmg_pc_opts);
+  if (s == "rmg_pc_level_out") return sizeof(rmg_pc_level_out);
+  if (s == "rmg_pc_result") return sizeof(rmg_pc_result);
   return -1;
 }
 
@@ -681,15 +693,19 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
   for (int l = 0; l < n_levels; ++l) {
     const rmg_level& v = L[l];
     if (!pow2_in(v.n_fine, 4, 1024)) return fail(ctx, RMG_EINVAL, "level %d: bad n_fine %d", l, v.n_fine);
-    if (l == 0 ? v.n_coarse != 0 : v.n_coarse * 2 != v.n_fine)
-      return fail(ctx, RMG_EINVAL, "level %d: n_coarse must be %s", l, l == 0 ? "0" : "n_fine/2");
-    if (v.n_samples < 1 || !v.d_basis_fine || !v.d_xi || (l > 0 && !v.d_basis_coarse))
+    // an entry is a base level (no coarse member, n_coarse = 0) or a correction
+    // level (n_coarse = n_fine / 2); any entry may be either, so a caller can
+    // add samples to one correction level alone
+    const bool corr = v.n_coarse != 0;
+    if (corr && v.n_coarse * 2 != v.n_fine)
+      return fail(ctx, RMG_EINVAL, "level %d: n_coarse must be 0 or n_fine/2", l);
+    if (v.n_samples < 1 || !v.d_basis_fine || !v.d_xi || (corr && !v.d_basis_coarse))
       return fail(ctx, RMG_EINVAL, "level %d: bad samples or NULL pointer", l);
     if ((rc = check_problem(ctx, &v.fine, n_fields))) return rc;
-    if (l > 0 && (rc = check_problem(ctx, &v.coarse, n_fields))) return rc;
-    if ((rc = check_opts(ctx, opts, l > 0 ? v.n_coarse : v.n_fine))) return rc;
+    if (corr && (rc = check_problem(ctx, &v.coarse, n_fields))) return rc;
+    if ((rc = check_opts(ctx, opts, corr ? v.n_coarse : v.n_fine))) return rc;
     cls[v.n_fine].push_back({l, 0});
-    if (l > 0) cls[v.n_coarse].push_back({l, 1});
+    if (corr) cls[v.n_coarse].push_back({l, 1});
   }
   for (auto& kv : cls) {
     if (kv.second.size() > 2) return fail(ctx, RMG_EINVAL, "grid %d used by more than two segments", kv.first);
@@ -826,7 +842,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     const int32_t *sf, *sc = nullptr;
     const rmg_sample_stats *tf, *tc = nullptr;
     locate(v.n_fine, 0, &qf, &sf, &tf);
-    if (l > 0) locate(v.n_coarse, 1, &qc, &sc, &tc);
+    if (v.n_coarse) locate(v.n_coarse, 1, &qc, &sc, &tc);
     HIP_TRY(ctx, launch_level_sums(qf, qc, v.n_samples, sf, sc, tf, tc, d_sums + l, stream));
     if (d_qoi_out) {
       HIP_TRY(ctx, hipMemcpyAsync(d_qoi_out + qoff, qf, 8 * v.n_samples, hipMemcpyDeviceToDevice, stream));
