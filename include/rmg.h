@@ -64,7 +64,8 @@ typedef struct {
 } rmg_marginal;
 
 /* One deterministic problem (closure model, boundary and initial data, time grid).
- * qoi must be RMG_QOI_MEAN_SATURATION in this build (the outflux QoI: RMG_EINVAL);
+ * qoi must be RMG_QOI_MEAN_SATURATION for the forward entry points; the bottom
+ * outflux (RMG_QOI_BOTTOM_OUTFLUX) is the quantity of picard_mg_adjoint;
  * theta_s > theta_r, dt > 0 and n_steps >= 1 are required.
  * Fields per cell: Gardner and linear use field 0 = Ks; van Genuchten-Mualem uses
  * field 0 = Ks, 1 = alpha, 2 = n (so n_fields = 1 or 3).
@@ -246,6 +247,42 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* h_levels,
                         int n_fields, int n_modes, const rmg_marginal* h_marg,
                         const rmg_solver_opts* opts, rmg_level_sums* h_out,
                         double* d_qoi_out, hipStream_t stream);
+
+/*
+ * picard_mg_adjoint - per-sample quantity of interest and its gradient with respect
+ * to the KL coefficients by the discrete adjoint of the backward-Euler /
+ * modified-Picard solve (the derivative of the discrete model of Sections 4.1-4.2;
+ * the paper itself has no adjoint).
+ *   Q = sum_{k=1}^{n_steps} dt F(p^k),  F(p) = h sum_i K_i0 ((p_i0 - h_bottom) / (h/2) + 1),
+ * the time-integrated downward flux through the bottom Dirichlet face (problem->qoi
+ * must be RMG_QOI_BOTTOM_OUTFLUX).  Ks = h_marg->shift + exp(h_marg->log_mean +
+ * h_marg->scale * G), G = sum_j d_xi[s][j] d_basis[j][c] (eqs. KLexp, RandK).
+ * Backward in time, step k solves J_k^T lambda_k = dt dF/dp(p^k) - diag(C(p^k)/dt)
+ * lambda_{k+1} with J_k the exact Jacobian of the step residual at p^k (the
+ * modified-Picard operator plus the dK/dp terms) by the fixed-point iteration
+ * preconditioned with the forward multigrid cycle on the Picard operator; it stops
+ * when the correction's max norm is below eps_adjoint (at most opts->max_picard
+ * iterations per step).  The forward pass stores p every ckpt_every steps; the
+ * backward pass recomputes each segment of ckpt_every steps from its checkpoint
+ * (ckpt_every = 1: every step is stored, nothing is recomputed).
+ *   d_basis [n_modes][n*n], d_xi [S][n_modes] FP64 (device);
+ *   d_q [S], d_grad [S][n_modes] FP64: Q and dQ/dxi (NaN for a failed sample);
+ *   d_status [S] int32: rmg_sample_status of the forward solve, or of the adjoint
+ *   iteration if the forward converged;
+ *   d_stats: NULL or [2][S]: the forward solves' statistics, then the adjoint's
+ *   (picard_its = fixed-point iterations, mg_cycles = their cycles).
+ * Gardner and linear closures only (n_fields = 1).  The adjoint iteration runs on
+ * the level-streaming kernels with max(1, cycles_per_picard) cycles per iteration
+ * in the precision of opts (the residual of the adjoint system is FP64 in both).
+ * Synchronises with `stream`; RMG_ENOTCONV if some sample failed.  EINVAL: n not a
+ * power of two in 4..1024, S not in 1..65535, n_modes not in 1..1024, another
+ * closure or QoI, ckpt_every not dividing n_steps, eps_adjoint <= 0, NULL pointers,
+ * and the problem / option ranges of picard_mg_solve.
+ */
+int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+                      int n_modes, const double* d_basis, const rmg_marginal* h_marg, const double* d_xi,
+                      int64_t S, int ckpt_every, double eps_adjoint, double* d_q, double* d_grad,
+                      int32_t* d_status, rmg_sample_stats* d_stats, hipStream_t stream);
 
 /*
  * Adaptive multilevel estimator with parametric continuation (PC_MLMC,

@@ -9,6 +9,8 @@ enqueued on the current torch stream.
     picard_mg_solve(n, fields, problem, opts)        S samples on one grid (Sections 4.1-4.2)
     mlmc_level_estimate(levels, marginals, opts)     batched MLMC level sums (Section 5.1)
     pc_mlmc(levels, marginals, opts, eps, xi_source) adaptive PC_MLMC (Section 5.1, Algorithm 1)
+    picard_mg_adjoint(n, basis, xi, marginal, ...)   outflux QoI and dQ/dxi by the discrete adjoint
+    outflux_qoi(xi, basis, n, marginal, ...)         the same as a torch.autograd.Function
     optimal_samples(eps, V, W)                       eq. MLMCSAMP (host)
 """
 from __future__ import annotations
@@ -23,7 +25,8 @@ from ._abi import (COST_TIME, COST_WORK, CYCLE_V, CYCLE_W, FLAG_COARSE_TOP_32, F
                    SAMPLE_OK, VGM)
 
 __all__ = ["Problem", "SolverOpts", "Context", "RmgError", "sample_fields", "picard_mg_solve",
-           "mlmc_level_estimate", "pc_mlmc", "optimal_samples", "default_context"]
+           "mlmc_level_estimate", "pc_mlmc", "optimal_samples", "picard_mg_adjoint", "outflux_qoi",
+           "default_context"]
 
 
 class RmgError(RuntimeError):
@@ -207,6 +210,33 @@ class Context:
         self._raise(rc, allow_notconv=True)
         return [_decode_sums(s) for s in out], q, rc
 
+    def picard_mg_adjoint(self, n, basis, xi, marginal, problem: Problem, opts: SolverOpts, ckpt_every=1,
+                          eps_adjoint=1e-12, stream=None):
+        """Time-integrated bottom outflux Q per sample and dQ/dxi by the discrete adjoint.
+        basis [M][n*n], xi [S][M] float64 device tensors; marginal (shift, log_mean, scale) of Ks.
+        Returns dict(q [S], grad [S][M], status [S], stats_forward, stats_adjoint, rc)."""
+        torch = _torch()
+        S, M = xi.shape
+        _check_dev(xi, "xi", torch.float64, (S, M))
+        _check_dev(basis, "basis", torch.float64, (M, n * n))
+        dev = xi.device
+        q = torch.empty(S, dtype=torch.float64, device=dev)
+        grad = torch.empty(S, M, dtype=torch.float64, device=dev)
+        status = torch.empty(S, dtype=torch.int32, device=dev)
+        stats = torch.empty(2 * S * C.sizeof(_abi.SampleStats), dtype=torch.uint8, device=dev)
+        pr = problem.c()
+        pr.qoi = _abi.QOI_BOTTOM_OUTFLUX
+        op = opts.c()
+        mg = _abi.Marginal(*marginal)
+        rc = self._lib.picard_mg_adjoint(self._h, int(n), C.byref(pr), C.byref(op), int(M),
+                                         C.c_void_p(basis.data_ptr()), C.byref(mg), C.c_void_p(xi.data_ptr()),
+                                         int(S), int(ckpt_every), float(eps_adjoint), C.c_void_p(q.data_ptr()),
+                                         C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()),
+                                         C.c_void_p(stats.data_ptr()), _stream_ptr(stream))
+        self._raise(rc, allow_notconv=True)
+        st = _decode_stats(stats)
+        return dict(q=q, grad=grad, status=status, stats_forward=st[:S], stats_adjoint=st[S:], rc=rc)
+
     def pc_mlmc(self, levels, marginals, opts: SolverOpts, eps: float, xi_source, bias_rate=1.0,
                 cost_model=_abi.COST_WORK, max_rounds=50, max_pairs=1 << 40, max_pairs_per_call=0,
                 stream=None):
@@ -309,6 +339,47 @@ def picard_mg_solve(n, fields, problem: Problem, opts: SolverOpts, stream=None):
 def mlmc_level_estimate(levels, marginals, opts: SolverOpts, return_qoi=False, stream=None):
     dev = levels[0]["xi"].device.index or 0
     return default_context(dev).mlmc_level_estimate(levels, marginals, opts, return_qoi, stream)
+
+
+def picard_mg_adjoint(n, basis, xi, marginal, problem: Problem, opts: SolverOpts, **kw):
+    return default_context(xi.device.index or 0).picard_mg_adjoint(n, basis, xi, marginal, problem, opts, **kw)
+
+
+def _make_outflux_fn():
+    torch = _torch()
+
+    class OutfluxFn(torch.autograd.Function):
+        """Q(xi) = time-integrated bottom outflux of every sample, differentiable in xi.
+
+        The C entry point runs the forward solve and the adjoint sweep (with its
+        checkpoints) in one call, so the forward pass stores dQ/dxi and the backward
+        pass only scales it by the incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, xi, basis, n, marginal, problem, opts, ckpt_every, eps_adjoint):
+            out = picard_mg_adjoint(n, basis, xi.detach().contiguous(), marginal, problem, opts,
+                                    ckpt_every=ckpt_every, eps_adjoint=eps_adjoint)
+            ctx.save_for_backward(out["grad"])
+            ctx.status = out["status"]
+            return out["q"]
+
+        @staticmethod
+        def backward(ctx, gq):
+            (grad,) = ctx.saved_tensors
+            return gq[:, None] * grad, None, None, None, None, None, None, None
+
+    return OutfluxFn
+
+
+_OUTFLUX_FN = None
+
+
+def outflux_qoi(xi, basis, n, marginal, problem: Problem, opts: SolverOpts, ckpt_every=1, eps_adjoint=1e-12):
+    """Differentiable time-integrated bottom outflux (torch.autograd.Function over the adjoint)."""
+    global _OUTFLUX_FN
+    if _OUTFLUX_FN is None:
+        _OUTFLUX_FN = _make_outflux_fn()
+    return _OUTFLUX_FN.apply(xi, basis, n, marginal, problem, opts, ckpt_every, eps_adjoint)
 
 
 def pc_mlmc(levels, marginals, opts: SolverOpts, eps: float, xi_source, **kw):

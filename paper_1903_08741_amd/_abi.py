@@ -29,7 +29,7 @@ COST_WORK, COST_TIME = 0, 1
 
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
             "sample_fields", "picard_mg_solve", "mlmc_level_estimate", "rmg_set_kernel_timing",
-            "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples")
+            "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples", "picard_mg_adjoint")
 
 
 class Marginal(C.Structure):
@@ -137,6 +137,9 @@ def lib():
     L.mlmc_level_estimate.argtypes = [vp, i32, C.POINTER(Level), i32, i32, C.POINTER(Marginal),
                                       C.POINTER(SolverOpts), C.POINTER(LevelSums), vp, vp]
     L.mlmc_level_estimate.restype = i32
+    L.picard_mg_adjoint.argtypes = [vp, i32, C.POINTER(Problem), C.POINTER(SolverOpts), i32, vp,
+                                    C.POINTER(Marginal), vp, i64, i32, C.c_double, vp, vp, vp, vp, vp]
+    L.picard_mg_adjoint.restype = i32
     L.pc_mlmc.argtypes = [vp, i32, C.POINTER(PcLevel), i32, i32, C.POINTER(Marginal), C.POINTER(SolverOpts),
                           C.POINTER(PcOpts), XiSource, vp, C.POINTER(PcLevelOut), C.POINTER(PcResult), vp]
     L.pc_mlmc.restype = i32

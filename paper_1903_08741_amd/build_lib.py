@@ -18,7 +18,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librmg.so")
-SOURCES = ["solver_kernels.hip", "kl_fields.hip", "rmg_api.cpp", "rmg_pc_mlmc.cpp"]
+SOURCES = ["solver_kernels.hip", "adjoint_kernels.hip", "kl_fields.hip", "rmg_api.cpp", "rmg_pc_mlmc.cpp"]
 
 
 def hipcc() -> str:

@@ -675,6 +675,178 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
   return RMG_OK;
 }
 
+int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts, int n_modes,
+                      const double* d_basis, const rmg_marginal* h_marg, const double* d_xi, int64_t S,
+                      int ckpt_every, double eps_adjoint, double* d_q, double* d_grad, int32_t* d_status,
+                      rmg_sample_stats* d_stats, hipStream_t stream) {
+  if (!ctx) return RMG_EINVAL;
+  ctx->err.clear();
+  if (!pow2_in(n, 4, 1024)) return fail(ctx, RMG_EINVAL, "n=%d must be a power of two in 4..1024", n);
+  if (S < 1 || S > 65535) return fail(ctx, RMG_EINVAL, "S=%lld not in 1..65535", (long long)S);
+  if (n_modes < 1 || n_modes > 1024) return fail(ctx, RMG_EINVAL, "n_modes=%d not in 1..1024", n_modes);
+  if (!problem || !d_basis || !h_marg || !d_xi || !d_q || !d_grad || !d_status)
+    return fail(ctx, RMG_EINVAL, "NULL pointer");
+  if (problem->model != RMG_GARDNER && problem->model != RMG_LINEAR)
+    return fail(ctx, RMG_EINVAL, "the adjoint supports the Gardner and linear closures only");
+  if (problem->qoi != RMG_QOI_BOTTOM_OUTFLUX)
+    return fail(ctx, RMG_EINVAL, "the adjoint's quantity of interest is the bottom outflux (qoi = %d)",
+                (int)RMG_QOI_BOTTOM_OUTFLUX);
+  rmg_problem fprob = *problem;  // the forward kernels compute their own (unused) QoI
+  fprob.qoi = RMG_QOI_MEAN_SATURATION;
+  int rc = check_problem(ctx, &fprob, 1);
+  if (rc) return rc;
+  if ((rc = check_opts(ctx, opts, n))) return rc;
+  const int nst = problem->n_steps;
+  if (ckpt_every < 1 || ckpt_every > nst || nst % ckpt_every != 0)
+    return fail(ctx, RMG_EINVAL, "ckpt_every=%d must divide n_steps=%d", ckpt_every, nst);
+  if (!(eps_adjoint > 0.0)) return fail(ctx, RMG_EINVAL, "eps_adjoint must be > 0");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+  const int64_t N = (int64_t)n * n;
+  const int K = ckpt_every, slots = nst / K + 1;
+  // forward class (its own kernel choice) and adjoint class (level streaming)
+  std::vector<ClassJob> fjobs(1);
+  ClassJob& fj = fjobs[0];
+  fj.a.n = n;
+  fj.a.lg = ilog2i(n);
+  fj.a.nlev = ilog2i(n) - ilog2i(opts->coarsest_n) + 1;
+  fj.a.F = 1;
+  fj.a.S = S;
+  fj.a.cp.prob[0] = fprob;
+  fj.a.cp.prob[1] = fprob;
+  fj.a.cp.seg_split = S;
+  fj.a.nu1 = opts->nu1;
+  fj.a.nu2 = opts->nu2;
+  fj.a.gamma = opts->cycle == RMG_CYCLE_W ? 2 : 1;
+  fj.a.cpp = opts->cycles_per_picard;
+  fj.a.max_picard = opts->max_picard;
+  fj.a.eps = opts->eps_picard;
+  fj.a.eps_mg = opts->eps_mg;
+  class_plan(fj, opts);
+  if (!fj.whole && opts->cycles_per_picard == 0)
+    return fail(ctx, RMG_EINVAL, "grid %d: cycles_per_picard = 0 needs the whole-sample kernel", n);
+  ClassJob aj = fj;
+  rmg_solver_opts aopts = *opts;
+  aopts.flags |= 1 | 8;  // level streaming, fixed tiles
+  class_plan(aj, &aopts);
+  aj.a.cpp = std::max(1, opts->cycles_per_picard);
+
+  // workspace: a dry carve sizes it, the second carve places it
+  struct Bufs {
+    double *fields, *p, *fq, *hist, *seg, *mu, *b, *g, *qn;
+    int32_t *fst, *rst;
+    rmg_sample_stats *fstats, *rstats;
+  } bf{};
+  auto carve_all = [&](Arena& ar) {
+    bf.fields = (double*)ar.take(8 * S * N);
+    bf.p = (double*)ar.take(8 * S * N);
+    bf.fq = (double*)ar.take(8 * S);
+    bf.fst = (int32_t*)ar.take(4 * S);
+    bf.rst = (int32_t*)ar.take(4 * S);
+    bf.fstats = (rmg_sample_stats*)ar.take(sizeof(rmg_sample_stats) * S);
+    bf.rstats = (rmg_sample_stats*)ar.take(sizeof(rmg_sample_stats) * S);
+    bf.hist = (double*)ar.take(8 * S * slots * N);
+    bf.seg = K > 1 ? (double*)ar.take(8 * S * (K + 1) * N) : nullptr;
+    bf.mu = (double*)ar.take(8 * S * N);
+    bf.b = (double*)ar.take(8 * S * N);
+    bf.g = (double*)ar.take(8 * S * N);
+    bf.qn = (double*)ar.take(8 * S * nst);
+    class_carve(fj, ar);
+    class_carve(aj, ar);
+  };
+  Arena dry;
+  carve_all(dry);
+  if ((rc = reserve(ctx, dry.off + 256))) return rc;
+  Arena ar;
+  ar.base = (char*)ctx->ws;
+  ar.cap = ctx->ws_cap;
+  carve_all(ar);
+  if (ar.off > ar.cap) return fail(ctx, RMG_ENOMEM, "internal error: workspace accounting (%zu > %zu)", ar.off, ar.cap);
+
+  hipStream_t st = ctx->side[0];
+  fj.stream = aj.stream = st;
+  fj.h_count = aj.h_count = ctx->h_count;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
+  HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->ev[0], 0));
+  HIP_TRY(ctx, launch_kl_fields((int)N, n_modes, S, 1, d_basis, d_xi, h_marg, bf.fields, st));
+  fj.a.fields = aj.a.fields = bf.fields;
+
+  // forward pass: checkpoints p^0, p^K, p^2K, ...
+  fj.a.p = bf.p;
+  fj.a.qoi = bf.fq;
+  fj.a.status = bf.fst;
+  fj.a.stats = bf.fstats;
+  fj.a.p_hist = bf.hist;
+  fj.a.hist_every = K;
+  fj.a.hist_slots = slots;
+  const bool graphs = !(opts->flags & 2);
+  if ((rc = run_classes(ctx, fjobs, graphs))) return rc;
+
+  // backward pass, segment by segment
+  aj.a.p = bf.mu;
+  AdjArgs ad{};
+  ad.mu = bf.mu;
+  ad.b = bf.b;
+  ad.g = bf.g;
+  ad.qn = bf.qn;
+  ad.n_steps = nst;
+  ad.eps = eps_adjoint;
+  ad.max_its = opts->max_picard;
+  HIP_TRY(ctx, prepare_stream(aj.a, aj.pl));
+  HIP_TRY(ctx, launch_adj_init(aj.a, aj.pl, ad, bf.fst, st));
+  for (int seg = (K == 1 ? 0 : nst / K - 1); seg >= 0; --seg) {
+    if (K == 1) {
+      ad.hist = bf.hist;
+      ad.slots = slots;
+      ad.base = 0;
+      ad.lo = 1;
+      ad.hi = nst;
+    } else {
+      // recompute the segment's steps from its checkpoint, every step recorded
+      fj.a.cp.prob[0].n_steps = fj.a.cp.prob[1].n_steps = K;
+      fj.a.p0 = bf.hist + (int64_t)seg * N;
+      fj.a.p0_stride = (int64_t)slots * N;
+      fj.a.p_hist = bf.seg;
+      fj.a.hist_every = 1;
+      fj.a.hist_slots = K + 1;
+      fj.a.status = bf.rst;
+      fj.a.stats = bf.rstats;
+      fj.done = false;
+      if ((rc = run_classes(ctx, fjobs, graphs))) return rc;
+      ad.hist = bf.seg;
+      ad.slots = K + 1;
+      ad.base = seg * K;
+      ad.lo = seg * K + 1;
+      ad.hi = seg * K + K;
+    }
+    HIP_TRY(ctx, launch_adj_reset(aj.a, aj.pl, ad, st));
+    const int64_t bound = (int64_t)(ad.hi - ad.lo + 1) * ad.max_its + 16;
+    int64_t its = 0;
+    for (;;) {
+      for (int i = 0; i < 8; ++i) HIP_TRY(ctx, launch_adj_iteration(aj.a, aj.pl, ad, st));
+      its += 8;
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->h_count, aj.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipStreamSynchronize(st));
+      if (((volatile int32_t*)ctx->h_count)[0] == 0) break;
+      if (its > bound) return fail(ctx, RMG_EHIP, "adjoint samples still active after %lld iterations", (long long)its);
+    }
+    HIP_TRY(ctx, launch_adj_grad_final(aj.a, aj.pl, ad, st));
+    HIP_TRY(ctx, launch_adj_outflux(aj.a, ad, st));
+  }
+  HIP_TRY(ctx, launch_adj_finish(aj.a, aj.pl, ad, bf.fst, d_q, d_status, d_stats ? d_stats + S : nullptr, st));
+  if (d_stats)
+    HIP_TRY(ctx, hipMemcpyAsync(d_stats, bf.fstats, sizeof(rmg_sample_stats) * S, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(ctx, launch_grad_xi(S, (int)N, n_modes, d_basis, bf.g, bf.fields, h_marg[0], d_status, d_grad, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
+  HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1], 0));
+  std::vector<int32_t> sv(S);
+  HIP_TRY(ctx, hipMemcpyAsync(sv.data(), d_status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  for (int32_t v : sv)
+    if (v != RMG_SAMPLE_OK) return fail(ctx, RMG_ENOTCONV, "some samples did not converge");
+  return RMG_OK;
+}
+
 int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fields, int n_modes,
                         const rmg_marginal* h_marg, const rmg_solver_opts* opts, rmg_level_sums* h_out,
                         double* d_qoi_out, hipStream_t stream) {

@@ -24,6 +24,8 @@ struct SampleState {
   int32_t active, new_step, step, it;
   int32_t status, tot_its, cycles, nanflag;
   double final_dp;
+  int32_t pend;  // adjoint: the step above `step` converged and its gradient term is pending
+  int32_t pad_;
 };
 
 // Problems of one grid-size class: samples [0, seg_split) use prob[0], the rest prob[1].
@@ -63,6 +65,28 @@ struct SolveArgs {
   int32_t* status;
   rmg_sample_stats* stats;
   int64_t s0;  // whole-sample kernel: first sample of the launch (launches cover chunks of S)
+  // optional initial pressure head p0 + s * p0_stride (else the problem's uniform h_init)
+  const double* p0;
+  int64_t p0_stride;
+  // optional history: the pressure head after step k (k = 0: initial) for every k that is a
+  // multiple of hist_every, at p_hist + (s * hist_slots + k / hist_every) * n * n
+  double* p_hist;
+  int hist_every, hist_slots;
+};
+
+// Level-streaming discrete adjoint (backward through the time steps): the state of one
+// segment of steps lo .. hi, solved from hi down to lo.
+struct AdjArgs {
+  const double* hist;  // pressure heads p^k at hist + (s * slots + k - base) * n * n
+  int slots, base;
+  int lo, hi;
+  int n_steps;         // of the whole integration (layout of qn)
+  double* mu;          // [S][n*n] adjoint state (minus the Lagrange multiplier of the step)
+  double* b;           // [S][n*n] right-hand side of the current step
+  double* g;           // [S][n*n] dQ/dlog Ks accumulated over the converged steps
+  double* qn;          // [S][n_steps] outflux F(p^k) of every step
+  double eps;          // stop a step when ||d mu||_inf < eps
+  int max_its;         // fixed-point iterations allowed per step
 };
 
 // LDS bytes of the whole-sample kernel for grid n (0 if it does not fit).
@@ -100,6 +124,25 @@ hipError_t prepare_stream(const SolveArgs& a, const StreamPlan& pl);
 // One Picard iteration of every active sample: stream operations only, capturable.
 hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
+// The multigrid cycles of one iteration (down legs, coarse kernel, up legs; the finest
+// up leg adds the correction to a.p): what launch_stream_iteration runs between the
+// fine residual and the control kernel.
+hipError_t launch_stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
+
+// Adjoint (streaming path).  a.p must point at ad.mu.
+hipError_t launch_adj_init(const SolveArgs& a, const StreamPlan& pl, const AdjArgs& ad, const int32_t* fwd_status,
+                           hipStream_t st);
+hipError_t launch_adj_reset(const SolveArgs& a, const StreamPlan& pl, const AdjArgs& ad, hipStream_t st);
+// One fixed-point iteration of every active sample (capturable).
+hipError_t launch_adj_iteration(const SolveArgs& a, const StreamPlan& pl, const AdjArgs& ad, hipStream_t st);
+// Gradient terms still pending when the segment's loop ended.
+hipError_t launch_adj_grad_final(const SolveArgs& a, const StreamPlan& pl, const AdjArgs& ad, hipStream_t st);
+hipError_t launch_adj_outflux(const SolveArgs& a, const AdjArgs& ad, hipStream_t st);
+hipError_t launch_adj_finish(const SolveArgs& a, const StreamPlan& pl, const AdjArgs& ad, const int32_t* fwd_status,
+                             double* q, int32_t* status, rmg_sample_stats* stats, hipStream_t st);
+// dQ/dxi[s][j] = sum_c B[j][c] g[s][c] scale (Ks - shift) / Ks (NaN for failed samples).
+hipError_t launch_grad_xi(int64_t S, int N, int M, const double* B, const double* g, const double* Ks,
+                          rmg_marginal marg, const int32_t* status, double* grad, hipStream_t st);
 size_t level_bytes(int m, int64_t S, bool fp64);
 
 // KL fields: out[r][c] = shift_f + exp(log_mean_f + scale_f * sum_k xi[r][k] B[k][c]), f = r mod F.

@@ -17,18 +17,9 @@
 #include "rmg_internal.hpp"
 #include "rmg_lds.hpp"
 #include "rmg_smoother.hpp"
+#include "rmg_tiles.hpp"
 
 namespace rmg {
-
-__device__ __forceinline__ const rmg_problem& class_problem(const ClassProblems& cp, int64_t s) {
-  return s < cp.seg_split ? cp.prob[0] : cp.prob[1];
-}
-
-#define RMG_TILE_FOR(w, ri, rj)                                                                 \
-  for (int w_ = (w), once_ = 1; once_; once_ = 0)                                                 \
-    for (unsigned mg_ = rmg_magic(w_), once2_ = 1u; once2_; once2_ = 0u)                          \
-      for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < w_ * w_; k_ += (int)blockDim.x)        \
-        if ((rj = (int)__umulhi((unsigned)k_, mg_), ri = k_ - rj * w_), true)
 
 // Mean effective saturation (theta - theta_r)/(theta_s - theta_r) over the cells.
 // The summation order is fixed independently of the block size: lane t <
@@ -100,7 +91,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   double* const thold = SL ? thS : a.theta_old + s * N;
   const double* const fld = SL ? fS : a.fields + s * F * N;  // field f of cell c at fld[f*N + c]
   for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    p[c] = P.h_init;
+    p[c] = a.p0 ? a.p0[s * a.p0_stride + c] : P.h_init;
     if (SL)
       for (int f = 0; f < F; ++f) fS[f * N + c] = a.fields[(s * F + f) * N + c];
   }
@@ -131,6 +122,9 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     }
     __syncthreads();
     // outer residual and fine-level coefficients
+    double* hist = nullptr;  // history slot of the step that starts here, if recorded
+    if (new_step && a.p_hist && step % a.hist_every == 0)
+      hist = a.p_hist + (s * a.hist_slots + step / a.hist_every) * N;
     for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
       double pc[kUnroll], pw[kUnroll], pe[kUnroll], ps[kUnroll], pn[kUnroll], to[kUnroll];
       double k0[kUnroll], k1[kUnroll], k2[kUnroll];
@@ -160,6 +154,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
         if (new_step) {
           th_old = cl.theta;
           thold[c] = cl.theta;
+          if (hist) hist[c] = pc[q];
         }
         const double Kw = i > 0 ? Kc[c - 1] : 0.0, Ke = i < n - 1 ? Kc[c + 1] : 0.0;
         const double Ks_ = j > 0 ? Kc[c - n] : 0.0, Kn = j < n - 1 ? Kc[c + n] : 0.0;
@@ -238,6 +233,10 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   __syncthreads();
   if (SL)
     for (int c = threadIdx.x; c < N; c += blockDim.x) pg[c] = p[c];
+  if (a.p_hist && status == RMG_SAMPLE_OK && P.n_steps % a.hist_every == 0) {
+    double* hist = a.p_hist + (s * a.hist_slots + P.n_steps / a.hist_every) * N;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) hist[c] = p[c];
+  }
   const double q = mean_saturation(P, fld, F, N, 0, p, red);
   if (threadIdx.x == 0) {
     a.qoi[s] = status == RMG_SAMPLE_OK ? q : __longlong_as_double(0x7ff8000000000000ll);
@@ -334,7 +333,7 @@ __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long lon
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = e / N;
-    a.p[e] = class_problem(a.cp, s).h_init;
+    a.p[e] = a.p0 ? a.p0[s * a.p0_stride + (e - s * N)] : class_problem(a.cp, s).h_init;
   }
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < a.S;
        s += (int64_t)gridDim.x * blockDim.x) {
@@ -348,6 +347,8 @@ __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long lon
     z.cycles = 0;
     z.nanflag = 0;
     z.final_dp = 0.0;
+    z.pend = 0;
+    z.pad_ = 0;
     state[s] = z;
     dpmax[s] = 0ull;
   }
@@ -414,6 +415,11 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   R* cdt0 = (R*)pl.lv.cdt[0] + s * N;
   R* ctop0 = (R*)pl.lv.ctop[0] + s * n;
   double* thold = a.theta_old + s * N;
+  double* hist = nullptr;  // history slot of the step that starts here, if recorded
+  if (new_step && a.p_hist) {
+    const int k = pl.state[s].step;
+    if (k % a.hist_every == 0) hist = a.p_hist + (s * a.hist_slots + k / a.hist_every) * N;
+  }
   RMG_TILE_FOR(T, li, lj) {
     const int e = lj * T + li;
     const int gi = x0 + li, gj = y0 + lj;
@@ -425,6 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
     if (new_step) {
       th_old = cl.theta;
       thold[c] = cl.theta;
+      if (hist) hist[c] = sp[le];
     } else {
       th_old = thold[c];
     }
@@ -445,50 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
       if (gj == n - 1) ctop0[gi] = rct;
     }
   }
-  // in-tile coarsening, ping-pong between bufA and bufB
-  R* src = bufA;
-  R* dst = bufB;
-  int t = T;
-  for (int l = 1; l <= pl.ltop; ++l) {
-    __syncthreads();
-    const int tc = t >> 1;
-    const int m = n >> l;
-    const int64_t M2 = (int64_t)m * m;
-    R* scw = src;
-    R* scdt = src + t * t;
-    R* scs = src + 2 * t * t;
-    R* dcw = dst;
-    R* dcdt = dst + tc * tc;
-    R* dcs = dst + 2 * tc * tc;
-    R* gcw = (R*)pl.lv.cw[l] + s * M2;
-    R* gcs = (R*)pl.lv.cs[l] + s * M2;
-    R* gcdt = (R*)pl.lv.cdt[l] + s * M2;
-    R* gctop = (R*)pl.lv.ctop[l] + s * m;
-    const int X0 = x0 >> l, Y0 = y0 >> l;
-    RMG_TILE_FOR(tc, I, J) {
-      const int e = J * tc + I;
-      const int f00 = (2 * J) * t + 2 * I;
-      const R cw = coarse_face<R>(scw[f00], scw[f00 + t]);
-      const R cs = coarse_face<R>(scs[f00], scs[f00 + 1]);
-      const R cd = coarse_cdt<R>(scdt[f00], scdt[f00 + 1], scdt[f00 + t], scdt[f00 + t + 1]);
-      dcw[e] = cw;
-      dcs[e] = cs;
-      dcdt[e] = cd;
-      const int64_t gc = (int64_t)(Y0 + J) * m + X0 + I;
-      gcw[gc] = cw;
-      gcs[gc] = cs;
-      gcdt[gc] = cd;
-    }
-    for (int I = threadIdx.x; I < tc; I += blockDim.x) {
-      const R ct = coarse_face<R>(scs[t * t + 2 * I], scs[t * t + 2 * I + 1]);
-      dcs[tc * tc + I] = ct;
-      if (y0 + T == n) gctop[X0 + I] = ct;
-    }
-    R* tmp = src;
-    src = dst;
-    dst = tmp;
-    t = tc;
-  }
+  tile_coarsen<R>(pl, s, n, T, x0, y0, bufA, bufB);
 }
 
 // Levels ltop .. nlev-1 of one sample in LDS: load level ltop, coarsen, V-cycle,
@@ -639,6 +603,10 @@ __global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPla
   const rmg_problem P = class_problem(a.cp, s);
   const int64_t N = (int64_t)a.n * a.n;
   const double q = mean_saturation(P, a.fields, a.F, N, s, a.p + s * N, red);
+  if (a.p_hist && pl.state[s].status == RMG_SAMPLE_OK && P.n_steps % a.hist_every == 0) {
+    double* hist = a.p_hist + (s * a.hist_slots + P.n_steps / a.hist_every) * N;
+    for (int64_t c = threadIdx.x; c < N; c += blockDim.x) hist[c] = a.p[s * N + c];
+  }
   if (threadIdx.x == 0) {
     const SampleState st = pl.state[s];
     a.qoi[s] = st.status == RMG_SAMPLE_OK ? q : __longlong_as_double(0x7ff8000000000000ll);
@@ -714,15 +682,9 @@ static_assert(blk_nb(16, 5) <= 2 && blk_nb(16, 4) <= 1 && blk_nb(32, 5) <= 3 && 
               "blocks per thread of the instantiated down/up kernels (nu <= 4)");
 
 template <class R>
-static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
   const bool fp64 = sizeof(R) == 8;
-  const dim3 blk(kBlock);
   const int n = a.n;
-  {
-    const int T = n < kTile ? n : kTile;
-    const unsigned tiles = (unsigned)((n / T) * (n / T));
-    hipLaunchKernelGGL(k_fine<R>, dim3(tiles, (unsigned)a.S), blk, 0, st, a, pl);
-  }
   const int nc = n >> (a.nlev - 1);
   const size_t lcv = coarse_lds(n >> pl.ltop, nc, fp64);
   hipError_t err = hipSuccess;
@@ -753,6 +715,19 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
     launch_up<R>(ts, dim3(tiles, (unsigned)a.S), st, a, pl, l, (l == 0 && last) ? 1 : 0);
   };
   for (int cyc = 0; cyc < a.cpp; ++cyc) cycle(cycle, 0, cyc == 0, cyc == a.cpp - 1);
+  return err;
+}
+
+template <class R>
+static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+  const dim3 blk(kBlock);
+  const int n = a.n;
+  {
+    const int T = n < kTile ? n : kTile;
+    const unsigned tiles = (unsigned)((n / T) * (n / T));
+    hipLaunchKernelGGL(k_fine<R>, dim3(tiles, (unsigned)a.S), blk, 0, st, a, pl);
+  }
+  const hipError_t err = stream_cycles<R>(a, pl, st);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_control, dim3((unsigned)((a.S + kBlock - 1) / kBlock)), blk, 0, st, a, pl);
   return hipGetLastError();
@@ -774,6 +749,11 @@ hipError_t prepare_stream(const SolveArgs& a, const StreamPlan& pl) {
 
 hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
   return pl.fp64 ? stream_iteration<double>(a, pl, st) : stream_iteration<float>(a, pl, st);
+}
+
+hipError_t launch_stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+  const hipError_t e = pl.fp64 ? stream_cycles<double>(a, pl, st) : stream_cycles<float>(a, pl, st);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
