@@ -260,12 +260,158 @@ def cpu_baseline(max_picard, cycles, gpu_its_per_solve):
                       "run's iteration counts on 256^2, divided by the worker count"}
 
 
+# ------------------------------------------------------------ adjoint workload
+def _oracle_adjoint_job(args):
+    """Oracle forward + adjoint (twin multigrid forward, sparse-LU adjoint) of the first
+    `steps` steps of one adjoint-workload sample."""
+    i, steps, Bn, max_picard = args
+    import workloads as W
+    from oracle import adjoint as oadj, kl as okl
+    cfg, f = W.ADJOINT_128, W.KS_FIELD
+    n = cfg["n"]
+    xi = W.xi_draws(cfg["workload_id"], 0, [i], 1, cfg["n_modes"])[0, 0]
+    Ks = okl.lognormal(okl.gaussian_field(xi, Bn), f["log_mean"], f["scale"]).reshape(n, n)
+    t0 = time.perf_counter()
+    r = oadj.solve_with_gradient(dict(W.GARDNER_INFILTRATION, n_steps=steps), Ks, n,
+                                 dict(W.SOLVER, max_picard=max_picard), basis=Bn, mode="mg")
+    return time.perf_counter() - t0, r["status"]
+
+
+def adjoint_cpu_baseline(max_picard, steps=2):
+    """The oracle adjoint on a bounded sample: the first `steps` of the 20 steps of 16
+    samples, one process per core; the full workload's time is that per-sample time
+    scaled by 20 / steps, times the sample count, over the worker count."""
+    import multiprocessing as mp
+    import workloads as W
+    from oracle import kl as okl
+    cfg, f = W.ADJOINT_128, W.KS_FIELD
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    _, B = okl.basis(f["sigma2"], f["corr_len"], cfg["n_modes"], [cfg["n"]], ref_n=64)
+    jobs = [(i, steps, B[cfg["n"]], max_picard) for i in range(16)]
+    env_threads = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(min(cores, len(jobs))) as pool:
+        res = list(pool.imap_unordered(_oracle_adjoint_job, jobs, chunksize=1))
+    wall = time.perf_counter() - t0
+    if env_threads is None:
+        os.environ.pop("OMP_NUM_THREADS", None)
+    else:
+        os.environ["OMP_NUM_THREADS"] = env_threads
+    per_sample = sum(t for t, _ in res) / len(res) * (cfg["n_steps"] / steps)
+    est_wall = per_sample * cfg["n_samples"] / cores
+    return {"value": cfg["n_samples"] / est_wall, "unit": "sample gradients/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle forward (twin multigrid) + adjoint (sparse LU) of the first {steps} of "
+                      f"{cfg['n_steps']} steps of 16 samples in {wall:.1f}s wall on {min(cores, len(jobs))} "
+                      f"processes; scaled by {cfg['n_steps']}/{steps} steps and {cfg['n_samples']} samples "
+                      "over the worker count"}
+
+
+def adjoint_bench(args, torch, rmg, W):
+    """The adjoint workload: 1024 samples of 128^2, 100 KL modes, 20 steps, checkpoints every
+    5 steps; one step = one picard_mg_adjoint call (fields, forward with checkpoints,
+    segment recomputation, adjoint sweep, dQ/dxi)."""
+    from paper_1903_08741_amd import _abi, kl_setup
+    cfg, f, g = W.ADJOINT_128, W.KS_FIELD, W.GARDNER_INFILTRATION
+    dev = torch.device("cuda:0")
+    n, S, M = cfg["n"], cfg["n_samples"], cfg["n_modes"]
+    _, tables = kl_setup.kl_tables(f["sigma2"], f["corr_len"], M, [n])
+    B = torch.from_numpy(tables[n]).to(dev)
+    xi = torch.from_numpy(W.xi_draws(cfg["workload_id"], 0, range(S), 1, M)[:, 0, :].copy()).to(dev)
+    prob = rmg.Problem(model=rmg.GARDNER, n_steps=cfg["n_steps"], theta_r=g["theta_r"], theta_s=g["theta_s"],
+                       gardner_a=g["gardner_a"], h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"],
+                       dt=g["dt"])
+    marg = (0.0, f["log_mean"], f["scale"])
+    # absolute tolerance on the multipliers' corrections: they are ~1e-4 in this workload
+    # (dt times the outflux sensitivity), so 1e-13 converges them to ~1e-9 relative
+    eps_adj = 1e-13
+    precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
+    opts = rmg.SolverOpts(precision=precision, max_picard=args.max_picard)
+    if args.no_autotune:
+        opts.flags |= rmg.FLAG_NO_AUTOTUNE
+    ctx = rmg.default_context(0)
+
+    def call(o):
+        return ctx.picard_mg_adjoint(n, B, xi, marg, prob, o, ckpt_every=cfg["ckpt_every"], eps_adjoint=eps_adj)
+    for i in range(args.warmup):
+        t0 = time.time()
+        out = call(opts)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.time() - t0:.3f}s rc={out['rc']}")
+    ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = call(opts)
+        log(f"step {i} done rc={out['rc']}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1000.0 * dt / args.steps
+    kt = ctx.kernel_timing()
+    ctx.set_kernel_timing(_abi.TIME_NONE)
+    ok = out["status"] == 0
+    n_ok = int(ok.sum().item())
+    fwd, adj = out["stats_forward"], out["stats_adjoint"]
+    gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_down (nu1 fused red-black sweeps + residual + restriction), forward and adjoint sweeps",
+            "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
+            "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
+    extras = {}
+    if not args.no_extras and precision == rmg.MIXED:
+        o64 = rmg.SolverOpts(precision=rmg.FP64, max_picard=args.max_picard)
+        call(o64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ref = call(o64)
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t1)
+        both = ok & (ref["status"] == 0)
+        gm, gr = out["grad"][both], ref["grad"][both]
+        rel = ((gm - gr).abs().amax(dim=1) / gr.abs().amax(dim=1)).cpu()
+        qrel = ((out["q"][both] - ref["q"][both]).abs() / ref["q"][both].abs()).cpu()
+        extras["fp64_path"] = {"ms_per_step": ms64, "mixed_speedup": ms64 / ms,
+                               "samples_compared": int(both.sum().item()),
+                               "grad_rel_err_max": float(rel.max()) if rel.numel() else None,
+                               "grad_rel_err_median": float(rel.median()) if rel.numel() else None,
+                               "q_rel_err_max": float(qrel.max()) if qrel.numel() else None}
+        log(f"fp64 adjoint: {ms64:.1f} ms; grad rel err max {extras['fp64_path']['grad_rel_err_max']}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        t1 = time.time()
+        cpu = adjoint_cpu_baseline(args.max_picard)
+        log(f"cpu baseline {time.time() - t1:.1f}s")
+    res = {
+        "metric": "Picard-MG adjoint sample gradients/sec (dQ/dxi, 100 KL coefficients)",
+        "value": n_ok / (ms / 1000.0),
+        "unit": "sample gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 multigrid in f64 Picard and f64 adjoint residual" if precision == rmg.MIXED else "f64",
+        "data": "synthetic (seeded KL lognormal Ks fields)",
+        "config": {"workload": f"adjoint: {S} samples of {n}^2, Gardner, {M} KL modes, {cfg['n_steps']} steps "
+                               f"dt=0.01, QoI time-integrated bottom outflux, checkpoints every "
+                               f"{cfg['ckpt_every']} steps, V(2,2) per Picard / adjoint iteration, "
+                               f"eps 1e-8 forward, {eps_adj:g} adjoint",
+                   "samples": S, "converged_samples": n_ok,
+                   "forward_picard_iterations": int(fwd["picard_its"].sum()),
+                   "adjoint_iterations": int(adj["picard_its"].sum()),
+                   "precision": args.precision, "max_picard": args.max_picard},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    res.update(extras)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("gardner", "vg"), default="gardner",
+    ap.add_argument("--workload", choices=("gardner", "vg", "adjoint"), default="gardner",
                     help="gardner: the 5-level Gardner MLMC workload (default); vg: the van Genuchten "
-                         "workload with three fields and continuation (5 levels 32^2..512^2)")
+                         "workload with three fields and continuation (5 levels 32^2..512^2); adjoint: "
+                         "outflux gradients of 1024 samples of 128^2 (100 KL modes, 20 steps)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
@@ -287,6 +433,9 @@ def main():
     import paper_1903_08741_amd as rmg
     import workloads as W
 
+    if args.workload == "adjoint":
+        adjoint_bench(args, torch, rmg, W)
+        return
     dev = torch.device("cuda:0")
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
     vg = args.workload == "vg"

@@ -261,7 +261,8 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* h_levels,
  * lambda_{k+1} with J_k the exact Jacobian of the step residual at p^k (the
  * modified-Picard operator plus the dK/dp terms) by the fixed-point iteration
  * preconditioned with the forward multigrid cycle on the Picard operator; it stops
- * when the correction's max norm is below eps_adjoint (at most opts->max_picard
+ * when the correction's max norm is below eps_adjoint (absolute: choose it relative
+ * to the multipliers' size, about dt times dF/dp; at most opts->max_picard
  * iterations per step).  The forward pass stores p every ckpt_every steps; the
  * backward pass recomputes each segment of ckpt_every steps from its checkpoint
  * (ckpt_every = 1: every step is stored, nothing is recomputed).

@@ -794,6 +794,15 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
   ad.max_its = opts->max_picard;
   HIP_TRY(ctx, prepare_stream(aj.a, aj.pl));
   HIP_TRY(ctx, launch_adj_init(aj.a, aj.pl, ad, bf.fst, st));
+  // kernel timing covers the adjoint iterations' launches too (eager launches: all timed
+  // while the event ring has room; it is drained at every poll)
+  KernelTimer* tm = nullptr;
+  if (ctx->timing) {
+    tm = &ctx->timers[1];
+    tm->head = tm->tail = 0;
+    ctx->timer_es[1] = aj.fp64 ? 8 : 4;
+  }
+  aj.pl.timer = tm;
   for (int seg = (K == 1 ? 0 : nst / K - 1); seg >= 0; --seg) {
     if (K == 1) {
       ad.hist = bf.hist;
@@ -827,6 +836,7 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
       its += 8;
       HIP_TRY(ctx, hipMemcpyAsync(ctx->h_count, aj.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
+      if ((rc = harvest_timer(ctx, tm, tm ? tm->tail : 0))) return rc;
       if (((volatile int32_t*)ctx->h_count)[0] == 0) break;
       if (its > bound) return fail(ctx, RMG_EHIP, "adjoint samples still active after %lld iterations", (long long)its);
     }

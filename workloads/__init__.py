@@ -87,6 +87,12 @@ VG_INFILTRATION = dict(
 MLMC_VG = dict(workload_id=2, grids=(32, 64, 128, 256, 512), samples=(2048, 512, 128, 32, 8),
                n_shift_grad=0.1)
 
+# Adjoint sensitivities: the Gardner problem on 128 x 128 with 20 steps, Ks = exp(G) from a
+# 100-term KL expansion of the same covariance as KS_FIELD, 1024 samples; the quantity is
+# the time-integrated bottom outflux and its gradient in the 100 KL coefficients, with the
+# forward pressure head checkpointed every 5 steps.
+ADJOINT_128 = dict(workload_id=3, n=128, n_samples=1024, n_modes=100, n_steps=20, ckpt_every=5)
+
 
 def xi_draws(workload_id: int, level: int, sample_ids, n_fields: int, n_modes: int) -> np.ndarray:
     """Standard-normal KL coefficients, shape [len(sample_ids)][n_fields][n_modes], float64."""
