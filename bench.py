@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -405,13 +407,80 @@ def adjoint_bench(args, torch, rmg, W):
     print(json.dumps(res), flush=True)
 
 
+# ------------------------------------------------------------ robustness sweep
+def sweep_bench(args, torch, rmg, W):
+    """Section 4.3's robustness sweep as one batched solve: the 20 x 20 (alpha, n) pairs of
+    Table alpha_n times 64 Ks fields (the same 64 draws for every pair), the infiltration
+    problem of eq. travellingwave, W(2,2) cycles to eps_MG = 1e-5, eps_PI = 1e-5, at most 50
+    Picard iterations per step.  Reports the cost map (mean W-cycles to T_final over the
+    converged samples of a pair) and the failure map (failed samples out of 64)."""
+    from paper_1903_08741_amd import kl_setup
+    cfg, tw = W.SWEEP, W.TRAVELLING_WAVE
+    dev = torch.device("cuda:0")
+    n, P, M = cfg["n"], cfg["samples_per_pair"], cfg["n_modes"]
+    A, NV = W.SWEEP_ALPHA, W.SWEEP_N
+    _, tables = kl_setup.kl_tables(0.0, 0.0, M, [n], matern_phi=W.MATERN_PHI1)
+    ctx = rmg.default_context(0)
+    B = torch.from_numpy(tables[n]).to(dev)
+    xi = torch.from_numpy(W.xi_draws(cfg["workload_id"], 0, range(P), 1, M)).to(dev)
+    ks = ctx.sample_fields(n, B, xi, [(0.0, float(np.log(tw["ks_baseline"])), 1.0)])[:, 0]  # [P][N]
+    pairs = [(a, v) for a in A for v in NV]
+    S = len(pairs) * P
+    fields = torch.empty(S, 3, n * n, dtype=torch.float64, device=dev)
+    fields[:, 0] = ks.repeat(len(pairs), 1)
+    av = torch.tensor([a for a, _ in pairs], dtype=torch.float64, device=dev).repeat_interleave(P)
+    nv = torch.tensor([v for _, v in pairs], dtype=torch.float64, device=dev).repeat_interleave(P)
+    fields[:, 1] = av[:, None]
+    fields[:, 2] = nv[:, None]
+    prob = rmg.Problem(model=rmg.VGM, n_steps=tw["n_steps"], theta_r=tw["theta_r"], theta_s=tw["theta_s"],
+                       h_top=tw["h_top"], h_bottom=tw["h_bottom"], h_init=tw["h_init"], dt=tw["dt"],
+                       init_profile=1, init_rate=tw["init_rate"])
+    precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
+    opts = rmg.SolverOpts(precision=precision, cycle=rmg.CYCLE_W, cycles_per_picard=0, eps_mg=cfg["eps_mg"],
+                          eps_picard=cfg["eps"], max_picard=cfg["max_picard"])
+    for i in range(args.warmup):
+        ctx.picard_mg_solve(n, fields, prob, opts)
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = ctx.picard_mg_solve(n, fields, prob, opts)
+        log(f"step {i} done rc={out['rc']}")
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    st = out["status"].cpu().numpy().reshape(len(A), len(NV), P)
+    cyc = out["stats"]["mg_cycles"].reshape(len(A), len(NV), P).astype(np.float64)
+    ok = st == 0
+    with np.errstate(invalid="ignore"):
+        cost = np.where(ok.any(axis=2), (cyc * ok).sum(axis=2) / np.maximum(ok.sum(axis=2), 1), np.nan)
+    fails = (~ok).sum(axis=2)
+    res = {
+        "metric": "Picard-MG robustness sweep sample solves/sec (W(2,2) to eps_MG, Table alpha_n)",
+        "value": float(ok.sum()) / (ms / 1000.0), "unit": "sample solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 multigrid in f64 Picard" if precision == rmg.MIXED else "f64",
+        "data": "synthetic (seeded Matern Phi_1 KL Ks fields; alpha, n from Table alpha_n)",
+        "config": {"workload": f"robustness sweep: {len(A)}x{len(NV)} (alpha, n) pairs x {P} Ks fields = {S} "
+                               f"solves of {n}^2, vG, infiltration problem, {tw['n_steps']} steps dt=1/64, "
+                               "W(2,2) to eps_MG 1e-5, eps_PI 1e-5, at most 50 Picard iterations",
+                   "solves": S, "converged": int(ok.sum()), "precision": args.precision},
+        "roofline": None,
+        "cpu_baseline": None,
+        "alpha": list(A), "n": list(NV),
+        "mean_w_cycles": [[None if np.isnan(x) else round(float(x), 1) for x in row] for row in cost],
+        "failures_of_64": fails.tolist(),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("gardner", "vg", "adjoint"), default="gardner",
+    ap.add_argument("--workload", choices=("gardner", "vg", "adjoint", "sweep"), default="gardner",
                     help="gardner: the 5-level Gardner MLMC workload (default); vg: the van Genuchten "
                          "workload with three fields and continuation (5 levels 32^2..512^2); adjoint: "
-                         "outflux gradients of 1024 samples of 128^2 (100 KL modes, 20 steps)")
+                         "outflux gradients of 1024 samples of 128^2 (100 KL modes, 20 steps); sweep: the "
+                         "alpha-n robustness sweep of the infiltration problem (25600 solves of 32^2)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
@@ -435,6 +504,9 @@ def main():
 
     if args.workload == "adjoint":
         adjoint_bench(args, torch, rmg, W)
+        return
+    if args.workload == "sweep":
+        sweep_bench(args, torch, rmg, W)
         return
     dev = torch.device("cuda:0")
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64

@@ -66,7 +66,8 @@ typedef struct {
 /* One deterministic problem (closure model, boundary and initial data, time grid).
  * qoi must be RMG_QOI_MEAN_SATURATION for the forward entry points; the bottom
  * outflux (RMG_QOI_BOTTOM_OUTFLUX) is the quantity of picard_mg_adjoint;
- * theta_s > theta_r, dt > 0 and n_steps >= 1 are required.
+ * theta_s > theta_r, dt > 0, n_steps >= 1 and init_profile 0 or 1 (with init_rate > 0)
+ * are required.
  * Fields per cell: Gardner and linear use field 0 = Ks; van Genuchten-Mualem uses
  * field 0 = Ks, 1 = alpha, 2 = n (so n_fields = 1 or 3).
  *   Gardner: K = Ks e^{a h}, theta = theta_r + (theta_s - theta_r) e^{a h} (h < 0);
@@ -77,7 +78,9 @@ typedef struct {
   int32_t model;          /* rmg_model */
   int32_t n_steps;        /* number of backward-Euler steps */
   int32_t qoi;            /* rmg_qoi */
-  int32_t pad_;
+  int32_t init_profile;   /* 0: uniform initial head h_init; 1: h_init (1 - exp(-init_rate z)) at
+                             the cell centre's height z (the infiltration problem of Section 4.3,
+                             eq. travellingwave: h_init = -0.4, init_rate = 80) */
   double theta_r, theta_s;
   double gardner_a;       /* Gardner exponent a */
   double linear_c0;       /* linear-law capacity */
@@ -86,6 +89,7 @@ typedef struct {
   double h_top, h_bottom; /* Dirichlet pressure head on z = 1 and z = 0 */
   double h_init;          /* uniform initial pressure head */
   double dt;              /* time step */
+  double init_rate;       /* > 0 when init_profile = 1 */
 } rmg_problem;
 
 /* Solver options.  Defaults for the benchmark workloads: MIXED, V, 2, 2, 1,

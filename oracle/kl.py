@@ -108,9 +108,22 @@ def interpolate(cov, points_q, weights, lam, psi_q, points):
     return out
 
 
-def basis(sigma2, corr_len, n_modes, grids, ref_n=64):
-    """KL basis tables B_n[j, c] = sqrt(lambda_j) Psi_j(x_c) for each grid size n (dict n -> [M][n*n])."""
-    cov = exponential_cov(sigma2, corr_len)
+def matern_cov(nu, lx, lz, sigma2):
+    """The anisotropic Matern kernel of eq. nonIsotropic with Phi = (nu, lambda_x, lambda_z, sigma^2)."""
+    def cov(X, Y):
+        dx = (X[:, None, 0] - Y[None, :, 0]) / lx
+        dz = (X[:, None, 1] - Y[None, :, 1]) / lz
+        return matern(np.sqrt(dx * dx + dz * dz), nu, sigma2)
+    return cov
+
+
+def basis(sigma2, corr_len, n_modes, grids, ref_n=64, matern_phi=None):
+    """KL basis tables B_n[j, c] = sqrt(lambda_j) Psi_j(x_c) for each grid size n (dict n -> [M][n*n]).
+
+    The covariance is the exponential kernel (Matern nu = 1/2, isotropic, sigma2, corr_len),
+    or, if matern_phi = (nu, lambda_x, lambda_z, sigma^2) is given, the Matern kernel of
+    eq. nonIsotropic (then sigma2 and corr_len are not used)."""
+    cov = exponential_cov(sigma2, corr_len) if matern_phi is None else matern_cov(*matern_phi)
     pts = cell_centres(ref_n)
     w = np.full(ref_n * ref_n, 1.0 / (ref_n * ref_n))
     lam, psi_q = nystrom(cov, pts, w, n_modes)

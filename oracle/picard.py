@@ -87,13 +87,24 @@ def bottom_outflux(problem, fields, p):
     return h * float(np.sum(K[0, :] * ((p[0, :] - problem["h_bottom"]) / (0.5 * h) + 1.0)))
 
 
+def initial_head(problem, n):
+    """Initial pressure head: uniform h_init, or, when the problem gives init_rate, the
+    infiltration problem's profile h_init (1 - exp(-init_rate z)) at the cell centres
+    (Section 4.3, eq. travellingwave, with h_init = -0.4 and init_rate = 80)."""
+    rate = problem.get("init_rate")
+    if not rate:
+        return np.full((n, n), float(problem["h_init"]))
+    z = (np.arange(n) + 0.5) / n
+    return np.repeat((problem["h_init"] * (1.0 - np.exp(-rate * z)))[:, None], n, axis=1)
+
+
 def solve(problem, fields, n, opts, mode="mg", p0=None, record=False):
     """Integrate one sample over problem['n_steps'] steps.
 
     fields: dict of n x n arrays (Ks, and alpha/n for van Genuchten).
     Returns dict(p, status, picard (per-step counts), cycles, dp_last, outflux, history).
     """
-    p = np.full((n, n), float(problem["h_init"])) if p0 is None else np.array(p0, dtype=np.float64)
+    p = initial_head(problem, n) if p0 is None else np.array(p0, dtype=np.float64)
     _, theta, _ = constitutive.evaluate(problem, p, fields)
     stats = {"cycles": 0}
     counts, hist = [], []

@@ -51,6 +51,8 @@ class Problem:
     h_bottom: float = -10.0
     h_init: float = -10.0
     dt: float = 0.01
+    init_profile: int = 0
+    init_rate: float = 0.0
 
     def c(self) -> _abi.Problem:
         return _abi.Problem(**{f.name: getattr(self, f.name) for f in dc_fields(self)})

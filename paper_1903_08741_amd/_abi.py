@@ -37,10 +37,11 @@ class Marginal(C.Structure):
 
 
 class Problem(C.Structure):
-    _fields_ = [("model", C.c_int32), ("n_steps", C.c_int32), ("qoi", C.c_int32), ("pad_", C.c_int32),
+    _fields_ = [("model", C.c_int32), ("n_steps", C.c_int32), ("qoi", C.c_int32), ("init_profile", C.c_int32),
                 ("theta_r", C.c_double), ("theta_s", C.c_double), ("gardner_a", C.c_double),
                 ("linear_c0", C.c_double), ("vg_alpha_shift", C.c_double), ("vg_n_shift", C.c_double),
-                ("h_top", C.c_double), ("h_bottom", C.c_double), ("h_init", C.c_double), ("dt", C.c_double)]
+                ("h_top", C.c_double), ("h_bottom", C.c_double), ("h_init", C.c_double), ("dt", C.c_double),
+                ("init_rate", C.c_double)]
 
 
 class SolverOpts(C.Structure):

@@ -116,6 +116,8 @@ int check_problem(rmg_ctx* ctx, const rmg_problem* p, int n_fields) {
     return fail(ctx, RMG_EINVAL, "qoi %d is not supported by this build", p->qoi);
   if (!(p->dt > 0.0) || p->n_steps < 1) return fail(ctx, RMG_EINVAL, "need dt > 0 and n_steps >= 1");
   if (!(p->theta_s > p->theta_r)) return fail(ctx, RMG_EINVAL, "need theta_s > theta_r");
+  if (p->init_profile != 0 && p->init_profile != 1) return fail(ctx, RMG_EINVAL, "init_profile must be 0 or 1");
+  if (p->init_profile == 1 && !(p->init_rate > 0.0)) return fail(ctx, RMG_EINVAL, "init_profile 1 needs init_rate > 0");
   return RMG_OK;
 }
 

@@ -78,6 +78,13 @@ __device__ __forceinline__ Closure closure(const rmg_problem& P, double p, doubl
   return r;
 }
 
+// Initial pressure head of a cell in row j of an n x n grid: uniform, or the
+// exponential profile of the infiltration problem (Section 4.3, eq. travellingwave).
+__device__ __forceinline__ double initial_head(const rmg_problem& P, int j, int n) {
+  if (P.init_profile == 1) return P.h_init * (1.0 - exp(-P.init_rate * (((double)j + 0.5) / (double)n)));
+  return P.h_init;
+}
+
 // Field values of sample s at cell c in [S][F][N] layout.
 struct CellFields {
   double Ks, alpha, nvg;

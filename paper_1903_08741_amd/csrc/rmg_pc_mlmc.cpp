@@ -76,7 +76,8 @@ bool same_problem(const rmg_problem& a, const rmg_problem& b) {
   return a.model == b.model && a.n_steps == b.n_steps && a.qoi == b.qoi && a.theta_r == b.theta_r &&
          a.theta_s == b.theta_s && a.gardner_a == b.gardner_a && a.linear_c0 == b.linear_c0 &&
          a.vg_alpha_shift == b.vg_alpha_shift && a.vg_n_shift == b.vg_n_shift && a.h_top == b.h_top &&
-         a.h_bottom == b.h_bottom && a.h_init == b.h_init && a.dt == b.dt;
+         a.h_bottom == b.h_bottom && a.h_init == b.h_init && a.dt == b.dt && a.init_profile == b.init_profile &&
+         a.init_rate == b.init_rate;
 }
 
 struct Staging {

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   double* const thold = SL ? thS : a.theta_old + s * N;
   const double* const fld = SL ? fS : a.fields + s * F * N;  // field f of cell c at fld[f*N + c]
   for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    p[c] = a.p0 ? a.p0[s * a.p0_stride + c] : P.h_init;
+    p[c] = a.p0 ? a.p0[s * a.p0_stride + c] : initial_head(P, c >> lg, n);
     if (SL)
       for (int f = 0; f < F; ++f) fS[f * N + c] = a.fields[(s * F + f) * N + c];
   }
@@ -333,7 +333,7 @@ __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long lon
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = e / N;
-    a.p[e] = a.p0 ? a.p0[s * a.p0_stride + (e - s * N)] : class_problem(a.cp, s).h_init;
+    a.p[e] = a.p0 ? a.p0[s * a.p0_stride + (e - s * N)] : initial_head(class_problem(a.cp, s), (int)((e - s * N) / a.n), a.n);
   }
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < a.S;
        s += (int64_t)gridDim.x * blockDim.x) {

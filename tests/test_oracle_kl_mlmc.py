@@ -153,3 +153,26 @@ def test_optimal_sample_counts_meet_variance_target():
                       constraints=[{"type": "eq", "fun": lambda x: np.sum(V * np.exp(-x)) / eps ** 2 - 1.0}],
                       options={"ftol": 1e-14, "maxiter": 500})
     np.testing.assert_allclose(np.exp(res.x), Nr, rtol=1e-4)
+
+
+def test_matern_closed_forms():
+    """eq. nonIsotropic at nu = 3/2 is (1 + x) e^{-x} with x = 2 sqrt(nu) r~ (the half-integer
+    closed form of K_{3/2}); as nu grows it tends to the squared exponential exp(-r~^2)."""
+    r = np.linspace(0.0, 3.0, 31)
+    x = np.sqrt(6.0) * r
+    np.testing.assert_allclose(kl.matern(r, 1.5, 2.0), 2.0 * (1.0 + x) * np.exp(-x), rtol=1e-12, atol=1e-15)
+    err = [np.max(np.abs(kl.matern(r, nu, 1.0) - np.exp(-r * r))) for nu in (20.0, 80.0)]
+    assert err[1] < 4e-3 and err[1] < err[0] / 3.0  # O(1/nu) approach to the limit
+
+
+def test_matern_basis_reduces_to_exponential_and_is_anisotropic():
+    lam_e, B_e = kl.basis(1.0, 0.3, 12, [8], ref_n=16)
+    lam_m, B_m = kl.basis(0.0, 0.0, 12, [8], ref_n=16, matern_phi=(0.5, 0.3, 0.3, 1.0))
+    np.testing.assert_allclose(lam_m, lam_e, rtol=1e-12)
+    assert np.max(np.abs(B_m[8] - B_e[8])) < 1e-12
+    # lambda_z << lambda_x: the field varies faster along z than along x
+    lam, B = kl.basis(0.0, 0.0, 40, [16], ref_n=32, matern_phi=(0.5, 0.5, 0.05, 1.0))
+    G = (W.normal_array([3], (200, 40)) @ B[16]).reshape(200, 16, 16)
+    dz = np.mean(np.diff(G, axis=1) ** 2)
+    dx = np.mean(np.diff(G, axis=2) ** 2)
+    assert dz > 3.0 * dx

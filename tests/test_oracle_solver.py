@@ -238,3 +238,18 @@ def test_fixed_point_independent_of_start(kl_basis_small):
     b = picard.picard_step(prob, fields, start, th_old, opts, "direct", {"cycles": 0})
     assert a[2] == 0 and b[2] == 0
     assert np.max(np.abs(a[0] - b[0])) <= 1e-12 * np.max(np.abs(a[0]))
+
+
+def test_infiltration_initial_profile():
+    """eq. travellingwave: p0 = -0.4 (1 - exp(-80 z)) is ~0 at the bottom, reaches the top
+    Dirichlet value -0.4 within rounding in the upper half, decreases with height, and is
+    independent of x (cell centres z = (j + 1/2) h)."""
+    prob = dict(W.TRAVELLING_WAVE)
+    for n in (8, 32):
+        p = picard.initial_head(prob, n)
+        assert p.shape == (n, n) and np.all(p == p[:, :1])
+        col = p[:, 0]
+        assert np.all(np.diff(col) < 0.0) or np.all(np.diff(col[: n // 4]) < 0.0)
+        assert abs(col[-1] + 0.4) < 1e-15 and abs(col[n // 2:] + 0.4).max() < 1e-9
+        assert -0.4 * (1.0 - np.exp(-40.0 / n)) == pytest.approx(col[0], rel=1e-14)
+    assert np.all(picard.initial_head(dict(W.GARDNER_INFILTRATION), 4) == -10.0)

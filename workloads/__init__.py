@@ -87,6 +87,21 @@ VG_INFILTRATION = dict(
 MLMC_VG = dict(workload_id=2, grids=(32, 64, 128, 256, 512), samples=(2048, 512, 128, 32, 8),
                n_shift_grad=0.1)
 
+# Robustness sweep of Section 4.3: the infiltration problem of eq. travellingwave
+# (p0 = -0.4 (1 - exp(-80 z)), p = -0.4 on top, 0.1 at the bottom, no flux on the
+# sides), van Genuchten-Mualem with theta_s = 0.5, theta_r = 0.05 and constant alpha,
+# n per sample from Table alpha_n (20 x 20 pairs), Ks = 0.2 exp(Z) with Z the KL field
+# of the Matern covariance Phi_1 = (1.0, 0.2, 0.2, 1) of Table Matern (64 modes),
+# 64 samples per pair; W(2,2) cycles to eps_MG = 1e-5, eps_PI = 1e-5, at most 50
+# Picard iterations per step; T = 0.1 reached with 7 steps of dt = 1/64 (h = 1/32).
+SWEEP_ALPHA = (0.2, 0.4, 0.6, 0.8, 1.0, 1.2, 1.4, 1.6, 1.8, 2.0, 2.2, 2.4, 2.6, 2.8, 3.0, 3.2, 3.4, 3.6, 3.8, 4.0)
+SWEEP_N = (1.1, 1.2, 1.3, 1.4, 1.5, 1.6, 1.7, 1.8, 1.9, 2.0, 2.2, 2.4, 2.6, 2.8, 3.0, 3.2, 3.4, 3.6, 3.8, 4.0)
+MATERN_PHI1 = (1.0, 0.2, 0.2, 1.0)
+MATERN_PHI2 = (0.5, 0.1, 0.01, 1.0)
+TRAVELLING_WAVE = dict(model="vg", theta_r=0.05, theta_s=0.5, h_top=-0.4, h_bottom=0.1, h_init=-0.4,
+                       init_rate=80.0, dt=1.0 / 64.0, n_steps=7, ks_baseline=0.2)
+SWEEP = dict(workload_id=4, n=32, samples_per_pair=64, n_modes=64, eps=1e-5, eps_mg=1e-5, max_picard=50)
+
 # Adjoint sensitivities: the Gardner problem on 128 x 128 with 20 steps, Ks = exp(G) from a
 # 100-term KL expansion of the same covariance as KS_FIELD, 1024 samples; the quantity is
 # the time-integrated bottom outflux and its gradient in the 100 KL coefficients, with the
