@@ -67,8 +67,12 @@ hipError_t launch_kl_fields(int N, int M, int64_t rows, int F, const double* B, 
 }
 
 // ------------------------------------------------------------- level sums
-// Neumaier-compensated sums over the pairs of one level in sample order
-// (Section 5.1 eqs. SMC, MC_var need sum Y, sum Y^2 and the same for Q_f, Q_c).
+// Compensated sums over the pairs of one level (Section 5.1 eqs. SMC, MC_var need
+// sum Y, sum Y^2 and the same for Q_f, Q_c).  Thread t of the workgroup takes pairs
+// t, t + 256, ... with Neumaier compensation; the 256 partial sums (value + its
+// compensation) are then added in thread order as double-double numbers by thread
+// 0.  The order is fixed, so the result does not depend on scheduling.
+constexpr int kSumThreads = 256;
 struct Neu {
   double s, c;
 };
@@ -80,14 +84,25 @@ __device__ __forceinline__ void neu_add(Neu& a, double x) {
     a.c += (x - t) + a.s;
   a.s = t;
 }
+// a += (b.s + b.c) in double-double arithmetic (TwoSum of the leading parts).
+__device__ __forceinline__ void dd_acc(Neu& a, const Neu& b) {
+  const double s = a.s + b.s;
+  const double bb = s - a.s;
+  const double e = (a.s - (s - bb)) + (b.s - bb);
+  a.s = s;
+  a.c += e + b.c;
+}
 
-__global__ void k_level_sums(const double* qf, const double* qc, int64_t n, const int32_t* stf,
-                             const int32_t* stc, const rmg_sample_stats* sf,
-                             const rmg_sample_stats* sc, rmg_level_sums* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  Neu y = {0, 0}, y2 = {0, 0}, f = {0, 0}, f2 = {0, 0}, c = {0, 0}, c2 = {0, 0};
-  int64_t ok = 0, bad = 0, its = 0, cyc = 0, cyc_c = 0;
-  for (int64_t i = 0; i < n; ++i) {
+__global__ __launch_bounds__(kSumThreads) void k_level_sums(const double* qf, const double* qc, int64_t n,
+                                                            const int32_t* stf, const int32_t* stc,
+                                                            const rmg_sample_stats* sf,
+                                                            const rmg_sample_stats* sc, rmg_level_sums* out) {
+  __shared__ Neu part[6][kSumThreads];
+  __shared__ long long cnt[5][kSumThreads];
+  Neu acc[6];
+  for (int k = 0; k < 6; ++k) acc[k] = Neu{0.0, 0.0};
+  long long ok = 0, bad = 0, its = 0, cyc = 0, cyc_c = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kSumThreads) {
     its += sf[i].picard_its + (sc ? sc[i].picard_its : 0);
     cyc += sf[i].mg_cycles + (sc ? sc[i].mg_cycles : 0);
     cyc_c += sc ? sc[i].mg_cycles : 0;
@@ -98,32 +113,49 @@ __global__ void k_level_sums(const double* qf, const double* qc, int64_t n, cons
     }
     ++ok;
     const double a = qf[i], b = qc ? qc[i] : 0.0, d = a - b;
-    neu_add(y, d);
-    neu_add(y2, d * d);
-    neu_add(f, a);
-    neu_add(f2, a * a);
-    neu_add(c, b);
-    neu_add(c2, b * b);
+    neu_add(acc[0], d);
+    neu_add(acc[1], d * d);
+    neu_add(acc[2], a);
+    neu_add(acc[3], a * a);
+    neu_add(acc[4], b);
+    neu_add(acc[5], b * b);
+  }
+  for (int k = 0; k < 6; ++k) part[k][threadIdx.x] = acc[k];
+  cnt[0][threadIdx.x] = ok;
+  cnt[1][threadIdx.x] = bad;
+  cnt[2][threadIdx.x] = its;
+  cnt[3][threadIdx.x] = cyc;
+  cnt[4][threadIdx.x] = cyc_c;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  Neu tot[6];
+  long long c5[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < 6; ++k) tot[k] = Neu{0.0, 0.0};
+  for (int t = 0; t < kSumThreads; ++t) {
+    for (int k = 0; k < 6; ++k) dd_acc(tot[k], part[k][t]);
+    for (int k = 0; k < 5; ++k) c5[k] += cnt[k][t];
   }
   rmg_level_sums o;
-  o.n = ok;
-  o.n_failed = bad;
-  o.picard_its = its;
-  o.mg_cycles = cyc;
-  o.mg_cycles_coarse = cyc_c;
-  o.sY = {y.s, y.c};
-  o.sY2 = {y2.s, y2.c};
-  o.sQf = {f.s, f.c};
-  o.sQf2 = {f2.s, f2.c};
-  o.sQc = {c.s, c.c};
-  o.sQc2 = {c2.s, c2.c};
+  o.n = c5[0];
+  o.n_failed = c5[1];
+  o.picard_its = c5[2];
+  o.mg_cycles = c5[3];
+  o.mg_cycles_coarse = c5[4];
+  rmg_dd* dst[6] = {&o.sY, &o.sY2, &o.sQf, &o.sQf2, &o.sQc, &o.sQc2};
+  for (int k = 0; k < 6; ++k) {
+    // renormalise: hi = fl(s + c), lo = the rounding error of that sum
+    const double hi = tot[k].s + tot[k].c;
+    const double bb = hi - tot[k].s;
+    const double lo = (tot[k].s - (hi - bb)) + (tot[k].c - bb);
+    *dst[k] = {hi, lo};
+  }
   *out = o;
 }
 
 hipError_t launch_level_sums(const double* qf, const double* qc, int64_t n, const int32_t* stf,
                              const int32_t* stc, const rmg_sample_stats* sf,
                              const rmg_sample_stats* sc, rmg_level_sums* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_level_sums, dim3(1), dim3(64), 0, st, qf, qc, n, stf, stc, sf, sc, out);
+  hipLaunchKernelGGL(k_level_sums, dim3(1), dim3(kSumThreads), 0, st, qf, qc, n, stf, stc, sf, sc, out);
   return hipGetLastError();
 }
 
