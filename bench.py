@@ -407,6 +407,112 @@ def adjoint_bench(args, torch, rmg, W):
     print(json.dumps(res), flush=True)
 
 
+# ------------------------------------------------------------ adaptive PC_MLMC
+def pcmlmc_bench(args, torch, rmg, W):
+    """Algorithm 1 (pc_mlmc) with parametric continuation, cost in work units.  One step = one
+    whole adaptive run (warm-up, updates of N_l, all batches).
+
+    gardner (default): the Gardner problem of the MLMC workload on levels 16^2 .. 16 * 2^(L-1)
+    with the exponent a as the continuation parameter, a_l = 1 - 0.1 (L - 1 - l);
+    vg: the van Genuchten fields of the vg workload on levels 32^2 .. 32 * 2^(L-1) with n shifted
+    by (L - 1 - l) * 0.1.  With one V(2,2) per Picard step to 1e-8 most van Genuchten pairs on
+    128^2 and finer exceed the iteration limit (the modified Picard iteration stalls as the
+    infiltration front steepens), so Algorithm 1 cannot reach its targets there: the draws per
+    level are capped (max_pairs) and the run then reports RMG_ENOTCONV."""
+    from paper_1903_08741_amd import _abi, kl_setup
+    dev = torch.device("cuda:0")
+    L = args.levels
+    vg = args.pc_model == "vg"
+    if vg:
+        cfg, vf, g = W.PC_MLMC_VG, W.VG_FIELDS, W.VG_INFILTRATION
+        grids = cfg["grids"][:L]
+        _, tables = kl_setup.kl_tables(1.0, vf["corr_len"], vf["n_modes"], list(grids) + [grids[0] // 2])
+        F, M, marg, wid = 3, vf["n_modes"], list(vf["marginals"]), cfg["workload_id"]
+        warm = cfg["warmup"]
+
+        def prob(l):
+            return rmg.Problem(model=rmg.VGM, n_steps=args.time_steps, theta_r=g["theta_r"], theta_s=g["theta_s"],
+                               h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"], dt=g["dt"],
+                               vg_n_shift=(L - 1 - l) * cfg["n_shift_grad"])
+        theta = f"n shifted by (L-1-l)*{cfg['n_shift_grad']}, {args.time_steps} steps dt={g['dt']}"
+    else:
+        f, g = W.KS_FIELD, W.GARDNER_INFILTRATION
+        grids = tuple(16 << l for l in range(L))
+        _, tables = kl_setup.kl_tables(f["sigma2"], f["corr_len"], f["n_modes"], list(grids) + [8])
+        F, M, marg, wid = 1, f["n_modes"], [(0.0, f["log_mean"], f["scale"])], 6
+        warm = (64, 32, 16, 8, 8, 4)
+
+        def prob(l):
+            return rmg.Problem(model=rmg.GARDNER, n_steps=g["n_steps"], theta_r=g["theta_r"], theta_s=g["theta_s"],
+                               gardner_a=1.0 - 0.1 * (L - 1 - l), h_top=g["h_top"], h_bottom=g["h_bottom"],
+                               h_init=g["h_init"], dt=g["dt"])
+        theta = f"Gardner a_l = 1 - 0.1 (L-1-l), {g['n_steps']} steps dt={g['dt']}"
+    levels = []
+    for l, n in enumerate(grids):
+        levels.append(dict(n_fine=n, n_coarse=n // 2 if l else 0, n_warmup=warm[l], fine=prob(l),
+                           coarse=prob(l - 1) if l else None,
+                           basis_fine=torch.from_numpy(tables[n]).to(dev),
+                           basis_coarse=torch.from_numpy(tables[n // 2]).to(dev) if l else None))
+
+    def src(level, first, count):
+        log(f"  draw level {level}: pairs {first}..{first + count - 1}")
+        return W.xi_draws(wid, level, range(first, first + count), F, M)
+    ctx = rmg.default_context(0)
+    precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
+
+    def run(prec):
+        opts = rmg.SolverOpts(precision=prec, max_picard=args.max_picard)
+        return ctx.pc_mlmc(levels, marg, opts, args.eps, src, max_rounds=50, max_pairs=args.max_pairs)
+    for i in range(args.warmup):
+        run(precision)
+        torch.cuda.synchronize()
+    ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = run(precision)
+        log(f"step {i} done rc={r['rc']} rounds={r['rounds']}")
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    kt = ctx.kernel_timing()
+    ctx.set_kernel_timing(_abi.TIME_NONE)
+    gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
+    solves = sum(x["drawn"] * (2 if l else 1) for l, x in enumerate(r["levels"]))
+    lv = [{"grid": grids[l], "pairs_drawn": x["drawn"], "successful": x["sums"]["n"], "failed": x["sums"]["n_failed"],
+           "N_l": x["target"], "W_l": x["W"], "V_l": x["V"], "mean_Y": x["mean"]} for l, x in enumerate(r["levels"])]
+    rmse = (r["bias"] ** 2 + r["sampling_err2"]) ** 0.5 if L > 1 else r["sampling_err2"] ** 0.5
+    extras = {}
+    if not args.no_extras and precision == rmg.MIXED:
+        t1 = time.perf_counter()
+        r64 = run(rmg.FP64)
+        extras["fp64_path"] = {"ms": 1e3 * (time.perf_counter() - t1), "mean": r64["mean"],
+                               "sampling_err": r64["sampling_err2"] ** 0.5,
+                               "mean_difference": r["mean"] - r64["mean"],
+                               "pairs_drawn": [x["drawn"] for x in r64["levels"]]}
+    res = {
+        "metric": "PC_MLMC wall time to the sampling tolerance (Algorithm 1)",
+        "value": ms / 1000.0, "unit": "s per adaptive run", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32 multigrid in f64 Picard" if precision == rmg.MIXED else "f64",
+        "data": "synthetic (seeded KL fields)",
+        "config": {"workload": f"PC_MLMC, {'van Genuchten-Mualem' if vg else 'Gardner'}, {L} levels "
+                               f"{grids[0]}^2..{grids[-1]}^2, {theta}, eps {args.eps:g}, work cost model, "
+                               f"V(2,2) per Picard, eps_PI 1e-8, at most {args.max_pairs} pairs per level",
+                   "levels": lv, "rounds": r["rounds"], "calls": r["calls"], "solves": solves,
+                   "converged": bool(r["converged"]), "rc": r["rc"], "precision": args.precision,
+                   "max_picard": args.max_picard},
+        "estimate": {"mean": r["mean"], "var": r["var"], "sampling_err": r["sampling_err2"] ** 0.5,
+                     "bias_estimate": r["bias"], "rmse_estimate": rmse},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "k_down over every batch of the run",
+                     "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"])},
+        "cpu_baseline": None,
+    }
+    res.update(extras)
+    print(json.dumps(res), flush=True)
+
+
 # ------------------------------------------------------------ robustness sweep
 def sweep_bench(args, torch, rmg, W):
     """Section 4.3's robustness sweep as one batched solve: the 20 x 20 (alpha, n) pairs of
@@ -476,11 +582,16 @@ def sweep_bench(args, torch, rmg, W):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("gardner", "vg", "adjoint", "sweep"), default="gardner",
+    ap.add_argument("--workload", choices=("gardner", "vg", "adjoint", "sweep", "pcmlmc"), default="gardner",
                     help="gardner: the 5-level Gardner MLMC workload (default); vg: the van Genuchten "
                          "workload with three fields and continuation (5 levels 32^2..512^2); adjoint: "
                          "outflux gradients of 1024 samples of 128^2 (100 KL modes, 20 steps); sweep: the "
                          "alpha-n robustness sweep of the infiltration problem (25600 solves of 32^2)")
+    ap.add_argument("--levels", type=int, default=4, help="pcmlmc: number of levels (at most 6)")
+    ap.add_argument("--eps", type=float, default=2e-3, help="pcmlmc: sampling tolerance")
+    ap.add_argument("--time-steps", type=int, default=20, help="pcmlmc vg: backward-Euler steps (dt = 0.005)")
+    ap.add_argument("--pc-model", choices=("gardner", "vg"), default="gardner", help="pcmlmc: hierarchy")
+    ap.add_argument("--max-pairs", type=int, default=50000, help="pcmlmc: cap on the pairs drawn per level")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
@@ -507,6 +618,9 @@ def main():
         return
     if args.workload == "sweep":
         sweep_bench(args, torch, rmg, W)
+        return
+    if args.workload == "pcmlmc":
+        pcmlmc_bench(args, torch, rmg, W)
         return
     dev = torch.device("cuda:0")
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64

@@ -102,6 +102,13 @@ TRAVELLING_WAVE = dict(model="vg", theta_r=0.05, theta_s=0.5, h_top=-0.4, h_bott
                        init_rate=80.0, dt=1.0 / 64.0, n_steps=7, ks_baseline=0.2)
 SWEEP = dict(workload_id=4, n=32, samples_per_pair=64, n_modes=64, eps=1e-5, eps_mg=1e-5, max_picard=50)
 
+# Adaptive PC_MLMC (Algorithm 1) on the van Genuchten fields above: levels 32^2 .. 32 * 2^L
+# with n shifted by (L - l) * 0.1 on level l, warm-up pairs per level, tolerance eps of the
+# sampling error; dt = 0.005 as in MLMC_VG (the full hierarchy runs 6 levels to 1024^2 with
+# 100 steps and eps = 1e-3; the default benchmark run is the first four levels, 20 steps).
+PC_MLMC_VG = dict(workload_id=5, grids=(32, 64, 128, 256, 512, 1024), warmup=(64, 32, 16, 8, 4, 4),
+                  n_shift_grad=0.1, n_steps_full=100, eps_full=1e-3)
+
 # Adjoint sensitivities: the Gardner problem on 128 x 128 with 20 steps, Ks = exp(G) from a
 # 100-term KL expansion of the same covariance as KS_FIELD, 1024 samples; the quantity is
 # the time-integrated bottom outflux and its gradient in the 100 KL coefficients, with the
