@@ -273,7 +273,7 @@ __global__ void k_adj_init(SolveArgs a, StreamPlan pl, AdjArgs ad, const int32_t
     z.nanflag = 0;
     z.final_dp = 0.0;
     z.pend = 0;
-    z.pad_ = 0;
+    z.fresh = 0;
     pl.state[s] = z;
     pl.dpmax[s] = 0ull;
   }

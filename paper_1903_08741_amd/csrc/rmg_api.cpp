@@ -160,7 +160,7 @@ size_t class_ws_bytes(const ClassJob& j) {
   size_t b = 256 + 8 * (size_t)S * n * n;  // theta_old
   if (!j.whole) {
     for (int l = 0; l <= j.pl.ltop; ++l) b += 256 * 7 + level_bytes(n >> l, S, j.fp64);
-    b += 3 * 256 + sizeof(SampleState) * S + 8 * S + 8;
+    b += 6 * 256 + 2 * (sizeof(SampleState) * S + 8 * S + 8);
   }
   return b;
 }
@@ -182,8 +182,11 @@ void class_carve(ClassJob& j, Arena& ar) {
     j.pl.lv.ctop[l] = ar.take(es * S * m);
   }
   j.pl.state = (SampleState*)ar.take(sizeof(SampleState) * S);
+  j.pl.state_prev = (SampleState*)ar.take(sizeof(SampleState) * S);
   j.pl.dpmax = (unsigned long long*)ar.take(8 * S);
+  j.pl.dpmax_prev = (unsigned long long*)ar.take(8 * S);
   j.pl.active_count = (int32_t*)ar.take(8);
+  j.pl.count_next = (int32_t*)ar.take(8);
 }
 
 void class_plan(ClassJob& j, const rmg_solver_opts* o) {
@@ -232,10 +235,12 @@ int autotune_class(rmg_ctx* ctx, ClassJob& j) {
   bool first = true;
   for (auto& c : cand) {
     set_tiles(j, c[0], c[1]);
+    const StreamPlan odd = flip(j.pl);
     HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
     HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream));
+    HIP_TRY(ctx, launch_stream_iteration(j.a, odd, j.stream));
     HIP_TRY(ctx, hipEventRecord(ctx->tev[0], j.stream));
-    for (int i = 0; i < 4; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream));
+    for (int i = 0; i < 4; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, (i & 1) ? odd : j.pl, j.stream));
     HIP_TRY(ctx, hipEventRecord(ctx->tev[1], j.stream));
     HIP_TRY(ctx, hipEventSynchronize(ctx->tev[1]));
     float ms = 0.f;
@@ -270,8 +275,9 @@ int harvest_timer(rmg_ctx* ctx, KernelTimer* t, int64_t upto) {
 
 // Run every class to completion.  Whole-sample classes are single launches.  A
 // streaming class advances in batches of G Picard iterations (a replayed HIP graph,
-// or eager launches); each batch ends with a 4-byte read-back of the class's
-// active-sample count and an event.  D batches stay in flight per class, so the
+// or eager launches) of alternating plan parity (G is even, so every batch starts
+// with the even plan and ends with the odd one); each batch ends with a 4-byte
+// read-back of the class's active-sample count (of its last iteration) and an event.  D batches stay in flight per class, so the
 // device never waits for the host; batches issued after the count reached zero
 // find no active sample and do nothing.  Classes are polled independently.
 // With kernel timing on, the first iteration of every batch is launched eagerly
@@ -280,6 +286,7 @@ int harvest_timer(rmg_ctx* ctx, KernelTimer* t, int64_t upto) {
 // launches, one in G, at almost no cost to the run.
 int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
   constexpr int G = 8, D = 3;
+  static_assert(G % 2 == 0, "a batch must end on the odd plan (double-buffered per-sample state)");
   const bool timing = ctx->timing != 0;
   const int Gg = timing ? G - 1 : G;  // iterations per graph replay
   if (jobs.size() > 16) return fail(ctx, RMG_EINVAL, "too many grid-size classes");
@@ -324,10 +331,13 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
       if (j.done) continue;
       StreamPlan untimed = j.pl;
       untimed.timer = nullptr;
+      const StreamPlan untimed_odd = flip(untimed);
       const char* what = "hipStreamBeginCapture";
       hipError_t e = hipStreamBeginCapture(j.stream, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) what = "captured iteration launches";
-      for (int i = 0; i < Gg && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, untimed, j.stream);
+      // with timing the batch's first (even) iteration is launched eagerly
+      for (int i = 0; i < Gg && e == hipSuccess; ++i)
+        e = launch_stream_iteration(j.a, ((i + (timing ? 1 : 0)) & 1) ? untimed_odd : untimed, j.stream);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(j.stream, &g);
       graphs[c] = g;
@@ -371,15 +381,17 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     const int k = (int)(issued[c] % D);
     StreamPlan untimed = j.pl;
     untimed.timer = nullptr;
+    const StreamPlan untimed_odd = flip(untimed);
     hipError_t e = hipSuccess;
     if (timing) e = launch_stream_iteration(j.a, j.pl, j.stream);
     if (use_graphs) {
       if (e == hipSuccess) e = hipGraphLaunch(execs[c], j.stream);
     } else {
-      for (int i = timing ? 1 : 0; i < G && e == hipSuccess; ++i) e = launch_stream_iteration(j.a, untimed, j.stream);
+      for (int i = timing ? 1 : 0; i < G && e == hipSuccess; ++i)
+        e = launch_stream_iteration(j.a, (i & 1) ? untimed_odd : untimed, j.stream);
     }
     if (e == hipSuccess)
-      e = hipMemcpyAsync(j.h_count + k, j.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, j.stream);
+      e = hipMemcpyAsync(j.h_count + k, flip(j.pl).active_count, sizeof(int32_t), hipMemcpyDeviceToHost, j.stream);
     if (e == hipSuccess) e = hipEventRecord(ctx->pev[c][k], j.stream);
     mark[c][k] = j.pl.timer ? j.pl.timer->tail : 0;
     ++issued[c];
@@ -412,7 +424,7 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
       const int32_t left = ((volatile int32_t*)j.h_count)[k];
       ++retired[c];
       if (left == 0) {
-        e = launch_stream_finish(j.a, j.pl, j.stream);
+        e = launch_stream_finish(j.a, flip(j.pl), j.stream);
         if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "finish launch: %s", hipGetErrorString(e));
         j.done = true;
         --active;

@@ -24,8 +24,8 @@ struct SampleState {
   int32_t active, new_step, step, it;
   int32_t status, tot_its, cycles, nanflag;
   double final_dp;
-  int32_t pend;  // adjoint: the step above `step` converged and its gradient term is pending
-  int32_t pad_;
+  int32_t pend;   // adjoint: the step above `step` converged and its gradient term is pending
+  int32_t fresh;  // streaming forward: no iteration has run yet (no stopping test pending)
 };
 
 // Problems of one grid-size class: samples [0, seg_split) use prob[0], the rest prob[1].
@@ -112,16 +112,39 @@ struct StreamPlan {
   int ts[kMaxLevels]; // output tile edge (16 or 32) of the down/up kernels per streaming level
   bool fp64;
   LevelPtrs lv;
+  // The per-sample state, the ||dp||_inf maxima and the active-sample counter are
+  // double-buffered by iteration parity: iteration i works on state / dpmax /
+  // active_count and decides the stopping test of iteration i - 1 from state_prev /
+  // dpmax_prev at its start (the fine kernel), so no separate control launch is
+  // needed.  flip() gives the plan of the other parity.
   SampleState* state;
+  SampleState* state_prev;
   unsigned long long* dpmax;
+  unsigned long long* dpmax_prev;
   int32_t* active_count;
+  int32_t* count_next;  // the counter of the next iteration (cleared by this one)
   KernelTimer* timer;               // host object, never dereferenced on the device
   unsigned long long* tcells;       // device counters of a timed launch, else null
 };
+inline StreamPlan flip(const StreamPlan& p) {
+  StreamPlan q = p;
+  q.state = p.state_prev;
+  q.state_prev = p.state;
+  q.dpmax = p.dpmax_prev;
+  q.dpmax_prev = p.dpmax;
+  q.active_count = p.count_next;
+  q.count_next = p.active_count;
+  return q;
+}
 hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 // Kernel attributes of the streaming kernels (call once before launching or capturing).
 hipError_t prepare_stream(const SolveArgs& a, const StreamPlan& pl);
 // One Picard iteration of every active sample: stream operations only, capturable.
+// Successive iterations must alternate the plan's parity (pl, flip(pl), pl, ...),
+// starting with the plan given to launch_stream_init; the state after an iteration
+// is in that iteration's plan's `state` (its stopping test is taken by the next
+// iteration, or is pending: the loop ends after an iteration in which no sample was
+// active, counted in that iteration's active_count).
 hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 // The multigrid cycles of one iteration (down legs, coarse kernel, up legs; the finest

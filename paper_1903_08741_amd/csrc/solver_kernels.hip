@@ -9,7 +9,7 @@
 //     all samples of a grid size: the fine residual (k_fine), the down and up
 //     legs of the levels finer than the coarse kernel's top (rmg_smoother.hpp),
 //     the one-workgroup-per-sample coarse V-cycle in LDS (k_coarse_v) and the
-//     per-sample control (k_control).
+//     stopping test of the previous iteration at the start of k_fine.
 // Section 4.1 (modified Picard) and Section 4.2 (cell-centred multigrid).
 #include <math.h>
 
@@ -327,7 +327,7 @@ hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
 }
 
 // ============================================================ level streaming
-__global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long long* dpmax) {
+__global__ void k_stream_init(SolveArgs a, StreamPlan pl) {
   const int64_t N = (int64_t)a.n * a.n;
   const int64_t tot = a.S * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
@@ -348,9 +348,40 @@ __global__ void k_stream_init(SolveArgs a, SampleState* state, unsigned long lon
     z.nanflag = 0;
     z.final_dp = 0.0;
     z.pend = 0;
-    z.pad_ = 0;
-    state[s] = z;
-    dpmax[s] = 0ull;
+    z.fresh = 1;
+    pl.state[s] = z;
+    pl.state_prev[s] = z;
+    pl.dpmax[s] = 0ull;
+    pl.dpmax_prev[s] = 0ull;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *pl.active_count = 0;
+    *pl.count_next = 0;
+  }
+}
+
+// The stopping test and step bookkeeping of one sample after a Picard iteration
+// whose ||dp||_inf is dp (Section 4.1: stop the step when ||dp||_inf < eps_PI;
+// Section 4.3: give up after max_picard iterations in a step).
+__device__ __forceinline__ void control_step(SampleState& st, double dp, const SolveArgs& a, const rmg_problem& P) {
+  st.it += 1;
+  st.tot_its += 1;
+  st.cycles += a.cpp;
+  st.final_dp = dp;
+  if (st.nanflag) {
+    st.status = RMG_SAMPLE_NONFINITE;
+    st.active = 0;
+  } else if (dp < a.eps) {
+    st.step += 1;
+    st.it = 0;
+    st.new_step = 1;
+    if (st.step == P.n_steps) st.active = 0;
+  } else {
+    st.new_step = 0;
+    if (st.it >= a.max_picard) {
+      st.status = RMG_SAMPLE_MAXITER;
+      st.active = 0;
+    }
   }
 }
 
@@ -362,10 +393,22 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   __shared__ double sp[34 * 34], sK[34 * 34];
   __shared__ R bufA[3 * 32 * 32 + 32], bufB[3 * 16 * 16 + 16];
   const int64_t s = blockIdx.y;
-  if (blockIdx.x == 0 && s == 0 && threadIdx.x == 0) *pl.active_count = 0;
-  if (!pl.state[s].active) return;
-  const int new_step = pl.state[s].new_step;
   const rmg_problem P = class_problem(a.cp, s);
+  // stopping test of the previous iteration (every workgroup of the sample takes the
+  // same decision; the first one stores it and clears this iteration's maximum)
+  SampleState st = pl.state_prev[s];
+  if (st.fresh)
+    st.fresh = 0;
+  else if (st.active)
+    control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    pl.state[s] = st;
+    pl.dpmax[s] = 0ull;
+    if (st.active) atomicAdd(pl.active_count, 1);
+    if (s == 0) *pl.count_next = 0;
+  }
+  if (!st.active) return;
+  const int new_step = st.new_step;
   const int n = a.n;
   const int T = n < kTile ? n : kTile, TL = T + 2;
   const int ntx = n / T;
@@ -417,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   double* thold = a.theta_old + s * N;
   double* hist = nullptr;  // history slot of the step that starts here, if recorded
   if (new_step && a.p_hist) {
-    const int k = pl.state[s].step;
+    const int k = st.step;
     if (k % a.hist_every == 0) hist = a.p_hist + (s * a.hist_slots + k / a.hist_every) * N;
   }
   RMG_TILE_FOR(T, li, lj) {
@@ -565,38 +608,6 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   }
 }
 
-// Per-sample stopping test and time-step bookkeeping after one Picard iteration.
-__global__ void k_control(SolveArgs a, StreamPlan pl) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= a.S) return;
-  SampleState st = pl.state[s];
-  if (!st.active) return;
-  const rmg_problem& P = class_problem(a.cp, s);
-  const double dp = __longlong_as_double((long long)pl.dpmax[s]);
-  pl.dpmax[s] = 0ull;
-  st.it += 1;
-  st.tot_its += 1;
-  st.cycles += a.cpp;
-  st.final_dp = dp;
-  if (st.nanflag) {
-    st.status = RMG_SAMPLE_NONFINITE;
-    st.active = 0;
-  } else if (dp < a.eps) {
-    st.step += 1;
-    st.it = 0;
-    st.new_step = 1;
-    if (st.step == P.n_steps) st.active = 0;
-  } else {
-    st.new_step = 0;
-    if (st.it >= a.max_picard) {
-      st.status = RMG_SAMPLE_MAXITER;
-      st.active = 0;
-    }
-  }
-  pl.state[s] = st;
-  if (st.active) atomicAdd(pl.active_count, 1);
-}
-
 __global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPlan pl) {
   __shared__ double red[kBlock];
   const int64_t s = blockIdx.x;
@@ -632,7 +643,7 @@ hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStrea
   const int64_t tot = a.S * (int64_t)a.n * a.n;
   int64_t blocks = (tot + kBlock - 1) / kBlock;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_stream_init, dim3((unsigned)blocks), dim3(kBlock), 0, st, a, pl.state, pl.dpmax);
+  hipLaunchKernelGGL(k_stream_init, dim3((unsigned)blocks), dim3(kBlock), 0, st, a, pl);
   return hipGetLastError();
 }
 
@@ -729,7 +740,6 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
   }
   const hipError_t err = stream_cycles<R>(a, pl, st);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_control, dim3((unsigned)((a.S + kBlock - 1) / kBlock)), blk, 0, st, a, pl);
   return hipGetLastError();
 }
 
