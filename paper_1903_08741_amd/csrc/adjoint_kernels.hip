@@ -99,7 +99,7 @@ __device__ __forceinline__ void adj_load_tile(const SolveArgs& a, const rmg_prob
                                               const double* pk, const double* mu, int n, int x0, int y0, int TL,
                                               double* sp, double* sK, double* sm) {
   const int64_t N = (int64_t)n * n;
-  for (int k = threadIdx.x; k < TL * TL; k += blockDim.x) {
+  for (int k = threadIdx.x; k < TL * TL; k += kBlock) {
     const int lj = k / TL, li = k - lj * TL;
     const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
     double pv = 0.0, Kv = 0.0, mv = 0.0;

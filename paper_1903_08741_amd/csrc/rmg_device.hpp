@@ -215,6 +215,8 @@ __device__ __forceinline__ R restrict4(R r00, R r01, R r10, R r11) {
 }
 
 // ------------------------------------------------------------ block helpers
+// NT: the workgroup size (compile-time constant).
+template <int NT>
 __device__ __forceinline__ double block_max(double v, double* red) {
   // wave64 reduction through LDS; every thread returns the block maximum
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -223,22 +225,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   if (lane == 0) red[wave] = v;
   __syncthreads();
   double r = red[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
-  return r;
-}
-
-// Fixed-order block sum (every thread returns the same value, identical on
-// every launch with the same blockDim).
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  __syncthreads();
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
+  for (int w = 1; w < NT / 64; ++w) r = fmax(r, red[w]);
   return r;
 }
 

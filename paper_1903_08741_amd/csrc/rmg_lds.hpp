@@ -1,4 +1,6 @@
 // Whole-grid multigrid levels held in LDS by one workgroup (gfx950, 160 KiB LDS per CU).
+// NT is the workgroup size (a compile-time constant, so that loops stride by a
+// constant instead of reading the launch size from the dispatch packet).
 //
 // Layout of a level with m x m cells (element type R):
 //   u   : one zero row, m*m cells, one zero row (plus one guard each end), so
@@ -71,11 +73,11 @@ __device__ __forceinline__ St5<R> lds_st5(const LdsLevel<R>& L, int c) {
 }
 
 // One colour of a red-black Gauss-Seidel sweep (colour 0 = red = (i+j) even).
-template <class R>
+template <class R, int NT>
 __device__ void lds_half_sweep(const LdsLevel<R>& L, int colour) {
   const int m = L.m, hlg = L.lg - 1;
   const int tot = (m * m) >> 1;
-  for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+  for (int k = threadIdx.x; k < tot; k += NT) {
     const int j = k >> hlg;
     const int q = k - (j << hlg);
     const int i = 2 * q + ((j + colour) & 1);
@@ -87,11 +89,11 @@ __device__ void lds_half_sweep(const LdsLevel<R>& L, int colour) {
 // Red half-sweep when the current iterate is zero: the neighbour sum vanishes, so
 // u = f / d without reading neighbours (the same operations as lds_half_sweep on a
 // zero iterate).
-template <class R>
+template <class R, int NT>
 __device__ void lds_half_sweep_from_zero(const LdsLevel<R>& L) {
   const int m = L.m, hlg = L.lg - 1;
   const int tot = (m * m) >> 1;
-  for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+  for (int k = threadIdx.x; k < tot; k += NT) {
     const int j = k >> hlg;
     const int q = k - (j << hlg);
     const int i = 2 * q + (j & 1);
@@ -105,11 +107,11 @@ __device__ void lds_half_sweep_from_zero(const LdsLevel<R>& L) {
 // read as u + (prolongated coarse correction); the red cells' own corrected values
 // are never needed (they are overwritten), and the black cells are overwritten by
 // the following black half-sweep, so no separate prolongation pass is required.
-template <class R>
+template <class R, int NT>
 __device__ void lds_half_sweep_prolong(const LdsLevel<R>& L, const LdsLevel<R>& C) {
   const int m = L.m, hlg = L.lg - 1, mc = C.m;
   const int tot = (m * m) >> 1;
-  for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+  for (int k = threadIdx.x; k < tot; k += NT) {
     const int j = k >> hlg;
     const int q = k - (j << hlg);
     const int i = 2 * q + (j & 1);
@@ -123,24 +125,24 @@ __device__ void lds_half_sweep_prolong(const LdsLevel<R>& L, const LdsLevel<R>& 
   }
 }
 
-template <class R>
+template <class R, int NT>
 __device__ void lds_sweeps(const LdsLevel<R>& L, int nu, bool from_zero = false) {
   for (int s = 0; s < nu; ++s) {
     if (s == 0 && from_zero)
-      lds_half_sweep_from_zero(L);
+      lds_half_sweep_from_zero<R, NT>(L);
     else
-      lds_half_sweep(L, 0);
+      lds_half_sweep<R, NT>(L, 0);
     __syncthreads();
-    lds_half_sweep(L, 1);
+    lds_half_sweep<R, NT>(L, 1);
     __syncthreads();
   }
 }
 
 // Coarse right-hand side = R (f - A u); coarse initial iterate 0.
-template <class R>
+template <class R, int NT>
 __device__ void lds_residual_restrict(const LdsLevel<R>& F, const LdsLevel<R>& C) {
   const int mc = C.m, m = F.m;
-  for (int kc = threadIdx.x; kc < mc * mc; kc += blockDim.x) {
+  for (int kc = threadIdx.x; kc < mc * mc; kc += NT) {
     const int J = kc >> C.lg, I = kc - (J << C.lg);
     const int c00 = (2 * J) * m + 2 * I;
     const R r00 = residual_value<R>(F.f[c00], F.u[c00], lds_st5(F, c00));
@@ -153,27 +155,27 @@ __device__ void lds_residual_restrict(const LdsLevel<R>& F, const LdsLevel<R>& C
 }
 
 // Piecewise-constant prolongation of the coarse correction (eq. transfer).
-template <class R>
+template <class R, int NT>
 __device__ void lds_prolong_add(const LdsLevel<R>& F, const LdsLevel<R>& C) {
   const int m = F.m;
-  for (int c = threadIdx.x; c < m * m; c += blockDim.x) {
+  for (int c = threadIdx.x; c < m * m; c += NT) {
     const int j = c >> F.lg, i = c - (j << F.lg);
     F.u[c] = F.u[c] + C.u[(j >> 1) * C.m + (i >> 1)];
   }
 }
 
 // Coefficients of the next coarser level.
-template <class R>
+template <class R, int NT>
 __device__ void lds_coarsen(const LdsLevel<R>& F, const LdsLevel<R>& C) {
   const int mc = C.m, m = F.m;
-  for (int kc = threadIdx.x; kc < mc * mc; kc += blockDim.x) {
+  for (int kc = threadIdx.x; kc < mc * mc; kc += NT) {
     const int J = kc >> C.lg, I = kc - (J << C.lg);
     const int c00 = (2 * J) * m + 2 * I;
     C.cw[kc] = coarse_face<R>(F.cw[c00], F.cw[c00 + m]);
     C.cs[kc] = coarse_face<R>(F.cs[c00], F.cs[c00 + 1]);
     C.cdt[kc] = coarse_cdt<R>(F.cdt[c00], F.cdt[c00 + 1], F.cdt[c00 + m], F.cdt[c00 + m + 1]);
   }
-  for (int I = threadIdx.x; I < mc; I += blockDim.x)
+  for (int I = threadIdx.x; I < mc; I += NT)
     C.cs[mc * mc + I] = coarse_face<R>(F.cs[m * m + 2 * I], F.cs[m * m + 2 * I + 1]);
 }
 
@@ -184,12 +186,12 @@ __device__ void lds_coarsen(const LdsLevel<R>& F, const LdsLevel<R>& C) {
 // reciprocal of the next pivot, final once step k is done, is formed by the
 // thread that writes it.  `A` is LDS scratch of N*(N+1) doubles and `ipiv` of N
 // doubles, N = m*m <= 16.
-template <class R>
+template <class R, int NT>
 __device__ void lds_coarsest_solve(const LdsLevel<R>& L, RMG_LDS double* A, RMG_LDS double* ipiv) {
   const int m = L.m, N = m * m, W = N + 1, lgN = 2 * L.lg;
-  for (int e = threadIdx.x; e < N * W; e += blockDim.x) A[e] = 0.0;
+  for (int e = threadIdx.x; e < N * W; e += NT) A[e] = 0.0;
   __syncthreads();
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+  for (int c = threadIdx.x; c < N; c += NT) {
     const int j = c >> L.lg, i = c - (j << L.lg);
     const double aw = (double)L.cw[c], ae = (double)L.cw[c + 1];
     const double as = (double)L.cs[c], an = (double)L.cs[c + m];
@@ -206,7 +208,7 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L, RMG_LDS double* A, RMG_
   __syncthreads();
   for (int k = 0; k < N; ++k) {
     const double pk = ipiv[k];
-    for (int e = threadIdx.x; e < N * N + N; e += blockDim.x) {
+    for (int e = threadIdx.x; e < N * N + N; e += NT) {
       int i, j;
       if (e < N * N) {
         i = e >> lgN;
@@ -222,7 +224,7 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L, RMG_LDS double* A, RMG_
     }
     __syncthreads();
   }
-  for (int c = threadIdx.x; c < N; c += blockDim.x) L.u[c] = (R)(A[c * W + N] * ipiv[c]);
+  for (int c = threadIdx.x; c < N; c += NT) L.u[c] = (R)(A[c * W + N] * ipiv[c]);
   __syncthreads();
 }
 
@@ -235,18 +237,18 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L, RMG_LDS double* A, RMG_
 
 // Post-smoothing of level l after its coarse correction (prolongation fused into the
 // first red half-sweep when nu2 > 0).
-template <class R>
+template <class R, int NT>
 __device__ void lds_up_leg(const LdsLevel<R>* lev, int l, int nu2) {
   if (RMG_FUSED_PROLONG && nu2 > 0) {
-    lds_half_sweep_prolong(lev[l], lev[l + 1]);
+    lds_half_sweep_prolong<R, NT>(lev[l], lev[l + 1]);
     __syncthreads();
-    lds_half_sweep(lev[l], 1);
+    lds_half_sweep<R, NT>(lev[l], 1);
     __syncthreads();
-    lds_sweeps(lev[l], nu2 - 1);
+    lds_sweeps<R, NT>(lev[l], nu2 - 1);
   } else {
-    lds_prolong_add(lev[l], lev[l + 1]);
+    lds_prolong_add<R, NT>(lev[l], lev[l + 1]);
     __syncthreads();
-    lds_sweeps(lev[l], nu2);
+    lds_sweeps<R, NT>(lev[l], nu2);
   }
 }
 
@@ -257,7 +259,7 @@ __device__ void lds_up_leg(const LdsLevel<R>* lev, int l, int nu2) {
 // every level before ascending past it.  A level's first visit starts from a zero
 // iterate (its restriction set it to zero), a second visit from the current
 // iterate.  `top_zero`: the iterate on level `top` is zero on entry.
-template <class R>
+template <class R, int NT>
 __device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, int gamma,
                           RMG_LDS double* A, RMG_LDS double* ipiv, bool top_zero) {
   int l = top;
@@ -265,13 +267,13 @@ __device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, in
   unsigned again = 0;  // bit l: level l owes one more coarse cycle (W-cycle)
   for (;;) {
     for (; l < nlev - 1; ++l) {
-      lds_sweeps(lev[l], nu1, RMG_ZERO_SWEEP && zero);
-      lds_residual_restrict(lev[l], lev[l + 1]);
+      lds_sweeps<R, NT>(lev[l], nu1, RMG_ZERO_SWEEP && zero);
+      lds_residual_restrict<R, NT>(lev[l], lev[l + 1]);
       __syncthreads();
       if (gamma == 2) again |= 1u << l;
       zero = true;
     }
-    lds_coarsest_solve(lev[nlev - 1], A, ipiv);
+    lds_coarsest_solve<R, NT>(lev[nlev - 1], A, ipiv);
     bool descend = false;
     while (l > top) {
       --l;
@@ -282,7 +284,7 @@ __device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, in
         descend = true;
         break;
       }
-      lds_up_leg(lev, l, nu2);
+      lds_up_leg<R, NT>(lev, l, nu2);
     }
     if (!descend) return;
   }

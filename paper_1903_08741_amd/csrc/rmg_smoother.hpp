@@ -351,8 +351,8 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
     mx = fmax(fmax(mx, fabs(d0)), fmax(fabs(d1), fmax(fabs(d2), fabs(d3))));
     if (!isfinite(d0) || !isfinite(d1) || !isfinite(d2) || !isfinite(d3)) bad = 1.0;
   }
-  mx = block_max(mx, red);
-  bad = block_max(bad, red);
+  mx = block_max<kBlock>(mx, red);
+  bad = block_max<kBlock>(bad, red);
   if (threadIdx.x == 0) {
     atomic_max_nonneg(pl.dpmax + s, mx);
     if (bad > 0.0) atomicOr(&pl.state[s].nanflag, 1);

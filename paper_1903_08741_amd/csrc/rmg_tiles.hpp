@@ -13,11 +13,11 @@ __device__ __forceinline__ const rmg_problem& class_problem(const ClassProblems&
   return s < cp.seg_split ? cp.prob[0] : cp.prob[1];
 }
 
-// Cells (ri, rj) of a w x w tile, distributed over the workgroup's threads.
+// Cells (ri, rj) of a w x w tile, distributed over the kBlock threads of the workgroup.
 #define RMG_TILE_FOR(w, ri, rj)                                                                 \
   for (int w_ = (w), once_ = 1; once_; once_ = 0)                                                 \
     for (unsigned mg_ = rmg_magic(w_), once2_ = 1u; once2_; once2_ = 0u)                          \
-      for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < w_ * w_; k_ += (int)blockDim.x)        \
+      for (int k_ = (int)threadIdx.x, rj = 0, ri = 0; k_ < w_ * w_; k_ += kBlock)                   \
         if ((rj = (int)__umulhi((unsigned)k_, mg_), ri = k_ - rj * w_), true)
 
 // Coefficients of the streaming levels 1 .. ltop inside the T x T fine tile at
@@ -61,7 +61,7 @@ __device__ void tile_coarsen(const StreamPlan& pl, int64_t s, int n, int T, int 
       gcs[gc] = cs;
       gcdt[gc] = cd;
     }
-    for (int I = threadIdx.x; I < tc; I += blockDim.x) {
+    for (int I = threadIdx.x; I < tc; I += kBlock) {
       const R ct = coarse_face<R>(scs[t * t + 2 * I], scs[t * t + 2 * I + 1]);
       dcs[tc * tc + I] = ct;
       if (y0 + T == n) gctop[X0 + I] = ct;

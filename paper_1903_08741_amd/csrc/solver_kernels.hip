@@ -26,10 +26,11 @@ namespace rmg {
 // kQoiLanes sums cells t, t + kQoiLanes, ... (thread k computes lanes k, k + B,
 // ... for a block of B threads), then a fixed binary tree over the lanes.
 constexpr int kQoiLanes = 256;
+template <int NT>
 __device__ double mean_saturation(const rmg_problem& P, const double* fields, int F, int64_t N,
                                   int64_t s, const double* p, double* red) {
   __syncthreads();
-  for (int t = threadIdx.x; t < kQoiLanes; t += blockDim.x) {
+  for (int t = threadIdx.x; t < kQoiLanes; t += NT) {
     double acc = 0.0;
     for (int64_t c = t; c < N; c += kQoiLanes) {
       const CellFields cf = load_fields(fields, F, N, s, c);
@@ -40,7 +41,7 @@ __device__ double mean_saturation(const rmg_problem& P, const double* fields, in
   }
   __syncthreads();
   for (int w = kQoiLanes >> 1; w > 0; w >>= 1) {
-    for (int t = threadIdx.x; t < w; t += blockDim.x) red[t] = red[t] + red[t + w];
+    for (int t = threadIdx.x; t < w; t += NT) red[t] = red[t] + red[t + w];
     __syncthreads();
   }
   const double r = red[0];
@@ -84,13 +85,13 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   R* rbase = (R*)(fS + (SL ? F * N : 0));
   __shared__ LdsLevel<R> lev[kMaxLevels];
   R* rend = lds_carve(rbase, lev, n, a.nlev);
-  for (R* q = rbase + threadIdx.x; q < rend; q += blockDim.x) *q = (R)0;
+  for (R* q = rbase + threadIdx.x; q < rend; q += NT) *q = (R)0;
 
   double* pg = a.p + s * N;
   double* const p = SL ? pS : pg;
   double* const thold = SL ? thS : a.theta_old + s * N;
   const double* const fld = SL ? fS : a.fields + s * F * N;  // field f of cell c at fld[f*N + c]
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+  for (int c = threadIdx.x; c < N; c += NT) {
     p[c] = a.p0 ? a.p0[s * a.p0_stride + c] : initial_head(P, c >> lg, n);
     if (SL)
       for (int f = 0; f < F; ++f) fS[f * N + c] = a.fields[(s * F + f) * N + c];
@@ -170,14 +171,14 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     }
     __syncthreads();
     for (int l = 0; l + 1 < a.nlev; ++l) {
-      lds_coarsen(lev[l], lev[l + 1]);
+      lds_coarsen<R, NT>(lev[l], lev[l + 1]);
       __syncthreads();
     }
     // a fixed number of cycles, or (cpp == 0) cycles until the correction equation's
     // residual max_c |f - A dp| (level 0, smoother precision) is below eps_mg
     int ncyc = 0;
     for (;;) {
-      lds_cycle(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, A, ipiv, ncyc == 0);
+      lds_cycle<R, NT>(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, A, ipiv, ncyc == 0);
       ++ncyc;
       if (a.cpp > 0) {
         if (ncyc == a.cpp) break;
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
       double rmax = 0.0;
       for (int c = threadIdx.x; c < N; c += NT)
         rmax = fmax(rmax, fabs((double)residual_value<R>(L0.f[c], L0.u[c], lds_st5(L0, c))));
-      rmax = block_max(rmax, red);
+      rmax = block_max<NT>(rmax, red);
       if (rmax < a.eps_mg || ncyc == kMaxMgCycles) break;
     }
     // Picard update p <- p + dp and ||dp||_inf
@@ -208,8 +209,8 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
         if (!isfinite(d)) bad = 1.0;
       }
     }
-    dp = block_max(mx, red);
-    const double anybad = block_max(bad, red);
+    dp = block_max<NT>(mx, red);
+    const double anybad = block_max<NT>(bad, red);
     ++it;
     ++tot_its;
     cycles += ncyc;
@@ -232,12 +233,12 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   }
   __syncthreads();
   if (SL)
-    for (int c = threadIdx.x; c < N; c += blockDim.x) pg[c] = p[c];
+    for (int c = threadIdx.x; c < N; c += NT) pg[c] = p[c];
   if (a.p_hist && status == RMG_SAMPLE_OK && P.n_steps % a.hist_every == 0) {
     double* hist = a.p_hist + (s * a.hist_slots + P.n_steps / a.hist_every) * N;
-    for (int c = threadIdx.x; c < N; c += blockDim.x) hist[c] = p[c];
+    for (int c = threadIdx.x; c < N; c += NT) hist[c] = p[c];
   }
-  const double q = mean_saturation(P, fld, F, N, 0, p, red);
+  const double q = mean_saturation<NT>(P, fld, F, N, 0, p, red);
   if (threadIdx.x == 0) {
     a.qoi[s] = status == RMG_SAMPLE_OK ? q : __longlong_as_double(0x7ff8000000000000ll);
     a.status[s] = status;
@@ -420,12 +421,12 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
     const int tot = TL * TL;
     const unsigned mg = rmg_magic(TL);
     constexpr int B = 4;
-    for (int k0 = threadIdx.x; k0 < tot; k0 += B * (int)blockDim.x) {
+    for (int k0 = threadIdx.x; k0 < tot; k0 += B * kBlock) {
       double pv[B], k0v[B], k1v[B], k2v[B];
       bool in[B];
 #pragma unroll
       for (int q = 0; q < B; ++q) {
-        const int k = k0 + q * (int)blockDim.x;
+        const int k = k0 + q * kBlock;
         const int lj = (int)__umulhi((unsigned)k, mg), li = k - lj * TL;
         const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
         in[q] = k < tot && gi >= 0 && gi < n && gj >= 0 && gj < n;
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
       }
 #pragma unroll
       for (int q = 0; q < B; ++q) {
-        const int k = k0 + q * (int)blockDim.x;
+        const int k = k0 + q * kBlock;
         if (k >= tot) continue;
         sp[k] = pv[q];
         sK[k] = in[q] ? closure(P, pv[q], k0v[q], k1v[q], k2v[q]).K : 0.0;
@@ -578,10 +579,10 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   for (int i = threadIdx.x; i < m; i += NT) T.cs[M2 + i] = CT[i];
   __syncthreads();
   for (int l = 0; l + 1 < nlev; ++l) {
-    lds_coarsen(lev[l], lev[l + 1]);
+    lds_coarsen<R, NT>(lev[l], lev[l + 1]);
     __syncthreads();
   }
-  lds_cycle(lev, 0, nlev, a.nu1, a.nu2, a.gamma, A, ipiv, u_zero != 0);
+  lds_cycle<R, NT>(lev, 0, nlev, a.nu1, a.nu2, a.gamma, A, ipiv, u_zero != 0);
   if (lt > 0 || !final_) {
     for (int v = threadIdx.x; v < nv; v += NT) {
       V o;
@@ -600,8 +601,8 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
     mx = fmax(mx, fabs(d));
     if (!isfinite(d)) bad = 1.0;
   }
-  mx = block_max(mx, red);
-  bad = block_max(bad, red);
+  mx = block_max<NT>(mx, red);
+  bad = block_max<NT>(bad, red);
   if (threadIdx.x == 0) {
     pl.dpmax[s] = (unsigned long long)__double_as_longlong(mx);
     if (bad > 0.0) pl.state[s].nanflag = 1;
@@ -613,10 +614,10 @@ __global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPla
   const int64_t s = blockIdx.x;
   const rmg_problem P = class_problem(a.cp, s);
   const int64_t N = (int64_t)a.n * a.n;
-  const double q = mean_saturation(P, a.fields, a.F, N, s, a.p + s * N, red);
+  const double q = mean_saturation<kBlock>(P, a.fields, a.F, N, s, a.p + s * N, red);
   if (a.p_hist && pl.state[s].status == RMG_SAMPLE_OK && P.n_steps % a.hist_every == 0) {
     double* hist = a.p_hist + (s * a.hist_slots + P.n_steps / a.hist_every) * N;
-    for (int64_t c = threadIdx.x; c < N; c += blockDim.x) hist[c] = a.p[s * N + c];
+    for (int64_t c = threadIdx.x; c < N; c += kBlock) hist[c] = a.p[s * N + c];
   }
   if (threadIdx.x == 0) {
     const SampleState st = pl.state[s];
