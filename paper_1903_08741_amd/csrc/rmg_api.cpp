@@ -23,6 +23,15 @@
 using namespace rmg;
 
 constexpr int kTimerPairs = 4096;
+// Share of the compute units (whole XCDs of 32) the whole-sample classes of a batched
+// MLMC call may use while level-streaming classes run beside them: a whole-sample
+// workgroup holds its compute unit for milliseconds, and a streaming kernel's
+// workgroups that land there wait; the streaming chains are the critical path.
+// Measured on the 5-level MLMC workload: all CUs 253 ms per call, 50 % 244 ms,
+// 25 % 239 ms.  0 disables the restriction.
+#ifndef RMG_WHOLE_CU_PCT
+#define RMG_WHOLE_CU_PCT 25
+#endif
 #ifndef RMG_WHOLE_MAX_N
 #define RMG_WHOLE_MAX_N 32
 #endif
@@ -46,6 +55,11 @@ struct rmg_ctx {
   // autotuner: tile edges (level 0, coarser streaming levels) per class signature
   std::map<std::string, std::pair<int, int>> tune;
   hipEvent_t tev[2] = {};
+  // set-up of each streaming class done (the whole-sample launches wait for them)
+  hipEvent_t iev[16] = {};
+  // whole-sample classes' stream restricted to part of the compute units (or null)
+  hipStream_t wstream = nullptr;
+  hipEvent_t wev = nullptr;
   std::string err;
 };
 
@@ -302,7 +316,11 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     }
   }
   // Streaming classes first: their set-up (and a first call's synchronous tile
-  // autotuning) must not wait behind, or be timed against, the whole-sample kernels.
+  // autotuning) must not wait behind, or be timed against, the whole-sample kernels;
+  // the whole-sample launches also wait until every streaming class's initialisation
+  // has run (a whole-sample launch occupies the compute units for milliseconds, and
+  // an initialisation dispatched beside it waited that long).
+  int ninit = 0;
   for (auto& j : jobs) {
     if (j.whole) continue;
     HIP_TRY(ctx, prepare_stream(j.a, j.pl));
@@ -311,9 +329,11 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
       const int rc = autotune_class(ctx, j);
       if (rc != RMG_OK) return rc;
     }
+    HIP_TRY(ctx, hipEventRecord(ctx->iev[ninit++], j.stream));
   }
   for (auto& j : jobs) {
     if (!j.whole) continue;
+    for (int q = 0; q < ninit; ++q) HIP_TRY(ctx, hipStreamWaitEvent(j.stream, ctx->iev[q], 0));
     HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
     j.done = true;
   }
@@ -515,6 +535,28 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device) {
         rmg_ctx_destroy(c);
         return RMG_EHIP;
       }
+  for (auto& e : c->iev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      rmg_ctx_destroy(c);
+      return RMG_EHIP;
+    }
+#if RMG_WHOLE_CU_PCT > 0
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess || cus < 32) {
+      rmg_ctx_destroy(c);
+      return RMG_EHIP;
+    }
+    const int keep = std::max(32, cus * RMG_WHOLE_CU_PCT / 100 / 32 * 32);
+    std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+    for (int k = 0; k < keep; ++k) mask[k / 32] |= 1u << (k % 32);
+    if (hipExtStreamCreateWithCUMask(&c->wstream, (uint32_t)mask.size(), mask.data()) != hipSuccess ||
+        hipEventCreateWithFlags(&c->wev, hipEventDisableTiming) != hipSuccess) {
+      rmg_ctx_destroy(c);
+      return RMG_EHIP;
+    }
+  }
+#endif
   for (auto& e : c->tev) {
     if (hipEventCreate(&e) != hipSuccess) {
       rmg_ctx_destroy(c);
@@ -596,6 +638,10 @@ void rmg_ctx_destroy(rmg_ctx* c) {
   for (auto& e : c->tev)
     if (e) (void)hipEventDestroy(e);
   if (c->d_tcells) (void)hipFree(c->d_tcells);
+  if (c->wstream) (void)hipStreamDestroy(c->wstream);
+  if (c->wev) (void)hipEventDestroy(c->wev);
+  for (auto& e : c->iev)
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& row : c->pev)
@@ -1004,9 +1050,11 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
   // kernel ends; the caller's stream is otherwise idle until the level sums.
   HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
   int nside = 0;
+  bool any_whole = false;
   for (size_t c = 0; c < jobs.size(); ++c) {
     if (jobs[c].whole) {
       jobs[c].stream = stream;
+      any_whole = true;
     } else {
       if (nside == 7) return fail(ctx, RMG_EINVAL, "more than seven level-streaming grid sizes");
       jobs[c].stream = ctx->side[nside++];
@@ -1014,10 +1062,22 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     jobs[c].h_count = ctx->h_count + 4 * (int)c;
   }
   for (int q = 0; q < nside; ++q) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[q], ctx->ev[0], 0));
+  // the whole-sample classes move to the restricted stream only when streaming
+  // classes run beside them (flag bit 7 keeps them on the caller's stream)
+  const bool wmasked = ctx->wstream && any_whole && nside > 0 && !(opts->flags & 128);
+  if (wmasked) {
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->wstream, ctx->ev[0], 0));
+    for (auto& j : jobs)
+      if (j.whole) j.stream = ctx->wstream;
+  }
   if ((rc = run_classes(ctx, jobs, !(opts->flags & 2)))) return rc;
   for (int q = 0; q < nside; ++q) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1 + q], ctx->side[q]));
     HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1 + q], 0));
+  }
+  if (wmasked) {
+    HIP_TRY(ctx, hipEventRecord(ctx->wev, ctx->wstream));
+    HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->wev, 0));
   }
   // level sums and optional per-sample QoIs
   int64_t qoff = 0;

@@ -329,12 +329,15 @@ hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st) {
 
 // ============================================================ level streaming
 __global__ void k_stream_init(SolveArgs a, StreamPlan pl) {
-  const int64_t N = (int64_t)a.n * a.n;
+  // n is a power of two: sample and cell of element e by shifts (no 64-bit division)
+  const int lg = a.lg;
+  const int64_t N = (int64_t)1 << (2 * lg);
   const int64_t tot = a.S * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = e / N;
-    a.p[e] = a.p0 ? a.p0[s * a.p0_stride + (e - s * N)] : initial_head(class_problem(a.cp, s), (int)((e - s * N) / a.n), a.n);
+    const int64_t s = e >> (2 * lg);
+    const int c = (int)(e & (N - 1));
+    a.p[e] = a.p0 ? a.p0[s * a.p0_stride + c] : initial_head(class_problem(a.cp, s), c >> lg, a.n);
   }
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < a.S;
        s += (int64_t)gridDim.x * blockDim.x) {
