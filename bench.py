@@ -148,9 +148,9 @@ def per_grid(torch, rmg, ctx, levels, opts, marg):
     return res
 
 
-def fp64_path(torch, rmg, ctx, levels, marg, max_picard, cycles, steps=2):
+def fp64_path(torch, rmg, ctx, levels, marg, max_picard, cycles, flags=0, steps=2):
     """The same workload with the multigrid in FP64 too (1 untimed call, `steps` timed)."""
-    opts = rmg.SolverOpts(precision=rmg.FP64, max_picard=max_picard, cycles_per_picard=cycles)
+    opts = rmg.SolverOpts(precision=rmg.FP64, max_picard=max_picard, cycles_per_picard=cycles, flags=flags)
     ctx.mlmc_level_estimate(levels, marg, opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -598,6 +598,9 @@ def main():
     ap.add_argument("--max-picard", type=int, default=500)
     ap.add_argument("--cycles", type=int, default=1, help="V(2,2) cycles per Picard iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--confine", choices=("default", "on", "off"), default="default",
+                    help="confine the classes of the batched call to parts of the compute units (flag bit 7); "
+                         "default: on for the gardner workload, off for vg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="32 x 32 streaming tiles on every level (profiling runs: timing under a counter "
                          "profiler is distorted, so an autotuner could pick other tiles there)")
@@ -630,6 +633,12 @@ def main():
     opts.cycles_per_picard = args.cycles
     if args.no_autotune:
         opts.flags |= rmg.FLAG_NO_AUTOTUNE
+    # confine the whole-sample and the smaller streaming classes to parts of the GPU so
+    # that the largest grid's chain finds free compute units: measured to help on the
+    # Gardner workload (its 256^2 chain is the critical path), not on the vg workload
+    confine = args.confine == "on" or (args.confine == "default" and not vg)
+    if confine:
+        opts.flags |= rmg.FLAG_CONFINE
     ctx = rmg.default_context(0)
     total = n_solves(levels)
     sums = None
@@ -668,7 +677,8 @@ def main():
     if not args.no_extras and not vg:
         extras["per_grid"] = per_grid(torch, rmg, ctx, levels, opts, marg)
         if precision == rmg.MIXED:
-            fms, ffail = fp64_path(torch, rmg, ctx, levels, marg, args.max_picard, args.cycles)
+            fms, ffail = fp64_path(torch, rmg, ctx, levels, marg, args.max_picard, args.cycles,
+                                     opts.flags & rmg.FLAG_CONFINE)
             extras["fp64_path"] = {"ms_per_step": fms, "failed_pairs": ffail, "mixed_speedup": fms / ms}
         extras["roofline_large_batch"] = large_batch_roofline(torch, rmg, ctx, W, levels, marg)
     cpu = None
@@ -700,7 +710,7 @@ def main():
                                          for lv in levels),
                    "failed_pairs": failed,
                    "picard_iterations_per_step": picard, "precision": args.precision,
-                   "cycles_per_picard": args.cycles, "max_picard": args.max_picard},
+                   "cycles_per_picard": args.cycles, "max_picard": args.max_picard, "confined": confine},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -117,9 +117,11 @@ typedef struct {
                                  LDS (64 x 64 in FP32), not only up to 32 x 32;
                                  bit 6: start the one-workgroup coarse V-cycle at 32 x 32 in FP32
                                  too (more level-streaming levels; results are identical);
-                                 bit 7: mlmc_level_estimate: let the whole-sample classes use every
-                                 compute unit even while level-streaming classes run (by default they
-                                 are confined to a quarter of them then; results are identical) */
+                                 bit 7: mlmc_level_estimate: while level-streaming classes run, confine
+                                 the whole-sample classes to a quarter of the compute units and the
+                                 streaming classes other than the largest grid to three quarters, so
+                                 that the largest grid's chain of short launches finds free units
+                                 (helps when that chain is the critical path; results are identical) */
   double eps_mg;              /* residual tolerance of cycles_per_picard = 0 (Section 4.2: 1e-5) */
   double eps_picard;          /* stop when ||dp||_inf < eps_picard (strict) */
 } rmg_solver_opts;

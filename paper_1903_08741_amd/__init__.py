@@ -19,7 +19,7 @@ import ctypes as C
 from dataclasses import dataclass, field, fields as dc_fields
 
 from . import _abi
-from ._abi import (COST_TIME, COST_WORK, CYCLE_V, CYCLE_W, FLAG_COARSE_TOP_32, FLAG_WHOLE_ALL_CUS, FLAG_EAGER, FLAG_FORCE_STREAMING, FLAG_NO_AUTOTUNE,  # noqa: F401
+from ._abi import (COST_TIME, COST_WORK, CYCLE_V, CYCLE_W, FLAG_COARSE_TOP_32, FLAG_CONFINE, FLAG_EAGER, FLAG_FORCE_STREAMING, FLAG_NO_AUTOTUNE,  # noqa: F401
                    FLAG_STATE_GLOBAL, FLAG_TILES_16, FLAG_WHOLE_WHERE_FITS, FP64, GARDNER, LINEAR, MIXED,
                    QOI_MEAN_SATURATION, RMG_ENOTCONV, RMG_OK, SAMPLE_MAXITER, SAMPLE_NONFINITE,
                    SAMPLE_OK, VGM)

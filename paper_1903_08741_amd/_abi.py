@@ -24,7 +24,7 @@ FLAG_NO_AUTOTUNE = 8
 FLAG_TILES_16 = 16
 FLAG_WHOLE_WHERE_FITS = 32
 FLAG_COARSE_TOP_32 = 64
-FLAG_WHOLE_ALL_CUS = 128
+FLAG_CONFINE = 128
 
 COST_WORK, COST_TIME = 0, 1
 

@@ -27,10 +27,18 @@ constexpr int kTimerPairs = 4096;
 // MLMC call may use while level-streaming classes run beside them: a whole-sample
 // workgroup holds its compute unit for milliseconds, and a streaming kernel's
 // workgroups that land there wait; the streaming chains are the critical path.
-// Measured on the 5-level MLMC workload: all CUs 253 ms per call, 50 % 244 ms,
-// 25 % 239 ms.  0 disables the restriction.
+// Measured on the 5-level Gardner MLMC workload: all CUs 253 ms per call, 50 % 244 ms,
+// 25 % 239 ms; on the van Genuchten workload the heavy 32^2 whole-sample class then
+// becomes the critical path (1776 ms against ~1500), so the restriction is requested
+// per call (flag bit 7).  0 compiles it out.
 #ifndef RMG_WHOLE_CU_PCT
 #define RMG_WHOLE_CU_PCT 25
+#endif
+// Share of the compute units the other level-streaming classes of such a call may
+// use, leaving the rest to the largest grid's chain (the critical path): 239 ms per
+// call with every class on every CU, 232 ms at 75 %, 230 ms at 63 %, 258 ms at 50 %.
+#ifndef RMG_OTHER_CU_PCT
+#define RMG_OTHER_CU_PCT 75
 #endif
 #ifndef RMG_WHOLE_MAX_N
 #define RMG_WHOLE_MAX_N 32
@@ -60,6 +68,8 @@ struct rmg_ctx {
   // whole-sample classes' stream restricted to part of the compute units (or null)
   hipStream_t wstream = nullptr;
   hipEvent_t wev = nullptr;
+  // streams for the streaming classes other than the largest grid, restricted too (or null)
+  hipStream_t mside[7] = {};
   std::string err;
 };
 
@@ -555,6 +565,16 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device) {
       rmg_ctx_destroy(c);
       return RMG_EHIP;
     }
+#if RMG_OTHER_CU_PCT > 0
+    const int keep2 = std::max(32, cus * RMG_OTHER_CU_PCT / 100 / 32 * 32);
+    std::vector<uint32_t> mask2((cus + 31) / 32, 0u);
+    for (int k = 0; k < keep2; ++k) mask2[k / 32] |= 1u << (k % 32);
+    for (auto& ms : c->mside)
+      if (hipExtStreamCreateWithCUMask(&ms, (uint32_t)mask2.size(), mask2.data()) != hipSuccess) {
+        rmg_ctx_destroy(c);
+        return RMG_EHIP;
+      }
+#endif
   }
 #endif
   for (auto& e : c->tev) {
@@ -638,6 +658,8 @@ void rmg_ctx_destroy(rmg_ctx* c) {
   for (auto& e : c->tev)
     if (e) (void)hipEventDestroy(e);
   if (c->d_tcells) (void)hipFree(c->d_tcells);
+  for (auto& ms : c->mside)
+    if (ms) (void)hipStreamDestroy(ms);
   if (c->wstream) (void)hipStreamDestroy(c->wstream);
   if (c->wev) (void)hipEventDestroy(c->wev);
   for (auto& e : c->iev)
@@ -1062,17 +1084,30 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     jobs[c].h_count = ctx->h_count + 4 * (int)c;
   }
   for (int q = 0; q < nside; ++q) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[q], ctx->ev[0], 0));
-  // the whole-sample classes move to the restricted stream only when streaming
-  // classes run beside them (flag bit 7 keeps them on the caller's stream)
-  const bool wmasked = ctx->wstream && any_whole && nside > 0 && !(opts->flags & 128);
+  // flag bit 7: the whole-sample classes move to the restricted stream when streaming
+  // classes run beside them (whether that helps depends on which class is critical)
+  const bool wmasked = ctx->wstream && any_whole && nside > 0 && (opts->flags & 128);
+  std::vector<hipStream_t> sused(ctx->side, ctx->side + nside);
   if (wmasked) {
     HIP_TRY(ctx, hipStreamWaitEvent(ctx->wstream, ctx->ev[0], 0));
     for (auto& j : jobs)
       if (j.whole) j.stream = ctx->wstream;
+    // the largest grid's chain is the critical path: the other streaming classes move
+    // to restricted streams, so that some compute units only ever see the largest grid
+    if (ctx->mside[0] && nside > 1) {
+      int k = 0;
+      for (auto& j : jobs)
+        if (!j.whole && k < nside - 1) {
+          HIP_TRY(ctx, hipStreamWaitEvent(ctx->mside[k], ctx->ev[0], 0));
+          j.stream = ctx->mside[k];
+          sused[k] = ctx->mside[k];
+          ++k;
+        }
+    }
   }
   if ((rc = run_classes(ctx, jobs, !(opts->flags & 2)))) return rc;
   for (int q = 0; q < nside; ++q) {
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[1 + q], ctx->side[q]));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1 + q], sused[q]));
     HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1 + q], 0));
   }
   if (wmasked) {
