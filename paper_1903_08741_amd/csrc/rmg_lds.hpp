@@ -65,6 +65,28 @@ __device__ R* lds_carve(R* base, LdsLevel<R>* lev, int m_top, int nlev) {
   return p;
 }
 
+// Zero the elements of a hierarchy carved by lds_carve that no routine writes: the
+// zero rows and guards around each level's u and the trailing guard of its cw.
+// Every other element (cells of u, f, cw, cs including the top weights, cdt) is
+// written before it is read: loaded or computed on the top level, produced by
+// lds_coarsen and lds_residual_restrict below it.
+template <class R, int NT>
+__device__ void lds_zero_padding(R* base, int m_top, int nlev) {
+  R* p = base;
+  int m = m_top;
+  for (int l = 0; l < nlev; ++l) {
+    const int span = (m + 2) * m + 2;  // u with its rows and guards
+    for (int k = threadIdx.x; k <= m; k += NT) {
+      p[k] = (R)0;
+      p[span - 1 - k] = (R)0;
+    }
+    p += span + m * m;  // past u and f: p is cw
+    if (threadIdx.x == 0) p[m * m] = (R)0;
+    p += (m * m + 1) + (m + 1) * m + m * m;
+    m >>= 1;
+  }
+}
+
 template <class R>
 __device__ __forceinline__ St5<R> lds_st5(const LdsLevel<R>& L, int c) {
   const int m = L.m;
@@ -179,52 +201,72 @@ __device__ void lds_coarsen(const LdsLevel<R>& F, const LdsLevel<R>& C) {
     C.cs[mc * mc + I] = coarse_face<R>(F.cs[m * m + 2 * I], F.cs[m * m + 2 * I + 1]);
 }
 
-// Exact solve on the coarsest level in FP64: Gauss-Jordan elimination without
-// pivoting on the symmetric positive definite matrix, one barrier per pivot.
-// Step k replaces every row i != k by row_i - (a_ik / a_kk) row_k on the
-// columns j > k (column k is then logically zero and never read again); the
-// reciprocal of the next pivot, final once step k is done, is formed by the
-// thread that writes it.  `A` is LDS scratch of N*(N+1) doubles and `ipiv` of N
-// doubles, N = m*m <= 16.
-template <class R, int NT>
-__device__ void lds_coarsest_solve(const LdsLevel<R>& L, RMG_LDS double* A, RMG_LDS double* ipiv) {
-  const int m = L.m, N = m * m, W = N + 1, lgN = 2 * L.lg;
-  for (int e = threadIdx.x; e < N * W; e += NT) A[e] = 0.0;
-  __syncthreads();
-  for (int c = threadIdx.x; c < N; c += NT) {
-    const int j = c >> L.lg, i = c - (j << L.lg);
-    const double aw = (double)L.cw[c], ae = (double)L.cw[c + 1];
-    const double as = (double)L.cs[c], an = (double)L.cs[c + m];
-    const St5<double> s = st5<double>((double)L.cdt[c], aw, ae, as, an, 0.0, 0.0, 0.0, 0.0);
-    RMG_LDS double* row = A + c * W;
-    row[c] = s.d;
-    if (i > 0) row[c - 1] = -aw;
-    if (i < m - 1) row[c + 1] = -ae;
-    if (j > 0) row[c - m] = -as;
-    if (j < m - 1) row[c + m] = -an;
-    row[N] = (double)L.f[c];
-    if (c == 0) ipiv[0] = 1.0 / s.d;
+// Value of v in lane `lane` of the wavefront, for every lane (two readlanes).
+__device__ __forceinline__ double wave_read(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Exact solve on the coarsest level (N = m*m = 4 or 16 unknowns) in FP64:
+// Gauss-Jordan elimination without pivoting on the symmetric positive definite
+// matrix, in the registers of the first wavefront.  Lane c holds row c of the
+// matrix (columns 0..N-1) and its right-hand side; step k reads the pivot row from
+// lane k (a wave-uniform value, so no LDS round trip and no barrier) and replaces
+// every row c != k by row_c - (a_ck / a_kk) row_k on the columns j > k (column k
+// is then logically zero and never read again).  The unknown is the row's
+// right-hand side times the reciprocal of its pivot.  Lanes N..63 duplicate rows.
+// Kept out of line: inlined, its unrolled rows and scalar pivot-row reads raised
+// the register pressure of the calling kernels, whose sweep loops then reloaded
+// spilled scalar registers (every level and class ran slower).
+template <class R, int N>
+__device__ __attribute__((noinline)) void coarsest_gauss_jordan(const LdsLevel<R>& L) {
+  constexpr int m = N == 16 ? 4 : 2, lg = N == 16 ? 2 : 1;
+  const int c = (int)(threadIdx.x & (N - 1));
+  const int j = c >> lg, i = c - (j << lg);
+  const double aw = (double)L.cw[c], ae = (double)L.cw[c + 1];
+  const double as = (double)L.cs[c], an = (double)L.cs[c + m];
+  const St5<double> s = st5<double>((double)L.cdt[c], aw, ae, as, an, 0.0, 0.0, 0.0, 0.0);
+  double a[N];
+#pragma unroll
+  for (int col = 0; col < N; ++col) {
+    double v = 0.0;
+    if (col == c) v = s.d;
+    if (i > 0 && col == c - 1) v = -aw;
+    if (i < m - 1 && col == c + 1) v = -ae;
+    if (j > 0 && col == c - m) v = -as;
+    if (j < m - 1 && col == c + m) v = -an;
+    a[col] = v;
   }
-  __syncthreads();
+  double b = (double)L.f[c], rpiv = 0.0;
+#pragma unroll
   for (int k = 0; k < N; ++k) {
-    const double pk = ipiv[k];
-    for (int e = threadIdx.x; e < N * N + N; e += NT) {
-      int i, j;
-      if (e < N * N) {
-        i = e >> lgN;
-        j = e & (N - 1);
-      } else {
-        i = e - N * N;
-        j = N;
-      }
-      if (i == k || j <= k) continue;
-      const double v = A[i * W + j] - (A[i * W + k] * pk) * A[k * W + j];
-      A[i * W + j] = v;
-      if (i == k + 1 && j == k + 1) ipiv[k + 1] = 1.0 / v;
+    // lane k's row is not modified in step k, so each pivot-row entry can be read
+    // just before the column it updates
+    const double pk = 1.0 / wave_read(a[k], k);
+    rpiv = c == k ? pk : rpiv;
+    const double mk = c != k ? a[k] * pk : 0.0;
+#pragma unroll
+    for (int col = k + 1; col < N; ++col) {
+      const double akj = wave_read(a[col], k);
+      if (c != k) a[col] = a[col] - mk * akj;
     }
-    __syncthreads();
+    const double bk = wave_read(b, k);
+    if (c != k) b = b - mk * bk;
   }
-  for (int c = threadIdx.x; c < N; c += NT) L.u[c] = (R)(A[c * W + N] * ipiv[c]);
+  if ((int)threadIdx.x < N) L.u[c] = (R)(b * rpiv);
+}
+
+template <class R, int NT>
+__device__ void lds_coarsest_solve(const LdsLevel<R>& L) {
+  static_assert(NT >= 64, "the coarsest solve runs on the first wavefront");
+  if (threadIdx.x < 64) {
+    if (L.m == 4)
+      coarsest_gauss_jordan<R, 16>(L);
+    else
+      coarsest_gauss_jordan<R, 4>(L);
+  }
   __syncthreads();
 }
 
@@ -261,7 +303,7 @@ __device__ void lds_up_leg(const LdsLevel<R>* lev, int l, int nu2) {
 // iterate.  `top_zero`: the iterate on level `top` is zero on entry.
 template <class R, int NT>
 __device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, int gamma,
-                          RMG_LDS double* A, RMG_LDS double* ipiv, bool top_zero) {
+                          bool top_zero) {
   int l = top;
   bool zero = top_zero;
   unsigned again = 0;  // bit l: level l owes one more coarse cycle (W-cycle)
@@ -273,7 +315,7 @@ __device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, in
       if (gamma == 2) again |= 1u << l;
       zero = true;
     }
-    lds_coarsest_solve<R, NT>(lev[nlev - 1], A, ipiv);
+    lds_coarsest_solve<R, NT>(lev[nlev - 1]);
     bool descend = false;
     while (l > top) {
       --l;

@@ -50,8 +50,8 @@ __device__ double mean_saturation(const rmg_problem& P, const double* fields, in
 }
 
 // ============================================================ whole sample
-// LDS doubles ahead of the level arrays: coarsest matrix N(N+1), pivots, reduction lanes.
-__host__ __device__ constexpr int whole_doubles(int NC) { return NC * (NC + 1) + 16 + kQoiLanes; }
+// LDS doubles ahead of the level arrays: reduction lanes.
+__host__ __device__ constexpr int whole_doubles() { return kQoiLanes; }
 
 #ifndef RMG_WS_UNROLL
 #define RMG_WS_UNROLL 1
@@ -72,12 +72,9 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   const rmg_problem P = class_problem(a.cp, s);
   const int n = a.n, lg = a.lg, F = a.F;
   const int N = n * n;
-  const int mc = n >> (a.nlev - 1), NC = mc * mc;
 
   RMG_LDS double* Kc = (RMG_LDS double*)smem;
-  RMG_LDS double* A = Kc + N;
-  RMG_LDS double* ipiv = A + NC * (NC + 1);
-  double* red = (double*)(ipiv + 16);
+  double* red = (double*)(Kc + N);
   double* dend = red + kQoiLanes;
   double* pS = dend;
   double* thS = pS + (SL ? N : 0);
@@ -178,7 +175,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     // residual max_c |f - A dp| (level 0, smoother precision) is below eps_mg
     int ncyc = 0;
     for (;;) {
-      lds_cycle<R, NT>(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, A, ipiv, ncyc == 0);
+      lds_cycle<R, NT>(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, ncyc == 0);
       ++ncyc;
       if (a.cpp > 0) {
         if (ncyc == a.cpp) break;
@@ -266,8 +263,8 @@ static size_t ws_bytes(int n, int nc, bool fp64, int F, bool state) {
   const int nlev = ilog2(n) - ilog2(nc) + 1;
   size_t relems = 0;
   for (int l = 0, m = n; l < nlev; ++l, m >>= 1) relems += lds_level_elems(m);
-  const size_t NC = (size_t)nc * nc, N = (size_t)n * n;
-  return 8 * (N + whole_doubles((int)NC) + (state ? (2 + F) * N : 0)) + relems * (fp64 ? 8 : 4);
+  const size_t N = (size_t)n * n;
+  return 8 * (N + whole_doubles() + (state ? (2 + F) * N : 0)) + relems * (fp64 ? 8 : 4);
 }
 
 size_t whole_sample_lds_bytes(int n, int nc, bool fp64, int F, bool* state_in_lds) {
@@ -525,15 +522,12 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   const int lt = pl.ltop;
   const int m = a.n >> lt;
   const int nlev = a.nlev - lt;
-  const int mc = a.n >> (a.nlev - 1), NC = mc * mc;
   const int M2 = m * m;
-  RMG_LDS double* A = (RMG_LDS double*)smem;
-  RMG_LDS double* ipiv = A + NC * (NC + 1);
-  double* red = (double*)(ipiv + 16);
+  double* red = (double*)smem;
   R* rbase = (R*)(red + NT / 64 + 1);
   __shared__ LdsLevel<R> lev[kMaxLevels];
-  R* rend = lds_carve(rbase, lev, m, nlev);
-  for (R* q = rbase + threadIdx.x; q < rend; q += NT) *q = (R)0;
+  lds_carve(rbase, lev, m, nlev);
+  lds_zero_padding<R, NT>(rbase, m, nlev);
   __syncthreads();
   const LdsLevel<R>& T = lev[0];
   using V = typename Vec16<R>::T;
@@ -585,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
     lds_coarsen<R, NT>(lev[l], lev[l + 1]);
     __syncthreads();
   }
-  lds_cycle<R, NT>(lev, 0, nlev, a.nu1, a.nu2, a.gamma, A, ipiv, u_zero != 0);
+  lds_cycle<R, NT>(lev, 0, nlev, a.nu1, a.nu2, a.gamma, u_zero != 0);
   if (lt > 0 || !final_) {
     for (int v = threadIdx.x; v < nv; v += NT) {
       V o;
@@ -654,8 +648,7 @@ hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStrea
 static size_t coarse_lds(int m, int nc, bool fp64) {
   size_t relems = 0;
   for (int mm = m; mm >= nc; mm >>= 1) relems += lds_level_elems(mm);
-  const size_t NC = (size_t)nc * nc;
-  return 8 * (NC * (NC + 1) + 16 + kCoarseThreads / 64 + 1) + relems * (fp64 ? 8 : 4);
+  return 8 * (kCoarseThreads / 64 + 1) + relems * (fp64 ? 8 : 4);
 }
 
 // Down and up kernels by tile edge and blocks per thread (nu <= 4: at most 3 blocks).
