@@ -332,4 +332,164 @@ __device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Top level of the coarse kernel with its coefficients in registers.  Within one
+// cycle the coefficients of a level do not change, so each thread keeps, for the
+// CPT cells of each colour it updates (the cells the loop of lds_half_sweep gives
+// it), the diagonal, the four face coefficients and the right-hand side in
+// registers: a half-sweep then reads only the four neighbour values from LDS
+// (instead of ten values per cell), all of a thread's loads issued before its
+// stores.  The arithmetic is that of st5 / gs_value in the same order, so the
+// results are bit-identical to lds_cycle's.
+
+template <class R, int CPT>
+struct SweepCache {
+  R d[2][CPT], aw[2][CPT], ae[2][CPT], as[2][CPT], an[2][CPT], f[2][CPT];
+};
+
+// Cell (i, j) of the r-th cell of `colour` of this thread on an M x M level.
+template <int NT, int M>
+__device__ __forceinline__ int sweep_cell(int colour, int r, int& i, int& j) {
+  constexpr int hlg = (M == 64 ? 6 : M == 32 ? 5 : M == 16 ? 4 : 3) - 1;
+  static_assert((1 << (hlg + 1)) == M, "unsupported level size");
+  const int k = (int)threadIdx.x + r * NT;
+  j = k >> hlg;
+  const int q = k - (j << hlg);
+  i = 2 * q + ((j + colour) & 1);
+  return j * M + i;
+}
+
+template <class R>
+__device__ __forceinline__ R cached_gs(R d, R aw, R ae, R as, R an, R f, R uw, R ue, R us, R un) {
+  R t1 = aw * uw;
+  t1 = t1 + ae * ue;
+  R t2 = as * us;
+  t2 = t2 + an * un;
+  St5<R> s;
+  s.d = d;
+  s.snb = t1 + t2;
+  return gs_value<R>(f, s);
+}
+
+template <class R, int NT, int M, int CPT>
+__device__ __forceinline__ void sweep_cache_load(SweepCache<R, CPT>& K, const LdsLevel<R>& L) {
+#pragma unroll
+  for (int colour = 0; colour < 2; ++colour)
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      int i, j;
+      const int c = sweep_cell<NT, M>(colour, r, i, j);
+      const R aw = L.cw[c], ae = L.cw[c + 1], as = L.cs[c], an = L.cs[c + M];
+      R d = L.cdt[c];
+      d = d + aw;
+      d = d + ae;
+      d = d + as;
+      d = d + an;
+      K.d[colour][r] = d;
+      K.aw[colour][r] = aw;
+      K.ae[colour][r] = ae;
+      K.as[colour][r] = as;
+      K.an[colour][r] = an;
+      K.f[colour][r] = L.f[c];
+    }
+}
+
+// One colour of a sweep from the cache.  MODE 0: neighbours from u; 1: the iterate
+// is zero (lds_half_sweep_from_zero); 2: neighbours are u plus the prolongated
+// coarse correction of C (lds_half_sweep_prolong).
+template <class R, int NT, int M, int CPT, int MODE>
+__device__ __forceinline__ void cached_half_sweep(const SweepCache<R, CPT>& K, const LdsLevel<R>& L,
+                                                  const LdsLevel<R>& C, int colour) {
+  R uw[CPT], ue[CPT], us[CPT], un[CPT];
+  int cc[CPT];
+#pragma unroll
+  for (int r = 0; r < CPT; ++r) {
+    int i, j;
+    const int c = sweep_cell<NT, M>(colour, r, i, j);
+    cc[r] = c;
+    if (MODE == 1) {
+      uw[r] = ue[r] = us[r] = un[r] = (R)0;
+    } else if (MODE == 0) {
+      uw[r] = L.u[c - 1];
+      ue[r] = L.u[c + 1];
+      us[r] = L.u[c - M];
+      un[r] = L.u[c + M];
+    } else {
+      constexpr int mc = M / 2;
+      uw[r] = i > 0 ? L.u[c - 1] + C.u[(j >> 1) * mc + ((i - 1) >> 1)] : (R)0;
+      ue[r] = i < M - 1 ? L.u[c + 1] + C.u[(j >> 1) * mc + ((i + 1) >> 1)] : (R)0;
+      us[r] = j > 0 ? L.u[c - M] + C.u[((j - 1) >> 1) * mc + (i >> 1)] : (R)0;
+      un[r] = j < M - 1 ? L.u[c + M] + C.u[((j + 1) >> 1) * mc + (i >> 1)] : (R)0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < CPT; ++r)
+    L.u[cc[r]] = cached_gs<R>(K.d[colour][r], K.aw[colour][r], K.ae[colour][r], K.as[colour][r],
+                              K.an[colour][r], K.f[colour][r], uw[r], ue[r], us[r], un[r]);
+}
+
+// lds_cycle from level 0 with the top level's sweeps from registers (M x M top
+// level, M*M = 2*CPT*NT): pre-smoothing, restriction, gamma cycles of level 1 (the
+// first from a zero iterate), post-smoothing with the prolongation fused into its
+// first red half-sweep -- the same sequence of operations as lds_cycle(lev, 0, ...).
+template <class R, int NT, int M>
+__device__ void lds_cycle_top_cached(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma,
+                                     bool top_zero) {
+  constexpr int CPT = M * M / (2 * NT);
+  static_assert(CPT >= 1 && 2 * CPT * NT == M * M, "every cell of the top level needs one owner");
+  const LdsLevel<R>& L = lev[0];
+  {
+    SweepCache<R, CPT> K;
+    sweep_cache_load<R, NT, M, CPT>(K, L);
+    for (int s = 0; s < nu1; ++s) {
+      if (s == 0 && RMG_ZERO_SWEEP && top_zero)
+        cached_half_sweep<R, NT, M, CPT, 1>(K, L, L, 0);
+      else
+        cached_half_sweep<R, NT, M, CPT, 0>(K, L, L, 0);
+      __syncthreads();
+      cached_half_sweep<R, NT, M, CPT, 0>(K, L, L, 1);
+      __syncthreads();
+    }
+  }
+  lds_residual_restrict<R, NT>(lev[0], lev[1]);
+  __syncthreads();
+  for (int g = 0; g < gamma; ++g) lds_cycle<R, NT>(lev, 1, nlev, nu1, nu2, gamma, g == 0);
+  if (RMG_FUSED_PROLONG && nu2 > 0) {
+    SweepCache<R, CPT> K;
+    sweep_cache_load<R, NT, M, CPT>(K, L);
+    cached_half_sweep<R, NT, M, CPT, 2>(K, L, lev[1], 0);
+    __syncthreads();
+    cached_half_sweep<R, NT, M, CPT, 0>(K, L, L, 1);
+    __syncthreads();
+    for (int s = 1; s < nu2; ++s) {
+      cached_half_sweep<R, NT, M, CPT, 0>(K, L, L, 0);
+      __syncthreads();
+      cached_half_sweep<R, NT, M, CPT, 0>(K, L, L, 1);
+      __syncthreads();
+    }
+  } else {
+    lds_up_leg<R, NT>(lev, 0, nu2);
+  }
+}
+
+// One cycle from the top level of the coarse kernel: register-cached top-level
+// sweeps where the level size has a specialisation, lds_cycle otherwise.
+template <class R, int NT>
+__device__ void lds_cycle_coarse(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma, bool top_zero) {
+  const int m = lev[0].m;
+  if constexpr (sizeof(R) == 4 && 64 * 64 == 8 * NT) {
+    if (nlev >= 2 && m == 64) {
+      lds_cycle_top_cached<R, NT, 64>(lev, nlev, nu1, nu2, gamma, top_zero);
+      return;
+    }
+  }
+  if constexpr (32 * 32 == 2 * NT) {
+    if (nlev >= 2 && m == 32) {
+      lds_cycle_top_cached<R, NT, 32>(lev, nlev, nu1, nu2, gamma, top_zero);
+      return;
+    }
+  }
+  lds_cycle<R, NT>(lev, 0, nlev, nu1, nu2, gamma, top_zero);
+}
+
 }  // namespace rmg

@@ -579,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
     lds_coarsen<R, NT>(lev[l], lev[l + 1]);
     __syncthreads();
   }
-  lds_cycle<R, NT>(lev, 0, nlev, a.nu1, a.nu2, a.gamma, u_zero != 0);
+  lds_cycle_coarse<R, NT>(lev, nlev, a.nu1, a.nu2, a.gamma, u_zero != 0);
   if (lt > 0 || !final_) {
     for (int v = threadIdx.x; v < nv; v += NT) {
       V o;
