@@ -69,7 +69,7 @@ __device__ R* lds_carve(R* base, LdsLevel<R>* lev, int m_top, int nlev) {
 // zero rows and guards around each level's u and the trailing guard of its cw.
 // Every other element (cells of u, f, cw, cs including the top weights, cdt) is
 // written before it is read: loaded or computed on the top level, produced by
-// lds_coarsen and lds_residual_restrict below it.
+// lds_residual_restrict (right-hand side, zero iterate, coefficients) below it.
 template <class R, int NT>
 __device__ void lds_zero_padding(R* base, int m_top, int nlev) {
   R* p = base;
@@ -160,8 +160,11 @@ __device__ void lds_sweeps(const LdsLevel<R>& L, int nu, bool from_zero = false)
   }
 }
 
-// Coarse right-hand side = R (f - A u); coarse initial iterate 0.
-template <class R, int NT>
+// Coarse right-hand side = R (f - A u); coarse initial iterate 0.  COARSEN: also
+// the coefficients of C in the same pass over the coarse cells (Section 4.2: each
+// coarse face the arithmetic mean of the two fine faces it covers, C/dt the mean of
+// the four fine cells, the top Dirichlet weights likewise).
+template <class R, int NT, bool COARSEN = false>
 __device__ void lds_residual_restrict(const LdsLevel<R>& F, const LdsLevel<R>& C) {
   const int mc = C.m, m = F.m;
   for (int kc = threadIdx.x; kc < mc * mc; kc += NT) {
@@ -173,7 +176,15 @@ __device__ void lds_residual_restrict(const LdsLevel<R>& F, const LdsLevel<R>& C
     const R r11 = residual_value<R>(F.f[c00 + m + 1], F.u[c00 + m + 1], lds_st5(F, c00 + m + 1));
     C.f[kc] = restrict4<R>(r00, r01, r10, r11);
     C.u[kc] = (R)0;
+    if (COARSEN) {
+      C.cw[kc] = coarse_face<R>(F.cw[c00], F.cw[c00 + m]);
+      C.cs[kc] = coarse_face<R>(F.cs[c00], F.cs[c00 + 1]);
+      C.cdt[kc] = coarse_cdt<R>(F.cdt[c00], F.cdt[c00 + 1], F.cdt[c00 + m], F.cdt[c00 + m + 1]);
+    }
   }
+  if (COARSEN)
+    for (int I = threadIdx.x; I < mc; I += NT)
+      C.cs[mc * mc + I] = coarse_face<R>(F.cs[m * m + 2 * I], F.cs[m * m + 2 * I + 1]);
 }
 
 // Piecewise-constant prolongation of the coarse correction (eq. transfer).
@@ -184,21 +195,6 @@ __device__ void lds_prolong_add(const LdsLevel<R>& F, const LdsLevel<R>& C) {
     const int j = c >> F.lg, i = c - (j << F.lg);
     F.u[c] = F.u[c] + C.u[(j >> 1) * C.m + (i >> 1)];
   }
-}
-
-// Coefficients of the next coarser level.
-template <class R, int NT>
-__device__ void lds_coarsen(const LdsLevel<R>& F, const LdsLevel<R>& C) {
-  const int mc = C.m, m = F.m;
-  for (int kc = threadIdx.x; kc < mc * mc; kc += NT) {
-    const int J = kc >> C.lg, I = kc - (J << C.lg);
-    const int c00 = (2 * J) * m + 2 * I;
-    C.cw[kc] = coarse_face<R>(F.cw[c00], F.cw[c00 + m]);
-    C.cs[kc] = coarse_face<R>(F.cs[c00], F.cs[c00 + 1]);
-    C.cdt[kc] = coarse_cdt<R>(F.cdt[c00], F.cdt[c00 + 1], F.cdt[c00 + m], F.cdt[c00 + m + 1]);
-  }
-  for (int I = threadIdx.x; I < mc; I += NT)
-    C.cs[mc * mc + I] = coarse_face<R>(F.cs[m * m + 2 * I], F.cs[m * m + 2 * I + 1]);
 }
 
 // Value of v in lane `lane` of the wavefront, for every lane (two readlanes).
@@ -300,21 +296,27 @@ __device__ void lds_up_leg(const LdsLevel<R>* lev, int l, int nu2) {
 // ascend with prolongation and post-smoothing; a W-cycle descends once more from
 // every level before ascending past it.  A level's first visit starts from a zero
 // iterate (its restriction set it to zero), a second visit from the current
-// iterate.  `top_zero`: the iterate on level `top` is zero on entry.
+// iterate.  `top_zero`: the iterate on level `top` is zero on entry.  `coarsen`:
+// the coefficients of the levels below `top` are formed on the first descent, each
+// in the restriction pass that enters its level (before the level is first used).
 template <class R, int NT>
 __device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, int gamma,
-                          bool top_zero) {
+                          bool top_zero, bool coarsen = false) {
   int l = top;
   bool zero = top_zero;
   unsigned again = 0;  // bit l: level l owes one more coarse cycle (W-cycle)
   for (;;) {
     for (; l < nlev - 1; ++l) {
       lds_sweeps<R, NT>(lev[l], nu1, RMG_ZERO_SWEEP && zero);
-      lds_residual_restrict<R, NT>(lev[l], lev[l + 1]);
+      if (coarsen)
+        lds_residual_restrict<R, NT, true>(lev[l], lev[l + 1]);
+      else
+        lds_residual_restrict<R, NT>(lev[l], lev[l + 1]);
       __syncthreads();
       if (gamma == 2) again |= 1u << l;
       zero = true;
     }
+    coarsen = false;
     lds_coarsest_solve<R, NT>(lev[nlev - 1]);
     bool descend = false;
     while (l > top) {
@@ -434,7 +436,7 @@ __device__ __forceinline__ void cached_half_sweep(const SweepCache<R, CPT>& K, c
 // first red half-sweep -- the same sequence of operations as lds_cycle(lev, 0, ...).
 template <class R, int NT, int M>
 __device__ void lds_cycle_top_cached(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma,
-                                     bool top_zero) {
+                                     bool top_zero, bool coarsen) {
   constexpr int CPT = M * M / (2 * NT);
   static_assert(CPT >= 1 && 2 * CPT * NT == M * M, "every cell of the top level needs one owner");
   const LdsLevel<R>& L = lev[0];
@@ -451,9 +453,12 @@ __device__ void lds_cycle_top_cached(const LdsLevel<R>* lev, int nlev, int nu1, 
       __syncthreads();
     }
   }
-  lds_residual_restrict<R, NT>(lev[0], lev[1]);
+  if (coarsen)
+    lds_residual_restrict<R, NT, true>(lev[0], lev[1]);
+  else
+    lds_residual_restrict<R, NT>(lev[0], lev[1]);
   __syncthreads();
-  for (int g = 0; g < gamma; ++g) lds_cycle<R, NT>(lev, 1, nlev, nu1, nu2, gamma, g == 0);
+  for (int g = 0; g < gamma; ++g) lds_cycle<R, NT>(lev, 1, nlev, nu1, nu2, gamma, g == 0, coarsen && g == 0);
   if (RMG_FUSED_PROLONG && nu2 > 0) {
     SweepCache<R, CPT> K;
     sweep_cache_load<R, NT, M, CPT>(K, L);
@@ -475,21 +480,22 @@ __device__ void lds_cycle_top_cached(const LdsLevel<R>* lev, int nlev, int nu1, 
 // One cycle from the top level of the coarse kernel: register-cached top-level
 // sweeps where the level size has a specialisation, lds_cycle otherwise.
 template <class R, int NT>
-__device__ void lds_cycle_coarse(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma, bool top_zero) {
+__device__ void lds_cycle_coarse(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma, bool top_zero,
+                                 bool coarsen) {
   const int m = lev[0].m;
   if constexpr (sizeof(R) == 4 && 64 * 64 == 8 * NT) {
     if (nlev >= 2 && m == 64) {
-      lds_cycle_top_cached<R, NT, 64>(lev, nlev, nu1, nu2, gamma, top_zero);
+      lds_cycle_top_cached<R, NT, 64>(lev, nlev, nu1, nu2, gamma, top_zero, coarsen);
       return;
     }
   }
   if constexpr (32 * 32 == 2 * NT) {
     if (nlev >= 2 && m == 32) {
-      lds_cycle_top_cached<R, NT, 32>(lev, nlev, nu1, nu2, gamma, top_zero);
+      lds_cycle_top_cached<R, NT, 32>(lev, nlev, nu1, nu2, gamma, top_zero, coarsen);
       return;
     }
   }
-  lds_cycle<R, NT>(lev, 0, nlev, nu1, nu2, gamma, top_zero);
+  lds_cycle<R, NT>(lev, 0, nlev, nu1, nu2, gamma, top_zero, coarsen);
 }
 
 }  // namespace rmg

@@ -167,15 +167,12 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
       }
     }
     __syncthreads();
-    for (int l = 0; l + 1 < a.nlev; ++l) {
-      lds_coarsen<R, NT>(lev[l], lev[l + 1]);
-      __syncthreads();
-    }
     // a fixed number of cycles, or (cpp == 0) cycles until the correction equation's
-    // residual max_c |f - A dp| (level 0, smoother precision) is below eps_mg
+    // residual max_c |f - A dp| (level 0, smoother precision) is below eps_mg; the
+    // first cycle forms the coarse levels' coefficients on its way down
     int ncyc = 0;
     for (;;) {
-      lds_cycle<R, NT>(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, ncyc == 0);
+      lds_cycle<R, NT>(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, ncyc == 0, ncyc == 0);
       ++ncyc;
       if (a.cpp > 0) {
         if (ncyc == a.cpp) break;
@@ -575,11 +572,7 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   }
   for (int i = threadIdx.x; i < m; i += NT) T.cs[M2 + i] = CT[i];
   __syncthreads();
-  for (int l = 0; l + 1 < nlev; ++l) {
-    lds_coarsen<R, NT>(lev[l], lev[l + 1]);
-    __syncthreads();
-  }
-  lds_cycle_coarse<R, NT>(lev, nlev, a.nu1, a.nu2, a.gamma, u_zero != 0);
+  lds_cycle_coarse<R, NT>(lev, nlev, a.nu1, a.nu2, a.gamma, u_zero != 0, true);
   if (lt > 0 || !final_) {
     for (int v = threadIdx.x; v < nv; v += NT) {
       V o;
