@@ -65,6 +65,26 @@ __device__ R* lds_carve(R* base, LdsLevel<R>* lev, int m_top, int nlev) {
   return p;
 }
 
+// The top level of a hierarchy carved by lds_carve at `base`, computed by every
+// thread itself (usable before the barrier that publishes the level table).
+template <class R>
+__device__ __forceinline__ LdsLevel<R> lds_top_level(R* base, int m_top) {
+  LdsLevel<R> L;
+  L.m = m_top;
+  L.lg = 31 - __clz(m_top);
+  R* p = base;
+  L.u = (RMG_LDS R*)(p + 1 + m_top);
+  p += (m_top + 2) * m_top + 2;
+  L.f = (RMG_LDS R*)p;
+  p += m_top * m_top;
+  L.cw = (RMG_LDS R*)p;
+  p += m_top * m_top + 1;
+  L.cs = (RMG_LDS R*)p;
+  p += (m_top + 1) * m_top;
+  L.cdt = (RMG_LDS R*)p;
+  return L;
+}
+
 // Zero the elements of a hierarchy carved by lds_carve that no routine writes: the
 // zero rows and guards around each level's u and the trailing guard of its cw.
 // Every other element (cells of u, f, cw, cs including the top weights, cdt) is

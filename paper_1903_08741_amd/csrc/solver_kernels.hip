@@ -523,10 +523,11 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   double* red = (double*)smem;
   R* rbase = (R*)(red + NT / 64 + 1);
   __shared__ LdsLevel<R> lev[kMaxLevels];
-  lds_carve(rbase, lev, m, nlev);
+  lds_carve(rbase, lev, m, nlev);  // the level table is read only after the barrier below
   lds_zero_padding<R, NT>(rbase, m, nlev);
-  __syncthreads();
-  const LdsLevel<R>& T = lev[0];
+  // the top level is loaded before the first barrier: its global loads overlap the
+  // start-up of the workgroup's waves
+  const LdsLevel<R> T = lds_top_level(rbase, m);
   using V = typename Vec16<R>::T;
   constexpr int E = 16 / sizeof(R);  // elements per vector; M2 is a multiple of E
   const V* F = (const V*)((const R*)pl.lv.f[lt] + s * M2);
