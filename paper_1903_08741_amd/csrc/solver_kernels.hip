@@ -414,6 +414,19 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   const int x0 = (tile % ntx) * T, y0 = (tile / ntx) * T;
   const int64_t N = (int64_t)n * n;
   const double* p = a.p + s * N;
+  double* thold = a.theta_old + s * N;
+  // the tile cells this thread computes after the barrier below (T = 32 or n, a power
+  // of two): their old moisture content, which the halo phase does not touch, is
+  // loaded first so that these loads are in flight during that phase
+  constexpr int Q = (kTile * kTile + kBlock - 1) / kBlock;
+  const int lgT = 31 - __clz(T);
+  double pth[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = (int)threadIdx.x + q * kBlock;
+    pth[q] = 0.0;
+    if (!new_step && k < T * T) pth[q] = thold[(int64_t)(y0 + (k >> lgT)) * n + x0 + (k & (T - 1))];
+  }
   {
     const int tot = TL * TL;
     const unsigned mg = rmg_magic(TL);
@@ -455,13 +468,16 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   R* cs0 = (R*)pl.lv.cs[0] + s * N;
   R* cdt0 = (R*)pl.lv.cdt[0] + s * N;
   R* ctop0 = (R*)pl.lv.ctop[0] + s * n;
-  double* thold = a.theta_old + s * N;
   double* hist = nullptr;  // history slot of the step that starts here, if recorded
   if (new_step && a.p_hist) {
     const int k = st.step;
     if (k % a.hist_every == 0) hist = a.p_hist + (s * a.hist_slots + k / a.hist_every) * N;
   }
-  RMG_TILE_FOR(T, li, lj) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = (int)threadIdx.x + q * kBlock;
+    if (k >= T * T) continue;
+    const int lj = k >> lgT, li = k & (T - 1);
     const int e = lj * T + li;
     const int gi = x0 + li, gj = y0 + lj;
     const int64_t c = (int64_t)gj * n + gi;
@@ -474,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
       thold[c] = cl.theta;
       if (hist) hist[c] = sp[le];
     } else {
-      th_old = thold[c];
+      th_old = pth[q];
     }
     const FineCell fc = fine_cell(gi, gj, n, sp[le], sp[le - 1], sp[le + 1], sp[le - TL], sp[le + TL],
                                   sK[le], sK[le - 1], sK[le + 1], sK[le - TL], sK[le + TL], cl.theta,
