@@ -513,6 +513,77 @@ def pcmlmc_bench(args, torch, rmg, W):
     print(json.dumps(res), flush=True)
 
 
+def pcmlmc_eps_sweep(args, torch, rmg, W):
+    """Cost of Algorithm 1 against the tolerance (Section 6: with h_L proportional to eps the
+    estimator's cost grows like the cost of one deterministic solve on the finest grid).  The
+    Gardner hierarchy of pcmlmc_bench; the tolerance is halved while the finest grid is refined
+    by one level: (eps, L) = (1.6e-2, 2), (8e-3, 3), (4e-3, 4), (2e-3, 5), levels 16^2 .. 16 * 2^(L-1).
+    Cost is reported in work units (the sum over levels of pairs x Picard-MG cycles x cells) and in
+    wall time; the exponent is the least-squares slope of log(cost) against log(1 / eps).  With a
+    fixed number of time steps the work of one finest solve grows like h_L^-2 times its iteration
+    count (the paper refines the time step with the mesh as well, hence its eps^-3)."""
+    from paper_1903_08741_amd import kl_setup
+    dev = torch.device("cuda:0")
+    f, g = W.KS_FIELD, W.GARDNER_INFILTRATION
+    points = [(1.6e-2, 2), (8e-3, 3), (4e-3, 4), (2e-3, 5)]
+    all_grids = tuple(16 << l for l in range(max(L for _, L in points)))
+    _, tables = kl_setup.kl_tables(f["sigma2"], f["corr_len"], f["n_modes"], list(all_grids) + [8])
+    marg = [(0.0, f["log_mean"], f["scale"])]
+    warm = (64, 32, 16, 8, 8, 4)
+    ctx = rmg.default_context(0)
+    precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
+    out = []
+    for eps, L in points:
+        def prob(l, L=L):
+            return rmg.Problem(model=rmg.GARDNER, n_steps=g["n_steps"], theta_r=g["theta_r"], theta_s=g["theta_s"],
+                               gardner_a=1.0 - 0.1 * (L - 1 - l), h_top=g["h_top"], h_bottom=g["h_bottom"],
+                               h_init=g["h_init"], dt=g["dt"])
+        levels = []
+        for l in range(L):
+            n = all_grids[l]
+            levels.append(dict(n_fine=n, n_coarse=n // 2 if l else 0, n_warmup=warm[l], fine=prob(l),
+                               coarse=prob(l - 1) if l else None,
+                               basis_fine=torch.from_numpy(tables[n]).to(dev),
+                               basis_coarse=torch.from_numpy(tables[n // 2]).to(dev) if l else None))
+
+        def src(level, first, count, L=L):
+            return W.xi_draws(100 + L, level, range(first, first + count), 1, f["n_modes"])
+        opts = rmg.SolverOpts(precision=precision, max_picard=args.max_picard)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.pc_mlmc(levels, marg, opts, eps, src, max_rounds=50, max_pairs=args.max_pairs)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        pt = {"eps": eps, "levels": L, "finest": all_grids[L - 1], "work": r["total_cost"], "wall_ms": ms,
+              "N_l": [x["target"] for x in r["levels"]], "pairs_drawn": [x["drawn"] for x in r["levels"]],
+              "W_finest": r["levels"][-1]["W"],
+              "sampling_err": r["sampling_err2"] ** 0.5, "bias_estimate": r["bias"], "mean": r["mean"],
+              "converged": bool(r["converged"]), "rc": r["rc"]}
+        log(f"eps {eps:g} L {L}: work {r['total_cost']:.4g}, {ms:.0f} ms, N_l {pt['N_l']}, "
+            f"sampling err {pt['sampling_err']:.3g}, bias {r['bias']:.3g}")
+        out.append(pt)
+    x = np.log([1.0 / p["eps"] for p in out])
+
+    def slope(y):
+        y = np.log(y)
+        return float(np.polyfit(x, y, 1)[0])
+    res = {
+        "metric": "PC_MLMC cost against the tolerance (Algorithm 1, h_L ~ eps)",
+        "value": slope([p["work"] for p in out]), "unit": "exponent of work in 1/eps", "n_gpus": 1,
+        "steps": len(out), "warmup": 0, "ms_per_step": float(np.mean([p["wall_ms"] for p in out])),
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32 multigrid in f64 Picard" if precision == rmg.MIXED else "f64",
+        "data": "synthetic (seeded KL fields)",
+        "config": {"workload": f"PC_MLMC eps sweep, Gardner a_l = 1 - 0.1 (L-1-l), {g['n_steps']} steps "
+                               f"dt={g['dt']}, levels 16^2..16*2^(L-1), work cost model",
+                   "points": out},
+        "wall_time_exponent": slope([p["wall_ms"] for p in out]),
+        "finest_solve_work_exponent": slope([p["W_finest"] for p in out]),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 # ------------------------------------------------------------ robustness sweep
 def sweep_bench(args, torch, rmg, W):
     """Section 4.3's robustness sweep as one batched solve: the 20 x 20 (alpha, n) pairs of
@@ -592,6 +663,9 @@ def main():
     ap.add_argument("--time-steps", type=int, default=20, help="pcmlmc vg: backward-Euler steps (dt = 0.005)")
     ap.add_argument("--pc-model", choices=("gardner", "vg"), default="gardner", help="pcmlmc: hierarchy")
     ap.add_argument("--max-pairs", type=int, default=50000, help="pcmlmc: cap on the pairs drawn per level")
+    ap.add_argument("--eps-sweep", action="store_true",
+                    help="pcmlmc gardner: cost of Algorithm 1 against the tolerance, the finest grid refined "
+                         "as eps halves (h_L ~ eps)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
@@ -623,7 +697,10 @@ def main():
         sweep_bench(args, torch, rmg, W)
         return
     if args.workload == "pcmlmc":
-        pcmlmc_bench(args, torch, rmg, W)
+        if args.eps_sweep:
+            pcmlmc_eps_sweep(args, torch, rmg, W)
+        else:
+            pcmlmc_bench(args, torch, rmg, W)
         return
     dev = torch.device("cuda:0")
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
