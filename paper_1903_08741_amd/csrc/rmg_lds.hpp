@@ -518,4 +518,20 @@ __device__ void lds_cycle_coarse(const LdsLevel<R>* lev, int nlev, int nu1, int 
   lds_cycle<R, NT>(lev, 0, nlev, nu1, nu2, gamma, top_zero, coarsen);
 }
 
+// One cycle of the whole-sample kernel: register-cached top-level sweeps for 32 x 32
+// grids on 256 threads (two cells of each colour per thread); other sizes use
+// lds_cycle (on 16 x 16 grids the cache's registers cost more occupancy than it
+// saves).
+template <class R, int NT>
+__device__ void lds_cycle_whole(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma, bool top_zero,
+                                bool coarsen) {
+  if constexpr (NT == 256) {
+    if (nlev >= 2 && lev[0].m == 32) {
+      lds_cycle_top_cached<R, NT, 32>(lev, nlev, nu1, nu2, gamma, top_zero, coarsen);
+      return;
+    }
+  }
+  lds_cycle<R, NT>(lev, 0, nlev, nu1, nu2, gamma, top_zero, coarsen);
+}
+
 }  // namespace rmg

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     // first cycle forms the coarse levels' coefficients on its way down
     int ncyc = 0;
     for (;;) {
-      lds_cycle<R, NT>(lev, 0, a.nlev, a.nu1, a.nu2, a.gamma, ncyc == 0, ncyc == 0);
+      lds_cycle_whole<R, NT>(lev, a.nlev, a.nu1, a.nu2, a.gamma, ncyc == 0, ncyc == 0);
       ++ncyc;
       if (a.cpp > 0) {
         if (ncyc == a.cpp) break;
