@@ -175,10 +175,12 @@ int64_t rmg_struct_size(const char* name);
  * level-streaming down-leg kernel (nu1 fused red-black sweeps + residual +
  * restriction, Section 4.2) with HIP events on the stream they run on, and counts
  * the fine cells those launches processed.  The streaming solver advances in
- * batches of eight Picard iterations; the first iteration of every batch is
- * launched eagerly and timed, the other seven replay a HIP graph (events recorded
- * inside a graph cannot be timed), so the totals cover a uniform one-in-eight
- * sample of the launches.  Results do not depend on timing.  Algorithmic bytes per processed cell
+ * batches of eight Picard iterations; the first iteration of a timed batch is
+ * launched eagerly and timed, the other iterations replay HIP graphs (events
+ * recorded inside a graph cannot be timed).  Grid-size classes with fewer than
+ * 2^22 cells per iteration time every eighth batch, larger ones every batch, so
+ * the totals cover a uniform one-in-64 (one-in-8) sample of the launches.
+ * Results do not depend on timing.  Algorithmic bytes per processed cell
  * (each array touched once): read f, the two face coefficients and C/dt, write
  * the iterate and a quarter of a coarse right-hand side (5.25 elements), plus
  * one element when the initial iterate is loaded rather than zero. */

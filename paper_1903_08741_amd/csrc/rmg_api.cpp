@@ -304,15 +304,18 @@ int harvest_timer(rmg_ctx* ctx, KernelTimer* t, int64_t upto) {
 // read-back of the class's active-sample count (of its last iteration) and an event.  D batches stay in flight per class, so the
 // device never waits for the host; batches issued after the count reached zero
 // find no active sample and do nothing.  Classes are polled independently.
-// With kernel timing on, the first iteration of every batch is launched eagerly
+// With kernel timing on, the first iteration of a timed batch is launched eagerly
 // with its timed launches bracketed by events (events recorded by graph nodes
-// cannot be timed) and the other G - 1 replay a graph: a uniform sample of the
-// launches, one in G, at almost no cost to the run.
+// cannot be timed) and the other G - 1 replay a second graph.  An eager iteration
+// costs a roughly fixed extra host and queue time, so classes with short iterations
+// (fewer than kDenseCells cells per iteration) time every kTimedEvery-th batch and
+// the others every batch: a uniform sample of the launches, one in G * kTimedEvery
+// or one in G.
 int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
-  constexpr int G = 8, D = 3;
+  constexpr int G = 8, D = 3, kTimedEvery = 8;
+  constexpr int64_t kDenseCells = int64_t(1) << 22;
   static_assert(G % 2 == 0, "a batch must end on the odd plan (double-buffered per-sample state)");
   const bool timing = ctx->timing != 0;
-  const int Gg = timing ? G - 1 : G;  // iterations per graph replay
   if (jobs.size() > 16) return fail(ctx, RMG_EINVAL, "too many grid-size classes");
   int ti = 0;
   for (auto& j : jobs) {
@@ -347,8 +350,9 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
     j.done = true;
   }
-  std::vector<hipGraphExec_t> execs(jobs.size(), nullptr);
-  std::vector<hipGraph_t> graphs(jobs.size(), nullptr);
+  // per class: a graph of the batch's G iterations, and (timing) one of its last G - 1
+  std::vector<hipGraphExec_t> execs(2 * jobs.size(), nullptr);
+  std::vector<hipGraph_t> graphs(2 * jobs.size(), nullptr);
   auto cleanup = [&]() {
     for (auto& e : execs)
       if (e) (void)hipGraphExecDestroy(e);
@@ -362,27 +366,28 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
       StreamPlan untimed = j.pl;
       untimed.timer = nullptr;
       const StreamPlan untimed_odd = flip(untimed);
-      const char* what = "hipStreamBeginCapture";
-      hipError_t e = hipStreamBeginCapture(j.stream, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) what = "captured iteration launches";
-      // with timing the batch's first (even) iteration is launched eagerly
-      for (int i = 0; i < Gg && e == hipSuccess; ++i)
-        e = launch_stream_iteration(j.a, ((i + (timing ? 1 : 0)) & 1) ? untimed_odd : untimed, j.stream);
-      hipGraph_t g = nullptr;
-      const hipError_t e2 = hipStreamEndCapture(j.stream, &g);
-      graphs[c] = g;
-      if (e == hipSuccess) {
-        e = e2;
-        what = "hipStreamEndCapture";
-      }
-      if (e == hipSuccess) {
-        e = hipGraphInstantiate(&execs[c], g, nullptr, nullptr, 0);
-        what = "hipGraphInstantiate";
-      }
-      if (e != hipSuccess) {
-        cleanup();
-        return fail(ctx, RMG_EHIP, "graph capture of the Picard iteration failed in %s: %s", what,
-                    hipGetErrorString(e));
+      for (int first = 0; first < (timing ? 2 : 1); ++first) {
+        const char* what = "hipStreamBeginCapture";
+        hipError_t e = hipStreamBeginCapture(j.stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) what = "captured iteration launches";
+        for (int i = first; i < G && e == hipSuccess; ++i)
+          e = launch_stream_iteration(j.a, (i & 1) ? untimed_odd : untimed, j.stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(j.stream, &g);
+        graphs[2 * c + first] = g;
+        if (e == hipSuccess) {
+          e = e2;
+          what = "hipStreamEndCapture";
+        }
+        if (e == hipSuccess) {
+          e = hipGraphInstantiate(&execs[2 * c + first], g, nullptr, nullptr, 0);
+          what = "hipGraphInstantiate";
+        }
+        if (e != hipSuccess) {
+          cleanup();
+          return fail(ctx, RMG_EHIP, "graph capture of the Picard iteration failed in %s: %s", what,
+                      hipGetErrorString(e));
+        }
       }
     }
   }
@@ -413,11 +418,12 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     untimed.timer = nullptr;
     const StreamPlan untimed_odd = flip(untimed);
     hipError_t e = hipSuccess;
-    if (timing) e = launch_stream_iteration(j.a, j.pl, j.stream);
+    const bool timed = timing && ((int64_t)j.a.S * j.a.n * j.a.n >= kDenseCells || issued[c] % kTimedEvery == 0);
+    if (timed) e = launch_stream_iteration(j.a, j.pl, j.stream);
     if (use_graphs) {
-      if (e == hipSuccess) e = hipGraphLaunch(execs[c], j.stream);
+      if (e == hipSuccess) e = hipGraphLaunch(execs[2 * c + (timed ? 1 : 0)], j.stream);
     } else {
-      for (int i = timing ? 1 : 0; i < G && e == hipSuccess; ++i)
+      for (int i = timed ? 1 : 0; i < G && e == hipSuccess; ++i)
         e = launch_stream_iteration(j.a, (i & 1) ? untimed_odd : untimed, j.stream);
     }
     if (e == hipSuccess)

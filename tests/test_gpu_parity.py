@@ -133,11 +133,14 @@ def test_graph_replay_equals_eager_and_timing_is_transparent(precision):
         assert torch.equal(a["h"], o["h"])
         assert (a["stats"]["picard_its"] == o["stats"]["picard_its"]).all()
     # one or two streaming levels (the coarse kernel starts at 64^2 in FP32, at 32^2 in
-    # FP64) of down-leg launches per Picard iteration; the first iteration of every
-    # batch of eight is timed
+    # FP64) of down-leg launches per Picard iteration; batches hold eight iterations
+    # (at most four more batches than the slowest sample needs are issued) and the
+    # first iteration of every eighth batch, starting with the first, is timed (this
+    # class has fewer than 2^22 cells per iteration)
     its = int(c["stats"]["picard_its"].max())
     k = 2 if precision == rmg.FP64 else 1
-    assert t["launches"] % k == 0 and k * (its // 8) <= t["launches"] <= k * (its // 8 + 4)
+    lo, hi = -(-(its // 8) // 8), -(-(its // 8 + 4) // 8)
+    assert t["launches"] % k == 0 and k * lo <= t["launches"] <= k * hi
     assert t["total_ms"] > 0 and t["cells"] > 0
     es = 8 if precision == rmg.FP64 else 4
     assert abs(t["algo_bytes"] - 5.25 * es * t["cells"]) < 1e-6 * t["algo_bytes"]
