@@ -64,7 +64,9 @@ __device__ __forceinline__ Closure closure(const rmg_problem& P, double p, doubl
       const double t = 1.0 - exp(m * log(w));
       r.K = Ks * sqrt(S) * t * t;
       r.theta = P.theta_r + dth * S;
-      r.C = dth * a * m * n * exp(-(m + 1.0) * l1u) * exp((n - 1.0) * lap);
+      // dS/d|ap| = m n (1+u)^-(m+1) |ap|^(n-1) with (1+u)^-(m+1) = S / (1+u) and
+      // |ap|^(n-1) = u / |ap|: no further exponentials
+      r.C = dth * a * m * n * (S / (1.0 + u)) * (u / ap);
     } else {
       r.K = Ks;
       r.theta = P.theta_s;

@@ -415,49 +415,56 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
   const int64_t N = (int64_t)n * n;
   const double* p = a.p + s * N;
   double* thold = a.theta_old + s * N;
-  // the tile cells this thread computes after the barrier below (T = 32 or n, a power
-  // of two): their old moisture content, which the halo phase does not touch, is
-  // loaded first so that these loads are in flight during that phase
+  // The tile's own cells (T = 32 or n, a power of two; k = threadIdx.x + q kBlock):
+  // pressure head and closure once per cell, K and p to LDS for the neighbours, the
+  // moisture content and capacity kept in registers for the cell phase after the
+  // barrier; the old moisture content is loaded here as well, so that its loads are
+  // in flight meanwhile.  Then the halo ring (one cell per thread): p and K only.
   constexpr int Q = (kTile * kTile + kBlock - 1) / kBlock;
   const int lgT = 31 - __clz(T);
-  double pth[Q];
+  double cth[Q], cC[Q], pth[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int k = (int)threadIdx.x + q * kBlock;
-    pth[q] = 0.0;
-    if (!new_step && k < T * T) pth[q] = thold[(int64_t)(y0 + (k >> lgT)) * n + x0 + (k & (T - 1))];
-  }
-  {
-    const int tot = TL * TL;
-    const unsigned mg = rmg_magic(TL);
-    constexpr int B = 4;
-    for (int k0 = threadIdx.x; k0 < tot; k0 += B * kBlock) {
-      double pv[B], k0v[B], k1v[B], k2v[B];
-      bool in[B];
-#pragma unroll
-      for (int q = 0; q < B; ++q) {
-        const int k = k0 + q * kBlock;
-        const int lj = (int)__umulhi((unsigned)k, mg), li = k - lj * TL;
-        const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
-        in[q] = k < tot && gi >= 0 && gi < n && gj >= 0 && gj < n;
-        pv[q] = k0v[q] = k1v[q] = k2v[q] = 0.0;
-        if (in[q]) {
-          const int64_t c = (int64_t)gj * n + gi;
-          pv[q] = p[c];
-          const CellFields cf = load_fields(a.fields, a.F, N, s, c);
-          k0v[q] = cf.Ks;
-          k1v[q] = cf.alpha;
-          k2v[q] = cf.nvg;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < B; ++q) {
-        const int k = k0 + q * kBlock;
-        if (k >= tot) continue;
-        sp[k] = pv[q];
-        sK[k] = in[q] ? closure(P, pv[q], k0v[q], k1v[q], k2v[q]).K : 0.0;
-      }
+    cth[q] = cC[q] = pth[q] = 0.0;
+    if (k < T * T) {
+      const int lj = k >> lgT, li = k & (T - 1);
+      const int64_t c = (int64_t)(y0 + lj) * n + x0 + li;
+      if (!new_step) pth[q] = thold[c];
+      const double pv = p[c];
+      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+      const Closure cl = closure(P, pv, cf.Ks, cf.alpha, cf.nvg);
+      const int le = (lj + 1) * TL + li + 1;
+      sp[le] = pv;
+      sK[le] = cl.K;
+      cth[q] = cl.theta;
+      cC[q] = cl.C;
     }
+  }
+  for (int r = threadIdx.x; r < 4 * TL - 4; r += kBlock) {
+    int li, lj;  // bottom row, top row, then the left and right columns without corners
+    if (r < TL) {
+      li = r;
+      lj = 0;
+    } else if (r < 2 * TL) {
+      li = r - TL;
+      lj = TL - 1;
+    } else {
+      const int q = r - 2 * TL;
+      li = (q & 1) ? TL - 1 : 0;
+      lj = 1 + (q >> 1);
+    }
+    const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
+    const int le = lj * TL + li;
+    double pv = 0.0, K = 0.0;
+    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+      const int64_t c = (int64_t)gj * n + gi;
+      pv = p[c];
+      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+      K = closure(P, pv, cf.Ks, cf.alpha, cf.nvg).K;
+    }
+    sp[le] = pv;
+    sK[le] = K;
   }
   __syncthreads();
   R* tcw = bufA;
@@ -482,19 +489,17 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
     const int gi = x0 + li, gj = y0 + lj;
     const int64_t c = (int64_t)gj * n + gi;
     const int le = (lj + 1) * TL + li + 1;
-    const CellFields cf = load_fields(a.fields, a.F, N, s, c);
-    const Closure cl = closure(P, sp[le], cf.Ks, cf.alpha, cf.nvg);
     double th_old;
     if (new_step) {
-      th_old = cl.theta;
-      thold[c] = cl.theta;
+      th_old = cth[q];
+      thold[c] = cth[q];
       if (hist) hist[c] = sp[le];
     } else {
       th_old = pth[q];
     }
     const FineCell fc = fine_cell(gi, gj, n, sp[le], sp[le - 1], sp[le + 1], sp[le - TL], sp[le + TL],
-                                  sK[le], sK[le - 1], sK[le + 1], sK[le - TL], sK[le + TL], cl.theta,
-                                  th_old, cl.C, P.dt, P.h_bottom, P.h_top);
+                                  sK[le], sK[le - 1], sK[le + 1], sK[le - TL], sK[le + TL], cth[q],
+                                  th_old, cC[q], P.dt, P.h_bottom, P.h_top);
     const R rf = (R)fc.f, rcw = (R)fc.cw, rcs = (R)fc.cs, rcdt = (R)fc.cdt;
     f0[c] = rf;
     cw0[c] = rcw;
