@@ -34,58 +34,51 @@ __host__ __device__ constexpr int lds_level_elems(int m) {
   return ((m + 2) * m + 2) + m * m + (m * m + 1) + (m + 1) * m + m * m;
 }
 
-// Carve levels of sizes m_top, m_top/2, ..., m_bottom out of `base`; returns the
-// end pointer.  The level table `lev` lives in LDS (a runtime-indexed table in
-// registers would be spilled to scratch); thread 0 fills it, the caller must
-// synchronise before reading it.
+// The levels m_top, m_top/2, ... laid out one after another from `base`.  Level l
+// starts sum_{k<l} lds_level_elems(m_top >> k) elements in, which in closed form
+// is 20 (m^2 - m_l^2) / 3 + 6 (m - m_l) + 3 l with m = m_top, m_l = m >> l, so a
+// level's pointers are a few scalar operations away and need no table: a table in
+// LDS would put one more LDS round trip in front of every phase's loads, and a
+// runtime-indexed table in registers would live in scratch memory.
 template <class R>
-__device__ R* lds_carve(R* base, LdsLevel<R>* lev, int m_top, int nlev) {
-  R* p = base;
-  int m = m_top;
-  int lg = 31 - __clz(m_top);
-  const bool w = threadIdx.x == 0;
-  for (int l = 0; l < nlev; ++l) {
-    if (w) {
-      lev[l].m = m;
-      lev[l].lg = lg;
-      lev[l].u = (RMG_LDS R*)(p + 1 + m);
-    }
-    p += (m + 2) * m + 2;
-    if (w) lev[l].f = (RMG_LDS R*)p;
-    p += m * m;
-    if (w) lev[l].cw = (RMG_LDS R*)p;
-    p += m * m + 1;
-    if (w) lev[l].cs = (RMG_LDS R*)p;
-    p += (m + 1) * m;
-    if (w) lev[l].cdt = (RMG_LDS R*)p;
-    p += m * m;
-    m >>= 1;
-    --lg;
+struct LdsHier {
+  R* base;
+  int m_top, lg_top;
+  __device__ __forceinline__ int offset(int l) const {
+    const int ml = m_top >> l;
+    return (20 * (m_top * m_top - ml * ml)) / 3 + 6 * (m_top - ml) + 3 * l;
   }
-  return p;
-}
+  __device__ __forceinline__ LdsLevel<R> operator[](int l) const {
+    LdsLevel<R> L;
+    const int m = m_top >> l;
+    L.m = m;
+    L.lg = lg_top - l;
+    R* p = base + offset(l);
+    L.u = (RMG_LDS R*)(p + 1 + m);
+    p += (m + 2) * m + 2;
+    L.f = (RMG_LDS R*)p;
+    p += m * m;
+    L.cw = (RMG_LDS R*)p;
+    p += m * m + 1;
+    L.cs = (RMG_LDS R*)p;
+    p += (m + 1) * m;
+    L.cdt = (RMG_LDS R*)p;
+    return L;
+  }
+  // one past the last element of levels 0 .. nlev-1
+  __device__ __forceinline__ R* end(int nlev) const { return base + offset(nlev); }
+};
 
-// The top level of a hierarchy carved by lds_carve at `base`, computed by every
-// thread itself (usable before the barrier that publishes the level table).
 template <class R>
-__device__ __forceinline__ LdsLevel<R> lds_top_level(R* base, int m_top) {
-  LdsLevel<R> L;
-  L.m = m_top;
-  L.lg = 31 - __clz(m_top);
-  R* p = base;
-  L.u = (RMG_LDS R*)(p + 1 + m_top);
-  p += (m_top + 2) * m_top + 2;
-  L.f = (RMG_LDS R*)p;
-  p += m_top * m_top;
-  L.cw = (RMG_LDS R*)p;
-  p += m_top * m_top + 1;
-  L.cs = (RMG_LDS R*)p;
-  p += (m_top + 1) * m_top;
-  L.cdt = (RMG_LDS R*)p;
-  return L;
+__device__ __forceinline__ LdsHier<R> lds_hier(R* base, int m_top) {
+  LdsHier<R> H;
+  H.base = base;
+  H.m_top = m_top;
+  H.lg_top = 31 - __clz(m_top);
+  return H;
 }
 
-// Zero the elements of a hierarchy carved by lds_carve that no routine writes: the
+// Zero the elements of a hierarchy (LdsHier) that no routine writes: the
 // zero rows and guards around each level's u and the trailing guard of its cw.
 // Every other element (cells of u, f, cw, cs including the top weights, cdt) is
 // written before it is read: loaded or computed on the top level, produced by
@@ -296,7 +289,7 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L) {
 // Post-smoothing of level l after its coarse correction (prolongation fused into the
 // first red half-sweep when nu2 > 0).
 template <class R, int NT>
-__device__ void lds_up_leg(const LdsLevel<R>* lev, int l, int nu2) {
+__device__ void lds_up_leg(const LdsHier<R>& lev, int l, int nu2) {
   if (RMG_FUSED_PROLONG && nu2 > 0) {
     lds_half_sweep_prolong<R, NT>(lev[l], lev[l + 1]);
     __syncthreads();
@@ -320,7 +313,7 @@ __device__ void lds_up_leg(const LdsLevel<R>* lev, int l, int nu2) {
 // the coefficients of the levels below `top` are formed on the first descent, each
 // in the restriction pass that enters its level (before the level is first used).
 template <class R, int NT>
-__device__ void lds_cycle(const LdsLevel<R>* lev, int top, int nlev, int nu1, int nu2, int gamma,
+__device__ void lds_cycle(const LdsHier<R>& lev, int top, int nlev, int nu1, int nu2, int gamma,
                           bool top_zero, bool coarsen = false) {
   int l = top;
   bool zero = top_zero;
@@ -455,11 +448,11 @@ __device__ __forceinline__ void cached_half_sweep(const SweepCache<R, CPT>& K, c
 // first from a zero iterate), post-smoothing with the prolongation fused into its
 // first red half-sweep -- the same sequence of operations as lds_cycle(lev, 0, ...).
 template <class R, int NT, int M>
-__device__ void lds_cycle_top_cached(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma,
+__device__ void lds_cycle_top_cached(const LdsHier<R>& lev, int nlev, int nu1, int nu2, int gamma,
                                      bool top_zero, bool coarsen) {
   constexpr int CPT = M * M / (2 * NT);
   static_assert(CPT >= 1 && 2 * CPT * NT == M * M, "every cell of the top level needs one owner");
-  const LdsLevel<R>& L = lev[0];
+  const LdsLevel<R> L = lev[0];
   {
     SweepCache<R, CPT> K;
     sweep_cache_load<R, NT, M, CPT>(K, L);
@@ -500,9 +493,9 @@ __device__ void lds_cycle_top_cached(const LdsLevel<R>* lev, int nlev, int nu1, 
 // One cycle from the top level of the coarse kernel: register-cached top-level
 // sweeps where the level size has a specialisation, lds_cycle otherwise.
 template <class R, int NT>
-__device__ void lds_cycle_coarse(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma, bool top_zero,
+__device__ void lds_cycle_coarse(const LdsHier<R>& lev, int nlev, int nu1, int nu2, int gamma, bool top_zero,
                                  bool coarsen) {
-  const int m = lev[0].m;
+  const int m = lev.m_top;
   if constexpr (sizeof(R) == 4 && 64 * 64 == 8 * NT) {
     if (nlev >= 2 && m == 64) {
       lds_cycle_top_cached<R, NT, 64>(lev, nlev, nu1, nu2, gamma, top_zero, coarsen);
@@ -523,10 +516,10 @@ __device__ void lds_cycle_coarse(const LdsLevel<R>* lev, int nlev, int nu1, int 
 // lds_cycle (on 16 x 16 grids the cache's registers cost more occupancy than it
 // saves).
 template <class R, int NT>
-__device__ void lds_cycle_whole(const LdsLevel<R>* lev, int nlev, int nu1, int nu2, int gamma, bool top_zero,
+__device__ void lds_cycle_whole(const LdsHier<R>& lev, int nlev, int nu1, int nu2, int gamma, bool top_zero,
                                 bool coarsen) {
   if constexpr (NT == 256) {
-    if (nlev >= 2 && lev[0].m == 32) {
+    if (nlev >= 2 && lev.m_top == 32) {
       lds_cycle_top_cached<R, NT, 32>(lev, nlev, nu1, nu2, gamma, top_zero, coarsen);
       return;
     }

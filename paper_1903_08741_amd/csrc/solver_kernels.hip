@@ -80,8 +80,8 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   double* thS = pS + (SL ? N : 0);
   double* fS = thS + (SL ? N : 0);
   R* rbase = (R*)(fS + (SL ? F * N : 0));
-  __shared__ LdsLevel<R> lev[kMaxLevels];
-  R* rend = lds_carve(rbase, lev, n, a.nlev);
+  const LdsHier<R> lev = lds_hier(rbase, n);
+  R* rend = lev.end(a.nlev);
   for (R* q = rbase + threadIdx.x; q < rend; q += NT) *q = (R)0;
 
   double* pg = a.p + s * N;
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
 
   int step = 0, it = 0, new_step = 1, status = RMG_SAMPLE_OK, tot_its = 0, cycles = 0;
   double dp = 0.0;
-  const LdsLevel<R>& L0 = lev[0];
+  const LdsLevel<R> L0 = lev[0];
   for (;;) {
     // conductivity at every cell (FP64)
     for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
@@ -543,12 +543,11 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   const int M2 = m * m;
   double* red = (double*)smem;
   R* rbase = (R*)(red + NT / 64 + 1);
-  __shared__ LdsLevel<R> lev[kMaxLevels];
-  lds_carve(rbase, lev, m, nlev);  // the level table is read only after the barrier below
+  const LdsHier<R> lev = lds_hier(rbase, m);
   lds_zero_padding<R, NT>(rbase, m, nlev);
   // the top level is loaded before the first barrier: its global loads overlap the
   // start-up of the workgroup's waves
-  const LdsLevel<R> T = lds_top_level(rbase, m);
+  const LdsLevel<R> T = lev[0];
   using V = typename Vec16<R>::T;
   constexpr int E = 16 / sizeof(R);  // elements per vector; M2 is a multiple of E
   const V* F = (const V*)((const R*)pl.lv.f[lt] + s * M2);
