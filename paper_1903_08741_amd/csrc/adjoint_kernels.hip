@@ -167,7 +167,61 @@ __global__ __launch_bounds__(kBlock) void k_adj_fine(SolveArgs a, StreamPlan pl,
   const int x0 = (blockIdx.x % ntx) * T, y0 = (blockIdx.x / ntx) * T;
   const int64_t N = (int64_t)n * n;
   const double* pk = ad.hist + (s * ad.slots + (st.step - ad.base)) * N;
-  adj_load_tile(a, P, s, pk, ad.mu + s * N, n, x0, y0, TL, sp, sK, sm);
+  const double* mu = ad.mu + s * N;
+  double* bb = ad.b + s * N;
+  // The tile's own cells (k = threadIdx.x + q kBlock; T = 32 or n, a power of two):
+  // p, mu and the closure once per cell, K to LDS for the neighbours and C kept in
+  // registers for the cell phase, the stored right-hand side (a step already
+  // started) loaded here so that its loads are in flight during this phase; then
+  // the halo ring (one cell per thread): p, K and mu only.
+  constexpr int Q = (kTile * kTile + kBlock - 1) / kBlock;
+  const int lgT = 31 - __clz(T);
+  double cC[Q], pb[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = (int)threadIdx.x + q * kBlock;
+    cC[q] = pb[q] = 0.0;
+    if (k < T * T) {
+      const int lj = k >> lgT, li = k & (T - 1);
+      const int64_t c = (int64_t)(y0 + lj) * n + x0 + li;
+      if (!st.new_step) pb[q] = bb[c];
+      const double pv = pk[c];
+      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+      const Closure cl = closure(P, pv, cf.Ks, cf.alpha, cf.nvg);
+      const int le = (lj + 1) * TL + li + 1;
+      sp[le] = pv;
+      sK[le] = cl.K;
+      sm[le] = mu[c];
+      cC[q] = cl.C;
+    }
+  }
+  for (int r = threadIdx.x; r < 4 * TL - 4; r += kBlock) {
+    int li, lj;  // bottom row, top row, then the left and right columns without corners
+    if (r < TL) {
+      li = r;
+      lj = 0;
+    } else if (r < 2 * TL) {
+      li = r - TL;
+      lj = TL - 1;
+    } else {
+      const int q = r - 2 * TL;
+      li = (q & 1) ? TL - 1 : 0;
+      lj = 1 + (q >> 1);
+    }
+    const int gi = x0 - 1 + li, gj = y0 - 1 + lj;
+    const int le = lj * TL + li;
+    double pv = 0.0, Kv = 0.0, mv = 0.0;
+    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+      const int64_t c = (int64_t)gj * n + gi;
+      pv = pk[c];
+      mv = mu[c];
+      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
+      Kv = closure(P, pv, cf.Ks, cf.alpha, cf.nvg).K;
+    }
+    sp[le] = pv;
+    sK[le] = Kv;
+    sm[le] = mv;
+  }
   __syncthreads();
   R* tcw = bufA;
   R* tcdt = bufA + T * T;
@@ -177,19 +231,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_fine(SolveArgs a, StreamPlan pl,
   R* cs0 = (R*)pl.lv.cs[0] + s * N;
   R* cdt0 = (R*)pl.lv.cdt[0] + s * N;
   R* ctop0 = (R*)pl.lv.ctop[0] + s * n;
-  double* bb = ad.b + s * N;
   const double h = 1.0 / (double)n;
-  RMG_TILE_FOR(T, li, lj) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = (int)threadIdx.x + q * kBlock;
+    if (k >= T * T) continue;
+    const int lj = k >> lgT, li = k & (T - 1);
     const int e = lj * T + li;
     const int gi = x0 + li, gj = y0 + lj;
     const int64_t c = (int64_t)gj * n + gi;
     const int le = (lj + 1) * TL + li + 1;
     const double pc = sp[le], Kc = sK[le];
-    const CellFields cf = load_fields(a.fields, a.F, N, s, c);
-    const double C = closure(P, pc, cf.Ks, cf.alpha, cf.nvg).C;
     const AdjCell ac = adj_cell(gi, gj, n, pc, sp[le - 1], sp[le + 1], sp[le - TL], sp[le + TL], Kc, sK[le - 1],
                                 sK[le + 1], sK[le - TL], sK[le + TL], sm[le], sm[le - 1], sm[le + 1], sm[le - TL],
-                                sm[le + TL], C, P.dt, P.h_bottom, P.h_top);
+                                sm[le + TL], cC[q], P.dt, P.h_bottom, P.h_top);
     const double Kp = dK_dp(P, pc, Kc);
     double b;
     if (st.new_step) {
@@ -200,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_fine(SolveArgs a, StreamPlan pl,
       }
       bb[c] = b;
     } else {
-      b = bb[c];
+      b = pb[q];
     }
     const double r = (b + Kp * ac.smu) - ac.Amu;
     const R rcw = (R)ac.cw, rcs = (R)ac.cs, rcdt = (R)ac.cdt;
