@@ -4,14 +4,17 @@
 //
 // Layout of a level with m x m cells (element type R):
 //   u   : one zero row, m*m cells, one zero row (plus one guard each end), so
-//         u[c - m], u[c + m], u[c - 1], u[c + 1] are always readable; neighbours
-//         outside the domain read 0 and meet a zero or Dirichlet-only coefficient;
+//         u[c - m], u[c + m], u[c - 1], u[c + 1] are always readable; a neighbour
+//         outside the domain (a zero row below or above, or across the left or
+//         right side the end cell of the adjacent row) meets a zero or
+//         Dirichlet-only coefficient;
 //   f, cdt : m*m;
 //   cw  : m*m + 1, cw[j*m] = 0 (no-flux left face) and cw[m*m] = 0, so the east
 //         coefficient cw[c + 1] of a right-edge cell is the next row's left face = 0;
 //   cs  : (m+1)*m, rows 0..m-1 are south faces (row 0: bottom Dirichlet weight),
 //         row m holds the top Dirichlet weights, so the north coefficient is cs[c + m].
-// The zero rows and guards are written once when the workgroup starts.
+// The zero rows and guards are written once when the workgroup starts; levels follow
+// one another in that order of arrays (LdsHier).
 #pragma once
 
 #include "rmg_device.hpp"
