@@ -163,16 +163,30 @@ __device__ void lds_half_sweep_prolong(const LdsLevel<R>& L, const LdsLevel<R>& 
   }
 }
 
-template <class R, int NT>
+// Ordering between phases: a workgroup barrier, or (WAVE: the levels that the first
+// wavefront runs alone) a wavefront-scope fence -- LDS operations of one wavefront
+// complete in issue order, so only the compiler must be kept from moving them.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <class R, int NT, bool WAVE = false>
 __device__ void lds_sweeps(const LdsLevel<R>& L, int nu, bool from_zero = false) {
   for (int s = 0; s < nu; ++s) {
     if (s == 0 && from_zero)
       lds_half_sweep_from_zero<R, NT>(L);
     else
       lds_half_sweep<R, NT>(L, 0);
-    __syncthreads();
+    lds_sync<WAVE>();
     lds_half_sweep<R, NT>(L, 1);
-    __syncthreads();
+    lds_sync<WAVE>();
   }
 }
 
@@ -270,7 +284,7 @@ __device__ __attribute__((noinline)) void coarsest_gauss_jordan(const LdsLevel<R
   if ((int)threadIdx.x < N) L.u[c] = (R)(b * rpiv);
 }
 
-template <class R, int NT>
+template <class R, int NT, bool WAVE = false>
 __device__ void lds_coarsest_solve(const LdsLevel<R>& L) {
   static_assert(NT >= 64, "the coarsest solve runs on the first wavefront");
   if (threadIdx.x < 64) {
@@ -279,7 +293,7 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L) {
     else
       coarsest_gauss_jordan<R, 4>(L);
   }
-  __syncthreads();
+  lds_sync<WAVE>();
 }
 
 #ifndef RMG_ZERO_SWEEP
@@ -291,20 +305,24 @@ __device__ void lds_coarsest_solve(const LdsLevel<R>& L) {
 
 // Post-smoothing of level l after its coarse correction (prolongation fused into the
 // first red half-sweep when nu2 > 0).
-template <class R, int NT>
+template <class R, int NT, bool WAVE = false>
 __device__ void lds_up_leg(const LdsHier<R>& lev, int l, int nu2) {
   if (RMG_FUSED_PROLONG && nu2 > 0) {
     lds_half_sweep_prolong<R, NT>(lev[l], lev[l + 1]);
-    __syncthreads();
+    lds_sync<WAVE>();
     lds_half_sweep<R, NT>(lev[l], 1);
-    __syncthreads();
-    lds_sweeps<R, NT>(lev[l], nu2 - 1);
+    lds_sync<WAVE>();
+    lds_sweeps<R, NT, WAVE>(lev[l], nu2 - 1);
   } else {
     lds_prolong_add<R, NT>(lev[l], lev[l + 1]);
-    __syncthreads();
-    lds_sweeps<R, NT>(lev[l], nu2);
+    lds_sync<WAVE>();
+    lds_sweeps<R, NT, WAVE>(lev[l], nu2);
   }
 }
+
+#ifndef RMG_WS_WAVE_M
+#define RMG_WS_WAVE_M 8
+#endif
 
 // One multigrid cycle from level `top` of the LDS hierarchy (levels top .. nlev-1;
 // gamma = 1: V-cycle, gamma = 2: W-cycle; Section 4.2), written as a loop: descend
@@ -315,25 +333,47 @@ __device__ void lds_up_leg(const LdsHier<R>& lev, int l, int nu2) {
 // iterate.  `top_zero`: the iterate on level `top` is zero on entry.  `coarsen`:
 // the coefficients of the levels below `top` are formed on the first descent, each
 // in the restriction pass that enters its level (before the level is first used).
-template <class R, int NT>
+// WM > 0: the levels below `top` of at most WM x WM cells are cycled by the first
+// wavefront alone, without workgroup barriers, as the bottom solve of the levels
+// above them (the same operations in the same order per cell).  Measured: it pays
+// in the whole-sample kernel's W-cycles (WM = 8: robustness sweep -2 %), not in the
+// coarse kernel's V-cycle (WM = 16 there: +1 % per MLMC step).
+template <class R, int NT, bool WAVE = false, int WM = 0>
 __device__ void lds_cycle(const LdsHier<R>& lev, int top, int nlev, int nu1, int nu2, int gamma,
                           bool top_zero, bool coarsen = false) {
+  int nb = nlev - 1;  // bottom: the coarsest level, or the first wavefront's levels
+  if constexpr (!WAVE && NT > 64 && WM > 0) {
+    for (int l = top + 1; l < nlev - 1; ++l)
+      if ((lev.m_top >> l) <= WM) {
+        nb = l;
+        break;
+      }
+  }
   int l = top;
   bool zero = top_zero;
   unsigned again = 0;  // bit l: level l owes one more coarse cycle (W-cycle)
   for (;;) {
-    for (; l < nlev - 1; ++l) {
-      lds_sweeps<R, NT>(lev[l], nu1, RMG_ZERO_SWEEP && zero);
+    for (; l < nb; ++l) {
+      lds_sweeps<R, NT, WAVE>(lev[l], nu1, RMG_ZERO_SWEEP && zero);
       if (coarsen)
         lds_residual_restrict<R, NT, true>(lev[l], lev[l + 1]);
       else
         lds_residual_restrict<R, NT>(lev[l], lev[l + 1]);
-      __syncthreads();
+      lds_sync<WAVE>();
       if (gamma == 2) again |= 1u << l;
       zero = true;
     }
+    if constexpr (!WAVE && NT > 64 && WM > 0) {
+      if (nb < nlev - 1) {
+        if (threadIdx.x < 64) lds_cycle<R, 64, true>(lev, nb, nlev, nu1, nu2, gamma, zero, coarsen);
+        __syncthreads();
+      } else {
+        lds_coarsest_solve<R, NT>(lev[nlev - 1]);
+      }
+    } else {
+      lds_coarsest_solve<R, NT, WAVE>(lev[nlev - 1]);
+    }
     coarsen = false;
-    lds_coarsest_solve<R, NT>(lev[nlev - 1]);
     bool descend = false;
     while (l > top) {
       --l;
@@ -344,7 +384,7 @@ __device__ void lds_cycle(const LdsHier<R>& lev, int top, int nlev, int nu1, int
         descend = true;
         break;
       }
-      lds_up_leg<R, NT>(lev, l, nu2);
+      lds_up_leg<R, NT, WAVE>(lev, l, nu2);
     }
     if (!descend) return;
   }
@@ -450,7 +490,7 @@ __device__ __forceinline__ void cached_half_sweep(const SweepCache<R, CPT>& K, c
 // level, M*M = 2*CPT*NT): pre-smoothing, restriction, gamma cycles of level 1 (the
 // first from a zero iterate), post-smoothing with the prolongation fused into its
 // first red half-sweep -- the same sequence of operations as lds_cycle(lev, 0, ...).
-template <class R, int NT, int M>
+template <class R, int NT, int M, int WM = 0>
 __device__ void lds_cycle_top_cached(const LdsHier<R>& lev, int nlev, int nu1, int nu2, int gamma,
                                      bool top_zero, bool coarsen) {
   constexpr int CPT = M * M / (2 * NT);
@@ -474,7 +514,8 @@ __device__ void lds_cycle_top_cached(const LdsHier<R>& lev, int nlev, int nu1, i
   else
     lds_residual_restrict<R, NT>(lev[0], lev[1]);
   __syncthreads();
-  for (int g = 0; g < gamma; ++g) lds_cycle<R, NT>(lev, 1, nlev, nu1, nu2, gamma, g == 0, coarsen && g == 0);
+  for (int g = 0; g < gamma; ++g)
+    lds_cycle<R, NT, false, WM>(lev, 1, nlev, nu1, nu2, gamma, g == 0, coarsen && g == 0);
   if (RMG_FUSED_PROLONG && nu2 > 0) {
     SweepCache<R, CPT> K;
     sweep_cache_load<R, NT, M, CPT>(K, L);
@@ -523,11 +564,11 @@ __device__ void lds_cycle_whole(const LdsHier<R>& lev, int nlev, int nu1, int nu
                                 bool coarsen) {
   if constexpr (NT == 256) {
     if (nlev >= 2 && lev.m_top == 32) {
-      lds_cycle_top_cached<R, NT, 32>(lev, nlev, nu1, nu2, gamma, top_zero, coarsen);
+      lds_cycle_top_cached<R, NT, 32, RMG_WS_WAVE_M>(lev, nlev, nu1, nu2, gamma, top_zero, coarsen);
       return;
     }
   }
-  lds_cycle<R, NT>(lev, 0, nlev, nu1, nu2, gamma, top_zero, coarsen);
+  lds_cycle<R, NT, false, RMG_WS_WAVE_M>(lev, 0, nlev, nu1, nu2, gamma, top_zero, coarsen);
 }
 
 }  // namespace rmg
