@@ -126,11 +126,14 @@ def grid_classes(levels):
     return out
 
 
-def per_grid(torch, rmg, ctx, levels, opts, marg):
-    """Each grid's solves alone (one picard_mg_solve call per grid, after one untimed call)."""
+def per_grid(torch, rmg, ctx, levels, opts, marg, only=None):
+    """Each grid's solves alone (one picard_mg_solve call per grid, after one untimed call);
+    only: that grid size alone."""
     res = {}
     prob = levels[0]["fine"]
     for n, c in sorted(grid_classes(levels).items()):
+        if only is not None and n != only:
+            continue
         xi = torch.cat(c["xi"]).contiguous()
         fields = ctx.sample_fields(n, c["basis"], xi, marg)
         ctx.picard_mg_solve(n, fields, prob, opts)
@@ -663,6 +666,9 @@ def main():
     ap.add_argument("--time-steps", type=int, default=20, help="pcmlmc vg: backward-Euler steps (dt = 0.005)")
     ap.add_argument("--pc-model", choices=("gardner", "vg"), default="gardner", help="pcmlmc: hierarchy")
     ap.add_argument("--max-pairs", type=int, default=50000, help="pcmlmc: cap on the pairs drawn per level")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="gardner: solve only this grid size's class of the MLMC workload (one untimed and "
+                         "one timed call; for profiling one class)")
     ap.add_argument("--eps-sweep", action="store_true",
                     help="pcmlmc gardner: cost of Algorithm 1 against the tolerance, the finest grid refined "
                          "as eps halves (h_L ~ eps)")
@@ -717,6 +723,19 @@ def main():
     if confine:
         opts.flags |= rmg.FLAG_CONFINE
     ctx = rmg.default_context(0)
+    if args.grid:
+        res = per_grid(torch, rmg, ctx, levels, opts, marg, only=args.grid)
+        if not res:
+            sys.exit(f"no grid-size class {args.grid} in this workload")
+        r = res[str(args.grid)]
+        print(json.dumps({"metric": "Picard-MG sample solves/sec of one grid-size class", "value": r["solves_per_s"],
+                          "unit": "sample solves/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": r["ms"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f32 multigrid in f64 Picard" if precision == rmg.MIXED else "f64",
+                          "data": "synthetic (seeded KL lognormal Ks fields)",
+                          "config": {"workload": f"grid {args.grid} class of the {'vg' if vg else 'gardner'} MLMC "
+                                                 f"workload", **r}}), flush=True)
+        return
     total = n_solves(levels)
     sums = None
     for i in range(args.warmup):
