@@ -110,15 +110,30 @@ __device__ __forceinline__ St5<R> lds_st5(const LdsLevel<R>& L, int c) {
                 L.u[c - m], L.u[c + m]);
 }
 
+// Cell (i, j) of the k-th cell of `colour` on an m x m level (m = 2^(hlg+1)).  The
+// cells of one colour in a row lie two apart, so a row's worth of lanes would meet
+// every LDS bank it touches twice; lanes therefore take chunks of up to 16 cells
+// alternately from rows 2r and 2r+1, whose cells of that colour sit on the other
+// bank parity (a row is a multiple of 32 elements apart from the next-but-one), so
+// consecutive lanes cover all banks.  Any order of the cells of one colour gives
+// the same sweep.  (Keeping the plain row order below 32 x 32, where the chunks are
+// shorter, was measured slower: the branch cost more than the index operations.)
+__device__ __forceinline__ void rb_cell(int k, int m, int hlg, int colour, int& i, int& j) {
+  const int lgc = hlg < 4 ? hlg : 4;  // chunk of min(16, m/2) cells
+  const int w = k & (m - 1);          // position within the row pair
+  const int q = ((w >> (lgc + 1)) << lgc) | (w & ((1 << lgc) - 1));
+  j = 2 * (k >> (hlg + 1)) + ((w >> lgc) & 1);
+  i = 2 * q + ((j + colour) & 1);
+}
+
 // One colour of a red-black Gauss-Seidel sweep (colour 0 = red = (i+j) even).
 template <class R, int NT>
 __device__ void lds_half_sweep(const LdsLevel<R>& L, int colour) {
   const int m = L.m, hlg = L.lg - 1;
   const int tot = (m * m) >> 1;
   for (int k = threadIdx.x; k < tot; k += NT) {
-    const int j = k >> hlg;
-    const int q = k - (j << hlg);
-    const int i = 2 * q + ((j + colour) & 1);
+    int i, j;
+    rb_cell(k, m, hlg, colour, i, j);
     const int c = j * m + i;
     L.u[c] = gs_value<R>(L.f[c], lds_st5(L, c));
   }
@@ -132,9 +147,8 @@ __device__ void lds_half_sweep_from_zero(const LdsLevel<R>& L) {
   const int m = L.m, hlg = L.lg - 1;
   const int tot = (m * m) >> 1;
   for (int k = threadIdx.x; k < tot; k += NT) {
-    const int j = k >> hlg;
-    const int q = k - (j << hlg);
-    const int i = 2 * q + (j & 1);
+    int i, j;
+    rb_cell(k, m, hlg, 0, i, j);
     const int c = j * m + i;
     const St5<R> s = st5<R>(L.cdt[c], L.cw[c], L.cw[c + 1], L.cs[c], L.cs[c + m], (R)0, (R)0, (R)0, (R)0);
     L.u[c] = gs_value<R>(L.f[c], s);
@@ -150,9 +164,8 @@ __device__ void lds_half_sweep_prolong(const LdsLevel<R>& L, const LdsLevel<R>& 
   const int m = L.m, hlg = L.lg - 1, mc = C.m;
   const int tot = (m * m) >> 1;
   for (int k = threadIdx.x; k < tot; k += NT) {
-    const int j = k >> hlg;
-    const int q = k - (j << hlg);
-    const int i = 2 * q + (j & 1);
+    int i, j;
+    rb_cell(k, m, hlg, 0, i, j);
     const int c = j * m + i;
     const R uw = i > 0 ? L.u[c - 1] + C.u[(j >> 1) * mc + ((i - 1) >> 1)] : (R)0;
     const R ue = i < m - 1 ? L.u[c + 1] + C.u[(j >> 1) * mc + ((i + 1) >> 1)] : (R)0;
@@ -410,10 +423,7 @@ template <int NT, int M>
 __device__ __forceinline__ int sweep_cell(int colour, int r, int& i, int& j) {
   constexpr int hlg = (M == 64 ? 6 : M == 32 ? 5 : M == 16 ? 4 : 3) - 1;
   static_assert((1 << (hlg + 1)) == M, "unsupported level size");
-  const int k = (int)threadIdx.x + r * NT;
-  j = k >> hlg;
-  const int q = k - (j << hlg);
-  i = 2 * q + ((j + colour) & 1);
+  rb_cell((int)threadIdx.x + r * NT, M, hlg, colour, i, j);
   return j * M + i;
 }
 
