@@ -213,10 +213,16 @@ __device__ void lds_residual_restrict(const LdsLevel<R>& F, const LdsLevel<R>& C
   for (int kc = threadIdx.x; kc < mc * mc; kc += NT) {
     const int J = kc >> C.lg, I = kc - (J << C.lg);
     const int c00 = (2 * J) * m + 2 * I;
-    const R r00 = residual_value<R>(F.f[c00], F.u[c00], lds_st5(F, c00));
-    const R r01 = residual_value<R>(F.f[c00 + 1], F.u[c00 + 1], lds_st5(F, c00 + 1));
-    const R r10 = residual_value<R>(F.f[c00 + m], F.u[c00 + m], lds_st5(F, c00 + m));
-    const R r11 = residual_value<R>(F.f[c00 + m + 1], F.u[c00 + m + 1], lds_st5(F, c00 + m + 1));
+    // alternate 16-lane chunks take the two cells of a fine row in the other order,
+    // so that one load instruction touches both bank parities
+    const int sw = (threadIdx.x >> 4) & 1;
+    const int ca = c00 + sw, cb = c00 + 1 - sw;
+    const R ra0 = residual_value<R>(F.f[ca], F.u[ca], lds_st5(F, ca));
+    const R rb0 = residual_value<R>(F.f[cb], F.u[cb], lds_st5(F, cb));
+    const R ra1 = residual_value<R>(F.f[ca + m], F.u[ca + m], lds_st5(F, ca + m));
+    const R rb1 = residual_value<R>(F.f[cb + m], F.u[cb + m], lds_st5(F, cb + m));
+    const R r00 = sw ? rb0 : ra0, r01 = sw ? ra0 : rb0;
+    const R r10 = sw ? rb1 : ra1, r11 = sw ? ra1 : rb1;
     C.f[kc] = restrict4<R>(r00, r01, r10, r11);
     C.u[kc] = (R)0;
     if (COARSEN) {
