@@ -419,6 +419,10 @@ __device__ void lds_cycle(const LdsHier<R>& lev, int top, int nlev, int nu1, int
 // stores.  The arithmetic is that of st5 / gs_value in the same order, so the
 // results are bit-identical to lds_cycle's.
 
+#ifndef RMG_NEST_CACHE
+#define RMG_NEST_CACHE 1
+#endif
+
 template <class R, int CPT>
 struct SweepCache {
   R d[2][CPT], aw[2][CPT], ae[2][CPT], as[2][CPT], an[2][CPT], f[2][CPT];
@@ -502,16 +506,19 @@ __device__ __forceinline__ void cached_half_sweep(const SweepCache<R, CPT>& K, c
                               K.an[colour][r], K.f[colour][r], uw[r], ue[r], us[r], un[r]);
 }
 
-// lds_cycle from level 0 with the top level's sweeps from registers (M x M top
-// level, M*M = 2*CPT*NT): pre-smoothing, restriction, gamma cycles of level 1 (the
+// lds_cycle from level LVL (M x M cells, M*M = 2*CPT*NT) with that level's sweeps
+// from registers: pre-smoothing, restriction, gamma cycles of level LVL+1 (the
 // first from a zero iterate), post-smoothing with the prolongation fused into its
-// first red half-sweep -- the same sequence of operations as lds_cycle(lev, 0, ...).
-template <class R, int NT, int M, int WM = 0>
+// first red half-sweep -- the same sequence of operations as lds_cycle(lev, LVL,
+// ...).  Where level LVL+1 has one cell of each colour per thread, its cycles are
+// register-cached too.
+template <class R, int NT, int M, int WM = 0, int LVL = 0>
 __device__ void lds_cycle_top_cached(const LdsHier<R>& lev, int nlev, int nu1, int nu2, int gamma,
                                      bool top_zero, bool coarsen) {
   constexpr int CPT = M * M / (2 * NT);
   static_assert(CPT >= 1 && 2 * CPT * NT == M * M, "every cell of the top level needs one owner");
-  const LdsLevel<R> L = lev[0];
+  constexpr bool kNest = RMG_NEST_CACHE && WM == 0 && (M / 2) * (M / 2) == 2 * NT;
+  const LdsLevel<R> L = lev[LVL];
   {
     SweepCache<R, CPT> K;
     sweep_cache_load<R, NT, M, CPT>(K, L);
@@ -526,16 +533,23 @@ __device__ void lds_cycle_top_cached(const LdsHier<R>& lev, int nlev, int nu1, i
     }
   }
   if (coarsen)
-    lds_residual_restrict<R, NT, true>(lev[0], lev[1]);
+    lds_residual_restrict<R, NT, true>(lev[LVL], lev[LVL + 1]);
   else
-    lds_residual_restrict<R, NT>(lev[0], lev[1]);
+    lds_residual_restrict<R, NT>(lev[LVL], lev[LVL + 1]);
   __syncthreads();
-  for (int g = 0; g < gamma; ++g)
-    lds_cycle<R, NT, false, WM>(lev, 1, nlev, nu1, nu2, gamma, g == 0, coarsen && g == 0);
+  for (int g = 0; g < gamma; ++g) {
+    if constexpr (kNest) {
+      if (nlev >= LVL + 3) {
+        lds_cycle_top_cached<R, NT, M / 2, WM, LVL + 1>(lev, nlev, nu1, nu2, gamma, g == 0, coarsen && g == 0);
+        continue;
+      }
+    }
+    lds_cycle<R, NT, false, WM>(lev, LVL + 1, nlev, nu1, nu2, gamma, g == 0, coarsen && g == 0);
+  }
   if (RMG_FUSED_PROLONG && nu2 > 0) {
     SweepCache<R, CPT> K;
     sweep_cache_load<R, NT, M, CPT>(K, L);
-    cached_half_sweep<R, NT, M, CPT, 2>(K, L, lev[1], 0);
+    cached_half_sweep<R, NT, M, CPT, 2>(K, L, lev[LVL + 1], 0);
     __syncthreads();
     cached_half_sweep<R, NT, M, CPT, 0>(K, L, L, 1);
     __syncthreads();
@@ -546,7 +560,7 @@ __device__ void lds_cycle_top_cached(const LdsHier<R>& lev, int nlev, int nu1, i
       __syncthreads();
     }
   } else {
-    lds_up_leg<R, NT>(lev, 0, nu2);
+    lds_up_leg<R, NT>(lev, LVL, nu2);
   }
 }
 
