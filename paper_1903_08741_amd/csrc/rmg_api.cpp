@@ -333,6 +333,9 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
   // the whole-sample launches also wait until every streaming class's initialisation
   // has run (a whole-sample launch occupies the compute units for milliseconds, and
   // an initialisation dispatched beside it waited that long).
+  int nstream = 0;
+  for (const auto& j : jobs) nstream += j.whole ? 0 : 1;
+  for (auto& j : jobs) j.a.fuse_top = (!j.whole && nstream == 1) ? 1 : 0;
   int ninit = 0;
   for (auto& j : jobs) {
     if (j.whole) continue;

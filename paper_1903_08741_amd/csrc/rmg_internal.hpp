@@ -57,6 +57,8 @@ struct SolveArgs {
   int nu1, nu2, cpp, max_picard;
   int gamma;  // coarse cycles per level visit: 1 = V-cycle, 2 = W-cycle
   int state_global;  // whole-sample kernel: keep the FP64 state in global memory even if LDS fits
+  int fuse_top;      // level streaming with the coarse kernel's top level the finest: one launch
+                     // per Picard iteration (set when the class is its call's only streaming class)
   double eps;     // Picard stopping tolerance on ||dp||_inf
   double eps_mg;  // cycles_per_picard == 0: cycle until max |f - A dp| < eps_mg
   double* p;

@@ -620,6 +620,145 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   }
 }
 
+// One Picard iteration of an M x M sample whose finest level is the coarse kernel's
+// top level, in one workgroup: the stopping test of the previous iteration (as in
+// k_fine), the fine coefficients formed as k_fine forms them (closure once per cell;
+// p and K of the cells and of the zero ring around the grid staged in LDS where the
+// top level will lie: each thread keeps its cells' coefficients in registers until
+// the staging is dead, then writes them into the top level of the LDS hierarchy, so
+// the kernel needs no more LDS than k_coarse_v), the cycles of k_coarse_v, and its
+// Picard update.  One launch per iteration instead of two, and the top level's
+// coefficients never go through global memory; every value is computed by the same
+// operations in the same order as on the two-kernel path.
+#ifndef RMG_FUSED_FINE_COARSE
+#define RMG_FUSED_FINE_COARSE 1
+#endif
+constexpr int kFusedM = 64;  // the float coarse kernel's top level
+
+template <class R, int NT, int M>
+__global__ __launch_bounds__(NT) void k_fine_coarse(SolveArgs a, StreamPlan pl) {
+  static_assert((M * M) % NT == 0, "every thread forms the same number of cells");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t s = blockIdx.x;
+  const rmg_problem P = class_problem(a.cp, s);
+  SampleState st = pl.state_prev[s];
+  if (st.fresh)
+    st.fresh = 0;
+  else if (st.active)
+    control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
+  if (threadIdx.x == 0) {
+    pl.state[s] = st;
+    pl.dpmax[s] = 0ull;
+    if (st.active) atomicAdd(pl.active_count, 1);
+    if (s == 0) *pl.count_next = 0;
+  }
+  if (!st.active) return;
+  constexpr int M2 = M * M, TL = M + 2, LG = M == 64 ? 6 : M == 32 ? 5 : 4, Q = M2 / NT;
+  static_assert((1 << LG) == M, "unsupported grid size");
+  const int nlev = a.nlev;
+  const int new_step = st.new_step;
+  double* red = (double*)smem;
+  R* rbase = (R*)(red + NT / 64 + 1);
+  const LdsHier<R> lev = lds_hier(rbase, M);
+  const LdsLevel<R> T = lev[0];
+  static_assert(8 * (NT / 64 + 1) + 2 * sizeof(double) * TL * TL <= 8 * (NT / 64 + 1) + lds_level_elems(M) * sizeof(R),
+                "the staging fits in the top level's place");
+  double* sp = (double*)rbase;  // 8-byte aligned: rbase follows NT / 64 + 1 doubles
+  double* sK = sp + TL * TL;
+  const double* pg = a.p + s * M2;
+  double* thold = a.theta_old + s * M2;
+  double cth[Q], cC[Q], pth[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = (int)threadIdx.x + q * NT;
+    const int lj = c >> LG, li = c & (M - 1);
+    pth[q] = 0.0;
+    if (!new_step) pth[q] = thold[c];
+    const double pv = pg[c];
+    const CellFields cf = load_fields(a.fields, a.F, (int64_t)M2, s, c);
+    const Closure cl = closure(P, pv, cf.Ks, cf.alpha, cf.nvg);
+    const int le = (lj + 1) * TL + li + 1;
+    sp[le] = pv;
+    sK[le] = cl.K;
+    cth[q] = cl.theta;
+    cC[q] = cl.C;
+  }
+  for (int r = threadIdx.x; r < 4 * TL - 4; r += NT) {
+    int li, lj;  // bottom row, top row, then the left and right columns without corners
+    if (r < TL) {
+      li = r;
+      lj = 0;
+    } else if (r < 2 * TL) {
+      li = r - TL;
+      lj = TL - 1;
+    } else {
+      const int q = r - 2 * TL;
+      li = (q & 1) ? TL - 1 : 0;
+      lj = 1 + (q >> 1);
+    }
+    sp[lj * TL + li] = 0.0;
+    sK[lj * TL + li] = 0.0;
+  }
+  __syncthreads();
+  double* hist = nullptr;  // history slot of the step that starts here, if recorded
+  if (new_step && a.p_hist) {
+    const int k = st.step;
+    if (k % a.hist_every == 0) hist = a.p_hist + (s * a.hist_slots + k / a.hist_every) * M2;
+  }
+  R rf[Q], rcw[Q], rcs[Q], rcdt[Q], rct = (R)0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = (int)threadIdx.x + q * NT;
+    const int lj = c >> LG, li = c & (M - 1);
+    const int le = (lj + 1) * TL + li + 1;
+    double th_old;
+    if (new_step) {
+      th_old = cth[q];
+      thold[c] = cth[q];
+      if (hist) hist[c] = sp[le];
+    } else {
+      th_old = pth[q];
+    }
+    const FineCell fc = fine_cell(li, lj, M, sp[le], sp[le - 1], sp[le + 1], sp[le - TL], sp[le + TL], sK[le],
+                                  sK[le - 1], sK[le + 1], sK[le - TL], sK[le + TL], cth[q], th_old, cC[q], P.dt,
+                                  P.h_bottom, P.h_top);
+    rf[q] = (R)fc.f;
+    rcw[q] = (R)fc.cw;
+    rcs[q] = (R)fc.cs;
+    rcdt[q] = (R)fc.cdt;
+    if (q == Q - 1) rct = (R)fc.ctop;  // the top row's cells are every thread's last ones
+  }
+  static_assert(M <= NT, "the top row lies in the last NT cells, every thread's last ones");
+  __syncthreads();  // the staging is dead: the hierarchy takes its place
+  lds_zero_padding<R, NT>(rbase, M, nlev);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = (int)threadIdx.x + q * NT;
+    T.f[c] = rf[q];
+    T.cw[c] = rcw[q];
+    T.cs[c] = rcs[q];
+    T.cdt[c] = rcdt[q];
+    T.u[c] = (R)0;
+    if (q == Q - 1 && (c >> LG) == M - 1) T.cs[M2 + (c & (M - 1))] = rct;
+  }
+  __syncthreads();
+  for (int cyc = 0; cyc < a.cpp; ++cyc) lds_cycle_coarse<R, NT>(lev, nlev, a.nu1, a.nu2, a.gamma, cyc == 0, cyc == 0);
+  double* p = a.p + s * M2;
+  double mx = 0.0, bad = 0.0;
+  for (int c = threadIdx.x; c < M2; c += NT) {
+    const double d = (double)T.u[c];
+    p[c] += d;
+    mx = fmax(mx, fabs(d));
+    if (!isfinite(d)) bad = 1.0;
+  }
+  mx = block_max<NT>(mx, red);
+  bad = block_max<NT>(bad, red);
+  if (threadIdx.x == 0) {
+    pl.dpmax[s] = (unsigned long long)__double_as_longlong(mx);
+    if (bad > 0.0) pl.state[s].nanflag = 1;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPlan pl) {
   __shared__ double red[kBlock];
   const int64_t s = blockIdx.x;
@@ -740,10 +879,34 @@ static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStr
   return err;
 }
 
+// LDS of k_fine_coarse: that of k_coarse_v (the p / K staging lies in the top level's place).
+static size_t fine_coarse_lds(int m, int nc) { return coarse_lds(m, nc, false); }
+
+template <class R>
+static bool fine_coarse_fits(const SolveArgs& a, const StreamPlan& pl) {
+  return RMG_FUSED_FINE_COARSE && sizeof(R) == 4 && pl.ltop == 0 && a.n == kFusedM && a.nlev >= 2;
+}
+// Measured: with the class alone on the GPU the fused launch shortens the 64 x 64
+// class by 8 %; beside the larger streaming classes of a multilevel call it makes
+// the call 2 % slower (its one workgroup per sample holds a compute unit through the
+// coefficient assembly that k_fine spreads over four), so it is taken only when the
+// class is its call's only streaming class.
+template <class R>
+static bool fused_fine_coarse(const SolveArgs& a, const StreamPlan& pl) {
+  return a.fuse_top && fine_coarse_fits<R>(a, pl);
+}
+
 template <class R>
 static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
   const dim3 blk(kBlock);
   const int n = a.n;
+  if constexpr (sizeof(R) == 4) {
+    if (fused_fine_coarse<R>(a, pl)) {
+      hipLaunchKernelGGL((k_fine_coarse<R, kCoarseThreads, kFusedM>), dim3((unsigned)a.S), dim3(kCoarseThreads),
+                         fine_coarse_lds(n, n >> (a.nlev - 1)), st, a, pl);
+      return hipGetLastError();
+    }
+  }
   {
     const int T = n < kTile ? n : kTile;
     const unsigned tiles = (unsigned)((n / T) * (n / T));
@@ -761,6 +924,11 @@ static hipError_t set_stream_lds(const SolveArgs& a, const StreamPlan& pl) {
   // (the down and up kernels need at most 23 KiB of LDS, below the default limit)
   hipError_t e = hipFuncSetAttribute((const void*)k_coarse_v<R, kCoarseThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)coarse_lds(a.n >> pl.ltop, nc, fp64));
+  if constexpr (sizeof(R) == 4) {
+    if (e == hipSuccess && fine_coarse_fits<R>(a, pl))
+      e = hipFuncSetAttribute((const void*)k_fine_coarse<R, kCoarseThreads, kFusedM>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)fine_coarse_lds(a.n, nc));
+  }
   return e;
 }
 

@@ -352,3 +352,29 @@ def test_coarse_partner_equals_fine_member_bitwise():
     q = q.cpu().numpy()
     # layout: level 0 fine [0:6], level 0 coarse (NaN) [6:12], level 1 fine [12:18], level 1 coarse [18:24]
     assert np.array_equal(q[0:6], q[18:24])
+
+
+def test_fused_iteration_equals_two_kernel_path_bitwise():
+    """A 64 x 64 class that is its call's only streaming class runs one fused launch per
+    Picard iteration; beside a 128 x 128 class it runs the fine kernel and then the coarse
+    kernel.  Both paths perform the same operations, so the QoIs agree bit for bit."""
+    say("fused 64^2 Picard iteration vs the two-kernel path")
+    Bs = oracle_basis()
+    xt = torch.from_numpy(W.xi_draws(13, 0, range(5), 1, 64)).to(DEV)
+    b64, b128 = torch.from_numpy(Bs[64]).to(DEV), torch.from_numpy(Bs[128]).to(DEV)
+    marg = [(0.0, 0.0, 1.0)]
+    lv0 = dict(n_fine=64, n_coarse=0, fine=rmg.Problem(), basis_fine=b64, xi=xt)
+    lv1 = dict(n_fine=128, n_coarse=64, fine=rmg.Problem(), coarse=rmg.Problem(), basis_fine=b128,
+               basis_coarse=b64, xi=xt[:2].contiguous())
+    opts = rmg.SolverOpts(max_picard=500)
+    _, q, rc = rmg.mlmc_level_estimate([lv0, lv1], marg, opts, return_qoi=True)
+    assert rc in (0, rmg.RMG_ENOTCONV)
+    q = q.cpu().numpy()
+    alone = rmg.picard_mg_solve(64, rmg.sample_fields(64, b64, xt, marg), rmg.Problem(), opts)
+    assert alone["rc"] in (0, rmg.RMG_ENOTCONV)
+    qa = alone["qoi"].cpu().numpy()
+    # layout: level 0 fine [0:5], level 0 coarse (NaN) [5:10], level 1 fine [10:12], level 1 coarse [12:14]
+    # (a sample that fails the iteration limit has a NaN QoI on both paths)
+    assert np.isfinite(qa).sum() >= 3
+    assert np.array_equal(q[0:5], qa, equal_nan=True)
+    assert np.array_equal(q[12:14], qa[:2], equal_nan=True)
