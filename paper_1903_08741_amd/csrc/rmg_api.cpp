@@ -30,13 +30,16 @@ constexpr int kTimerPairs = 4096;
 // Measured on the 5-level Gardner MLMC workload: all CUs 253 ms per call, 50 % 244 ms,
 // 25 % 239 ms; on the van Genuchten workload the heavy 32^2 whole-sample class then
 // becomes the critical path (1776 ms against ~1500), so the restriction is requested
-// per call (flag bit 7).  0 compiles it out.
+// per call (flag bit 7).  0 compiles it out.  Re-measured at the current kernels
+// (Gardner call 195.6 ms): 12.5 % 195.7 ms, 37.5 % 197.5 ms.
 #ifndef RMG_WHOLE_CU_PCT
 #define RMG_WHOLE_CU_PCT 25
 #endif
 // Share of the compute units the other level-streaming classes of such a call may
 // use, leaving the rest to the largest grid's chain (the critical path): 239 ms per
-// call with every class on every CU, 232 ms at 75 %, 230 ms at 63 %, 258 ms at 50 %.
+// call with every class on every CU, 232 ms at 75 %, 230 ms at 63 %, 258 ms at 50 %;
+// at the current kernels 195.6 ms at 75 %, 195.3 ms at 63 % (within the run-to-run
+// spread), 197.4 ms at 88 %.
 #ifndef RMG_OTHER_CU_PCT
 #define RMG_OTHER_CU_PCT 75
 #endif
