@@ -118,8 +118,19 @@ __device__ __forceinline__ St5<R> lds_st5(const LdsLevel<R>& L, int c) {
 // consecutive lanes cover all banks.  Any order of the cells of one colour gives
 // the same sweep.  (Keeping the plain row order below 32 x 32, where the chunks are
 // shorter, was measured slower: the branch cost more than the index operations.)
+// LGC: log2 of the chunk; LGC >= hlg gives the plain order (row 2r, then row 2r+1).
+// The chunks pay in the 512-thread coarse kernel (5-level step -1.5 %); the smaller
+// workgroups of the whole-sample kernel keep the plain order (with it, rather than
+// the chunks, the robustness sweep takes 1814 ms against 1829 ms and the 5-level
+// step 194.7 ms against 195.7 ms).
+template <int NT>
+__host__ __device__ constexpr int rb_chunk_lg() {
+  return NT >= 512 ? 4 : 30;
+}
+
+template <int LGC>
 __device__ __forceinline__ void rb_cell(int k, int m, int hlg, int colour, int& i, int& j) {
-  const int lgc = hlg < 4 ? hlg : 4;  // chunk of min(16, m/2) cells
+  const int lgc = hlg < LGC ? hlg : LGC;  // chunk of min(2^LGC, m/2) cells
   const int w = k & (m - 1);          // position within the row pair
   const int q = ((w >> (lgc + 1)) << lgc) | (w & ((1 << lgc) - 1));
   j = 2 * (k >> (hlg + 1)) + ((w >> lgc) & 1);
@@ -133,7 +144,7 @@ __device__ void lds_half_sweep(const LdsLevel<R>& L, int colour) {
   const int tot = (m * m) >> 1;
   for (int k = threadIdx.x; k < tot; k += NT) {
     int i, j;
-    rb_cell(k, m, hlg, colour, i, j);
+    rb_cell<rb_chunk_lg<NT>()>(k, m, hlg, colour, i, j);
     const int c = j * m + i;
     L.u[c] = gs_value<R>(L.f[c], lds_st5(L, c));
   }
@@ -148,7 +159,7 @@ __device__ void lds_half_sweep_from_zero(const LdsLevel<R>& L) {
   const int tot = (m * m) >> 1;
   for (int k = threadIdx.x; k < tot; k += NT) {
     int i, j;
-    rb_cell(k, m, hlg, 0, i, j);
+    rb_cell<rb_chunk_lg<NT>()>(k, m, hlg, 0, i, j);
     const int c = j * m + i;
     const St5<R> s = st5<R>(L.cdt[c], L.cw[c], L.cw[c + 1], L.cs[c], L.cs[c + m], (R)0, (R)0, (R)0, (R)0);
     L.u[c] = gs_value<R>(L.f[c], s);
@@ -165,7 +176,7 @@ __device__ void lds_half_sweep_prolong(const LdsLevel<R>& L, const LdsLevel<R>& 
   const int tot = (m * m) >> 1;
   for (int k = threadIdx.x; k < tot; k += NT) {
     int i, j;
-    rb_cell(k, m, hlg, 0, i, j);
+    rb_cell<rb_chunk_lg<NT>()>(k, m, hlg, 0, i, j);
     const int c = j * m + i;
     const R uw = i > 0 ? L.u[c - 1] + C.u[(j >> 1) * mc + ((i - 1) >> 1)] : (R)0;
     const R ue = i < m - 1 ? L.u[c + 1] + C.u[(j >> 1) * mc + ((i + 1) >> 1)] : (R)0;
@@ -214,8 +225,9 @@ __device__ void lds_residual_restrict(const LdsLevel<R>& F, const LdsLevel<R>& C
     const int J = kc >> C.lg, I = kc - (J << C.lg);
     const int c00 = (2 * J) * m + 2 * I;
     // alternate 16-lane chunks take the two cells of a fine row in the other order,
-    // so that one load instruction touches both bank parities
-    const int sw = (threadIdx.x >> 4) & 1;
+    // so that one load instruction touches both bank parities (the workgroups that
+    // sweep in chunks; the order does not change the values)
+    const int sw = rb_chunk_lg<NT>() <= 4 ? ((threadIdx.x >> 4) & 1) : 0;
     const int ca = c00 + sw, cb = c00 + 1 - sw;
     const R ra0 = residual_value<R>(F.f[ca], F.u[ca], lds_st5(F, ca));
     const R rb0 = residual_value<R>(F.f[cb], F.u[cb], lds_st5(F, cb));
@@ -433,7 +445,7 @@ template <int NT, int M>
 __device__ __forceinline__ int sweep_cell(int colour, int r, int& i, int& j) {
   constexpr int hlg = (M == 64 ? 6 : M == 32 ? 5 : M == 16 ? 4 : 3) - 1;
   static_assert((1 << (hlg + 1)) == M, "unsupported level size");
-  rb_cell((int)threadIdx.x + r * NT, M, hlg, colour, i, j);
+  rb_cell<rb_chunk_lg<NT>()>((int)threadIdx.x + r * NT, M, hlg, colour, i, j);
   return j * M + i;
 }
 
