@@ -31,6 +31,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# LDS peak: 256 compute units x 128 bytes per clock x 2.4 GHz.
+LDS_PEAK_BPS = 256 * 128 * 2.4e9
+# Access-pattern model of the coarse cycle (FP32, 64^2 -> 4^2, V(2,2)): per cell and level
+# visit, nu1 + nu2 = 4 red-black sweeps (the 64^2 and 32^2 levels keep coefficients, right-hand
+# side and diagonal in registers: four neighbour reads and one write per update; the coarser
+# levels read the five coefficients and the right-hand side from LDS as well: 11 accesses),
+# the residual restriction (11 reads per fine cell, a quarter of a coarse cell written twice)
+# and the prolongation (one coarse read per fine cell): 32.5 elements per visit on the cached
+# levels, 56.5 on the others; the cached levels hold 94 % of the visited cells.
+LDS_BYTES_PER_CELL_VISIT = 4 * (0.94 * 32.5 + 0.06 * 56.5)
+# Workgroup barriers per coarse cycle on 64^2 -> 4^2 with V(2,2): per level above the coarsest,
+# 2 nu1 pre-smoothing half-sweeps, the restriction and 2 nu2 post-smoothing half-sweeps (the
+# prolongation is fused into the first); one after the coarsest solve and one after the load.
+COARSE_BARRIER_PHASES = 4 * (2 * 2 + 1 + 2 * 2) + 1 + 1
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_down_mlmc5_mixed.md")
 KERNEL_SOURCES = ["rmg_smoother.hpp", "rmg_device.hpp", "rmg_internal.hpp"]
 
@@ -85,8 +99,9 @@ def build_levels(torch, rmg, W, precision, dev, max_picard):
 
 def build_vg_levels(torch, rmg, W, precision, dev, max_picard):
     """The van Genuchten workload: 5 levels 32^2..512^2 with 2048/512/128/32/8 pairs, three
-    KL fields (128 modes each), 50 steps of dt = 0.005, n shifted by (L - l) * 0.1 on level l
-    (the coarse member of a pair uses level l - 1's shift)."""
+    KL fields (128 modes each), the infiltration problem of eq. travellingwave with Ks_bl = 0.2,
+    50 steps of dt = 0.005, n shifted by (L - l) * 0.1 on level l (the coarse member of a pair
+    uses level l - 1's shift)."""
     from paper_1903_08741_amd import kl_setup
     cfg, vf, g = W.MLMC_VG, W.VG_FIELDS, W.VG_INFILTRATION
     grids = cfg["grids"]
@@ -98,7 +113,7 @@ def build_vg_levels(torch, rmg, W, precision, dev, max_picard):
     def prob(shift):
         return rmg.Problem(model=rmg.VGM, n_steps=g["n_steps"], theta_r=g["theta_r"], theta_s=g["theta_s"],
                            h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"], dt=g["dt"],
-                           vg_n_shift=shift)
+                           init_profile=1, init_rate=g["init_rate"], vg_n_shift=shift)
     levels = []
     for l, (n, S) in enumerate(zip(grids, cfg["samples"])):
         xi = torch.from_numpy(W.xi_draws(cfg["workload_id"], l, range(S), 3, vf["n_modes"])).to(dev)
@@ -151,16 +166,10 @@ def per_grid(torch, rmg, ctx, levels, opts, marg, only=None):
     return res
 
 
-def fp64_path(torch, rmg, ctx, levels, marg, max_picard, cycles, flags=0, steps=2):
+def fp64_path(torch, rmg, ctx, levels, marg, opts, steps=2):
     """The same workload with the multigrid in FP64 too (1 untimed call, `steps` timed)."""
-    opts = rmg.SolverOpts(precision=rmg.FP64, max_picard=max_picard, cycles_per_picard=cycles, flags=flags)
-    ctx.mlmc_level_estimate(levels, marg, opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        sums, _, _ = ctx.mlmc_level_estimate(levels, marg, opts)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
+    o = rmg.SolverOpts(**{**opts.__dict__, "precision": rmg.FP64})
+    ms, sums = timed_calls(torch, ctx, levels, marg, o, steps)
     failed = sum(s["n_failed"] for s in sums)
     log(f"fp64 path: {ms:.1f} ms per step, failed pairs {failed}")
     return ms, failed
@@ -196,29 +205,41 @@ def large_batch_roofline(torch, rmg, ctx, W, levels, marg):
 
 # ----------------------------------------------------------------- CPU baseline
 def _oracle_job(args):
-    """One oracle solve (twin mode: the same Picard / V-cycle iteration) of a workload sample."""
-    n, level, i, max_picard, cycles, Bn = args
+    """One oracle solve (twin mode: the same Picard / V-cycle iteration and fallback rule) of a
+    workload sample."""
+    n, level, i, sopts, Bn = args
     import workloads as W
     from oracle import kl as okl, picard as opicard
     f = W.KS_FIELD
     xi = W.xi_draws(W.MLMC_5LEVEL["workload_id"], level, [i], 1, f["n_modes"])[0, 0]
     Ks = okl.lognormal(okl.gaussian_field(xi, Bn), f["log_mean"], f["scale"]).reshape(n, n)
-    opts = dict(W.SOLVER, max_picard=max_picard, cycles_per_picard=cycles)
     t0 = time.perf_counter()
-    r = opicard.solve(dict(W.GARDNER_INFILTRATION), {"Ks": Ks}, n, opts, mode="mg")
+    r = opicard.solve(dict(W.GARDNER_INFILTRATION), {"Ks": Ks}, n, dict(W.SOLVER, **sopts), mode="mg")
     return n, time.perf_counter() - t0, sum(r["picard"]), r["status"]
 
 
-def cpu_baseline(max_picard, cycles, gpu_its_per_solve):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sopts, deadline_s=75.0):
     """Time the CPU oracle on a bounded sample of the workload, one solve per worker process.
 
-    Sample: the first draws of the fine member of each level, 32 solves on 16^2, 32 on
-    32^2, 16 on 64^2 and 8 on 128^2 (failing draws included, as in the workload).  The
-    full workload's oracle time is estimated per grid as (solves on that grid) x (mean
-    measured seconds per solve); 256^2 is not run (one solve takes up to minutes) and is
-    estimated from the 128^2 seconds per cell-iteration times the cell-iterations the GPU
-    run performed on 256^2.  Workers run in parallel, so the estimate is divided by the
-    worker count.
+    Sample: the first draws of the fine member of each level: 32 solves on 16^2, 32 on 32^2,
+    16 on 64^2, 8 on 128^2 and 4 on 256^2 (failing and retried draws included, with the
+    benchmark's solver settings and fallback rule).  Every grid's mean time per solve is
+    measured; the workload's oracle time is (solves per grid) x (mean time per solve), over
+    the worker count.  Solves still running at the deadline count with their elapsed time
+    (a lower bound on their time), which makes the reported CPU rate an upper bound.
+    Converged solves are counted on both sides (the GPU value counts solves of converged
+    pairs; the oracle's rate is solves per second).
     """
     import multiprocessing as mp
     import workloads as W
@@ -226,43 +247,52 @@ def cpu_baseline(max_picard, cycles, gpu_its_per_solve):
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
     f = W.KS_FIELD
     grids, samples = W.MLMC_5LEVEL["grids"], W.MLMC_5LEVEL["samples"]
-    run = {16: 32, 32: 32, 64: 16, 128: 8}
+    run = {16: 32, 32: 32, 64: 16, 128: 8, 256: 4}
     _, B = okl.basis(f["sigma2"], f["corr_len"], f["n_modes"], list(run), ref_n=64)
-    jobs = [(n, grids.index(n), i, max_picard, cycles, B[n]) for n in sorted(run, reverse=True)
-            for i in range(run[n])]
+    jobs = [(n, grids.index(n), i, sopts, B[n]) for n in sorted(run, reverse=True) for i in range(run[n])]
     env_threads = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
     t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(min(cores, len(jobs))) as pool:
-        res = list(pool.imap_unordered(_oracle_job, jobs, chunksize=1))
+    pool = mp.get_context("spawn").Pool(min(cores, len(jobs)))
+    pending = {k: (jobs[k][0], pool.apply_async(_oracle_job, (jobs[k],))) for k in range(len(jobs))}
+    per, unfinished = {}, {}
+    while pending and time.perf_counter() - t0 < deadline_s:
+        for k in list(pending):
+            n, ar = pending[k]
+            if ar.ready():
+                n_, t, its, st = ar.get()
+                per.setdefault(n_, []).append(t)
+                del pending[k]
+        time.sleep(0.2)
     wall = time.perf_counter() - t0
+    for k, (n, _) in pending.items():
+        unfinished[n] = unfinished.get(n, 0) + 1
+        per.setdefault(n, []).append(wall)  # lower bound of its time
+    pool.terminate()
+    pool.join()
     if env_threads is None:
         os.environ.pop("OMP_NUM_THREADS", None)
     else:
         os.environ["OMP_NUM_THREADS"] = env_threads
-    per = {}
-    for n, t, its, st in res:
-        per.setdefault(n, []).append((t, its))
     # solves per grid: the fine members of level l and the coarse members of level l + 1
     counts = {n: samples[l] + (samples[l + 1] if l + 1 < len(grids) else 0) for l, n in enumerate(grids)}
-    est = 0.0
-    for n, c in counts.items():
-        if n in per:
-            est += c * sum(t for t, _ in per[n]) / len(per[n])
-    nx = max(run)
-    sec_per_cell_it = sum(t for t, _ in per[nx]) / (sum(i for _, i in per[nx]) * nx * nx)
-    for n in counts:
-        if n not in per:
-            est += counts[n] * gpu_its_per_solve.get(n, 0.0) * n * n * sec_per_cell_it
+    est = sum(c * sum(per[n]) / len(per[n]) for n, c in counts.items())
     est_wall = est / cores
     total = sum(counts.values())
     desc = ", ".join(f"{run[n]}x{n}^2" for n in sorted(run))
+    note = ""
+    if unfinished:
+        note = ("; still running at the " + f"{deadline_s:.0f} s deadline: " +
+                ", ".join(f"{k} on {n}^2" for n, k in sorted(unfinished.items())) +
+                " (counted at their elapsed time, so the rate is an upper bound)")
     return {"value": total / est_wall, "unit": "sample solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(jobs)} oracle solves ({desc}; first draws of each level's fine member, "
-                      f"twin mode) in {wall:.1f}s wall on {min(cores, len(jobs))} processes; the "
-                      f"{total}-solve workload's time is estimated per grid from the measured mean "
-                      f"time per solve, 256^2 from the {nx}^2 time per cell-iteration and the GPU "
-                      "run's iteration counts on 256^2, divided by the worker count"}
+            "cpu_model": cpu_model(), "workers_cap": 16,
+            "per_grid_s_per_solve": {str(n): sum(v) / len(v) for n, v in sorted(per.items())},
+            "sample": f"{len(jobs)} oracle solves ({desc}; the first draws of each level's fine member, "
+                      f"twin mode with the benchmark's solver and fallback settings) in {wall:.1f}s wall on "
+                      f"{min(cores, len(jobs))} processes (one per core, at most 16); the {total}-solve "
+                      f"workload's time is the per-grid mean time per solve times the solves per grid, "
+                      f"divided by the worker count{note}"}
 
 
 # ------------------------------------------------------------ adjoint workload
@@ -331,7 +361,8 @@ def adjoint_bench(args, torch, rmg, W):
     # (dt times the outflux sensitivity), so 1e-13 converges them to ~1e-9 relative
     eps_adj = 1e-13
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
-    opts = rmg.SolverOpts(precision=precision, max_picard=args.max_picard)
+    opts = rmg.SolverOpts(precision=precision, max_picard=args.max_picard, fallback_cycles=args.fallback_cycles,
+                          fallback_max_picard=args.fallback_max_picard if args.fallback_cycles else 0)
     if args.no_autotune:
         opts.flags |= rmg.FLAG_NO_AUTOTUNE
     ctx = rmg.default_context(0)
@@ -365,7 +396,7 @@ def adjoint_bench(args, torch, rmg, W):
             "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
     extras = {}
     if not args.no_extras and precision == rmg.MIXED:
-        o64 = rmg.SolverOpts(precision=rmg.FP64, max_picard=args.max_picard)
+        o64 = rmg.SolverOpts(**{**opts.__dict__, "precision": rmg.FP64})
         call(o64)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -417,11 +448,10 @@ def pcmlmc_bench(args, torch, rmg, W):
 
     gardner (default): the Gardner problem of the MLMC workload on levels 16^2 .. 16 * 2^(L-1)
     with the exponent a as the continuation parameter, a_l = 1 - 0.1 (L - 1 - l);
-    vg: the van Genuchten fields of the vg workload on levels 32^2 .. 32 * 2^(L-1) with n shifted
-    by (L - 1 - l) * 0.1.  With one V(2,2) per Picard step to 1e-8 most van Genuchten pairs on
-    128^2 and finer exceed the iteration limit (the modified Picard iteration stalls as the
-    infiltration front steepens), so Algorithm 1 cannot reach its targets there: the draws per
-    level are capped (max_pairs) and the run then reports RMG_ENOTCONV."""
+    vg: the van Genuchten fields of the vg workload (infiltration problem of eq. travellingwave,
+    Ks_bl = 0.2) on levels 32^2 .. 32 * 2^(L-1) with n shifted by (L - 1 - l) * 0.1, 100 steps to
+    T = 0.25 (dt = 0.0025); the sampling tolerance is RMSE / sqrt(2), so that an eq. discErr bias
+    estimate below RMSE / sqrt(2) as well meets the RMSE target (eq. errMLMC)."""
     from paper_1903_08741_amd import _abi, kl_setup
     dev = torch.device("cuda:0")
     L = args.levels
@@ -432,18 +462,24 @@ def pcmlmc_bench(args, torch, rmg, W):
         _, tables = kl_setup.kl_tables(1.0, vf["corr_len"], vf["n_modes"], list(grids) + [grids[0] // 2])
         F, M, marg, wid = 3, vf["n_modes"], list(vf["marginals"]), cfg["workload_id"]
         warm = cfg["warmup"]
+        steps = args.time_steps or cfg["n_steps_full"]
+        dt = g["n_steps"] * g["dt"] / steps
+        eps = args.eps or args.rmse / 2 ** 0.5
 
         def prob(l):
-            return rmg.Problem(model=rmg.VGM, n_steps=args.time_steps, theta_r=g["theta_r"], theta_s=g["theta_s"],
-                               h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"], dt=g["dt"],
+            return rmg.Problem(model=rmg.VGM, n_steps=steps, theta_r=g["theta_r"], theta_s=g["theta_s"],
+                               h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"], dt=dt,
+                               init_profile=1, init_rate=g["init_rate"],
                                vg_n_shift=(L - 1 - l) * cfg["n_shift_grad"])
-        theta = f"n shifted by (L-1-l)*{cfg['n_shift_grad']}, {args.time_steps} steps dt={g['dt']}"
+        theta = (f"infiltration problem, n shifted by (L-1-l)*{cfg['n_shift_grad']}, {steps} steps dt={dt:g}, "
+                 f"RMSE target {args.rmse:g}")
     else:
         f, g = W.KS_FIELD, W.GARDNER_INFILTRATION
         grids = tuple(16 << l for l in range(L))
         _, tables = kl_setup.kl_tables(f["sigma2"], f["corr_len"], f["n_modes"], list(grids) + [8])
         F, M, marg, wid = 1, f["n_modes"], [(0.0, f["log_mean"], f["scale"])], 6
         warm = (64, 32, 16, 8, 8, 4)
+        eps = args.eps or 2e-3
 
         def prob(l):
             return rmg.Problem(model=rmg.GARDNER, n_steps=g["n_steps"], theta_r=g["theta_r"], theta_s=g["theta_s"],
@@ -464,8 +500,9 @@ def pcmlmc_bench(args, torch, rmg, W):
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
 
     def run(prec):
-        opts = rmg.SolverOpts(precision=prec, max_picard=args.max_picard)
-        return ctx.pc_mlmc(levels, marg, opts, args.eps, src, max_rounds=50, max_pairs=args.max_pairs)
+        opts = rmg.SolverOpts(precision=prec, max_picard=args.max_picard, fallback_cycles=args.fallback_cycles,
+                              fallback_max_picard=args.fallback_max_picard if args.fallback_cycles else 0)
+        return ctx.pc_mlmc(levels, marg, opts, eps, src, max_rounds=50, max_pairs=args.max_pairs)
     for i in range(args.warmup):
         run(precision)
         torch.cuda.synchronize()
@@ -482,7 +519,8 @@ def pcmlmc_bench(args, torch, rmg, W):
     gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
     solves = sum(x["drawn"] * (2 if l else 1) for l, x in enumerate(r["levels"]))
     lv = [{"grid": grids[l], "pairs_drawn": x["drawn"], "successful": x["sums"]["n"], "failed": x["sums"]["n_failed"],
-           "N_l": x["target"], "W_l": x["W"], "V_l": x["V"], "mean_Y": x["mean"]} for l, x in enumerate(r["levels"])]
+           "retried": x["sums"]["n_retried"], "N_l": x["target"], "W_l": x["W"], "V_l": x["V"], "mean_Y": x["mean"]}
+          for l, x in enumerate(r["levels"])]
     rmse = (r["bias"] ** 2 + r["sampling_err2"]) ** 0.5 if L > 1 else r["sampling_err2"] ** 0.5
     extras = {}
     if not args.no_extras and precision == rmg.MIXED:
@@ -500,7 +538,7 @@ def pcmlmc_bench(args, torch, rmg, W):
         "dtype": "f32 multigrid in f64 Picard" if precision == rmg.MIXED else "f64",
         "data": "synthetic (seeded KL fields)",
         "config": {"workload": f"PC_MLMC, {'van Genuchten-Mualem' if vg else 'Gardner'}, {L} levels "
-                               f"{grids[0]}^2..{grids[-1]}^2, {theta}, eps {args.eps:g}, work cost model, "
+                               f"{grids[0]}^2..{grids[-1]}^2, {theta}, eps {eps:g}, work cost model, "
                                f"V(2,2) per Picard, eps_PI 1e-8, at most {args.max_pairs} pairs per level",
                    "levels": lv, "rounds": r["rounds"], "calls": r["calls"], "solves": solves,
                    "converged": bool(r["converged"]), "rc": r["rc"], "precision": args.precision,
@@ -551,7 +589,9 @@ def pcmlmc_eps_sweep(args, torch, rmg, W):
 
         def src(level, first, count, L=L):
             return W.xi_draws(100 + L, level, range(first, first + count), 1, f["n_modes"])
-        opts = rmg.SolverOpts(precision=precision, max_picard=args.max_picard)
+        opts = rmg.SolverOpts(precision=precision, max_picard=args.max_picard,
+                              fallback_cycles=args.fallback_cycles,
+                              fallback_max_picard=args.fallback_max_picard if args.fallback_cycles else 0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = ctx.pc_mlmc(levels, marg, opts, eps, src, max_rounds=50, max_pairs=args.max_pairs)
@@ -653,17 +693,85 @@ def sweep_bench(args, torch, rmg, W):
     print(json.dumps(res), flush=True)
 
 
+def level_report(sums, levels):
+    """Per level: pairs, failed and retried pairs with their fractions, and the level mean."""
+    out = []
+    for l, (sm, lv) in enumerate(zip(sums, levels)):
+        S = int(lv["xi"].shape[0])
+        hi, lo = sm["sY"]
+        out.append({"level": l, "grid": lv["n_fine"], "pairs": S, "failed": sm["n_failed"],
+                    "failed_fraction": sm["n_failed"] / S, "retried": sm["n_retried"],
+                    "retried_fraction": sm["n_retried"] / S,
+                    "mean_Y": (hi + lo) / sm["n"] if sm["n"] else None, "picard_its": sm["picard_its"]})
+    return out
+
+
+def timed_calls(torch, ctx, levels, marg, opts, steps=1):
+    """One untimed call, then `steps` timed ones: (ms per call, level sums of the last)."""
+    ctx.mlmc_level_estimate(levels, marg, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sums, _, _ = ctx.mlmc_level_estimate(levels, marg, opts)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps, sums
+
+
+def solver_variants(torch, rmg, ctx, levels, marg, base, total):
+    """The same workload under other solver settings (outside the timed region): one V(2,2)
+    per Picard step without the fallback (failed pairs dropped), two V(2,2) per step, one
+    W(2,2) per step.  Converged solves per second and failures per level."""
+    out = []
+    for name, kw in (("V(2,2) x1, no fallback, limit 500", dict(cycles_per_picard=1, max_picard=500,
+                                                                 fallback_cycles=0, fallback_max_picard=0)),
+                     ("V(2,2) x2, no fallback, limit 500", dict(cycles_per_picard=2, max_picard=500,
+                                                                 fallback_cycles=0, fallback_max_picard=0)),
+                     ("W(2,2) x1, no fallback, limit 500", dict(cycle=rmg.CYCLE_W, cycles_per_picard=1,
+                                                                 max_picard=500, fallback_cycles=0,
+                                                                 fallback_max_picard=0))):
+        o = rmg.SolverOpts(**{**base.__dict__, **kw})
+        ms, sums = timed_calls(torch, ctx, levels, marg, o)
+        conv = sum(sm["n"] * (2 if lv["n_coarse"] else 1) for sm, lv in zip(sums, levels))
+        out.append({"solver": name, "ms_per_step": ms, "converged_solves": conv, "solves": total,
+                    "converged_solves_per_s": conv / (ms / 1e3),
+                    "failed_pairs_per_level": [sm["n_failed"] for sm in sums]})
+        log(f"variant {name}: {ms:.1f} ms, failed {[sm['n_failed'] for sm in sums]}")
+    return out
+
+
+def coarse_bound(kt, levels_visited_per_launch=None):
+    """Bound line of the one-workgroup-per-sample coarse cycle: level cells per second,
+    the LDS traffic of its access pattern against the LDS peak, and the time per barrier
+    phase (the kernel is a chain of short barrier-separated phases per sample)."""
+    if kt["total_ms"] <= 0 or kt["launches"] == 0:
+        return None
+    sec = kt["total_ms"] * 1e-3
+    cells_s = kt["cells"] / sec
+    lds_b = LDS_BYTES_PER_CELL_VISIT * kt["cells"]
+    return {"bound": "latency (LDS + barriers)", "kernel": "k_coarse_v (64^2 -> 4^2 cycle in LDS, one workgroup "
+                                                          "per sample)",
+            "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / kt["launches"],
+            "level_cells_per_s": cells_s, "lds_bytes_per_s_model": lds_b / sec,
+            "lds_peak_bytes_per_s": LDS_PEAK_BPS, "lds_frac": lds_b / sec / LDS_PEAK_BPS,
+            "lds_bytes_per_cell_visit_model": LDS_BYTES_PER_CELL_VISIT,
+            "barrier_phases_per_cycle": COARSE_BARRIER_PHASES}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=("gardner", "vg", "adjoint", "sweep", "pcmlmc"), default="gardner",
                     help="gardner: the 5-level Gardner MLMC workload (default); vg: the van Genuchten "
-                         "workload with three fields and continuation (5 levels 32^2..512^2); adjoint: "
-                         "outflux gradients of 1024 samples of 128^2 (100 KL modes, 20 steps); sweep: the "
-                         "alpha-n robustness sweep of the infiltration problem (25600 solves of 32^2)")
+                         "workload with three fields and continuation (5 levels 32^2..512^2, infiltration "
+                         "problem); adjoint: outflux gradients of 1024 samples of 128^2 (100 KL modes, 20 "
+                         "steps); sweep: the alpha-n robustness sweep of the infiltration problem (25600 "
+                         "solves of 32^2); pcmlmc: Algorithm 1")
     ap.add_argument("--levels", type=int, default=4, help="pcmlmc: number of levels (at most 6)")
-    ap.add_argument("--eps", type=float, default=2e-3, help="pcmlmc: sampling tolerance")
-    ap.add_argument("--time-steps", type=int, default=20, help="pcmlmc vg: backward-Euler steps (dt = 0.005)")
+    ap.add_argument("--eps", type=float, default=0.0,
+                    help="pcmlmc: sampling tolerance (default: 2e-3 for gardner; RMSE / sqrt(2) for vg)")
+    ap.add_argument("--rmse", type=float, default=1e-3, help="pcmlmc vg: target RMSE")
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="pcmlmc vg: backward-Euler steps to T = 0.25 (default 100)")
     ap.add_argument("--pc-model", choices=("gardner", "vg"), default="gardner", help="pcmlmc: hierarchy")
     ap.add_argument("--max-pairs", type=int, default=50000, help="pcmlmc: cap on the pairs drawn per level")
     ap.add_argument("--grid", type=int, default=0,
@@ -673,19 +781,25 @@ def main():
                     help="pcmlmc gardner: cost of Algorithm 1 against the tolerance, the finest grid refined "
                          "as eps halves (h_L ~ eps)")
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed calls first (the first calls of a workload tune tiles and the schedule)")
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
-    ap.add_argument("--max-picard", type=int, default=500)
-    ap.add_argument("--cycles", type=int, default=1, help="V(2,2) cycles per Picard iteration")
+    ap.add_argument("--max-picard", type=int, default=100, help="Picard iterations per step, first attempt")
+    ap.add_argument("--cycles", type=int, default=1, help="cycles per Picard iteration")
+    ap.add_argument("--cycle", choices=("V", "W"), default="V")
+    ap.add_argument("--fallback-cycles", type=int, default=2,
+                    help="cycles per Picard step of the fallback attempt of a failed sample (0: none)")
+    ap.add_argument("--fallback-max-picard", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--confine", choices=("default", "on", "off"), default="default",
-                    help="confine the classes of the batched call to parts of the compute units (flag bit 7); "
-                         "default: on for the gardner workload, off for vg")
+                    help="confine the classes of the batched call to parts of the compute units (on: flag "
+                         "bit 7, off: bit 8); default: the library's schedule tuner decides")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="32 x 32 streaming tiles on every level (profiling runs: timing under a counter "
-                         "profiler is distorted, so an autotuner could pick other tiles there)")
+                    help="32 x 32 streaming tiles on every level and no schedule tuning (profiling runs: "
+                         "timing under a counter profiler is distorted)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the per-grid, FP64-path and large-batch figures (outside the timed region)")
+                    help="skip the per-grid, FP64-path, solver-variant and large-batch figures (outside the "
+                         "timed region)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sample-parallel "
@@ -714,14 +828,15 @@ def main():
     build = build_vg_levels if vg else build_levels
     levels, opts, marg = build(torch, rmg, W, precision, dev, args.max_picard)
     opts.cycles_per_picard = args.cycles
+    opts.cycle = rmg.CYCLE_W if args.cycle == "W" else rmg.CYCLE_V
+    opts.fallback_cycles = args.fallback_cycles
+    opts.fallback_max_picard = args.fallback_max_picard if args.fallback_cycles else 0
     if args.no_autotune:
         opts.flags |= rmg.FLAG_NO_AUTOTUNE
-    # confine the whole-sample and the smaller streaming classes to parts of the GPU so
-    # that the largest grid's chain finds free compute units: measured to help on the
-    # Gardner workload (its 256^2 chain is the critical path), not on the vg workload
-    confine = args.confine == "on" or (args.confine == "default" and not vg)
-    if confine:
+    if args.confine == "on":
         opts.flags |= rmg.FLAG_CONFINE
+    elif args.confine == "off":
+        opts.flags |= rmg.FLAG_NO_CONFINE
     ctx = rmg.default_context(0)
     if args.grid:
         res = per_grid(torch, rmg, ctx, levels, opts, marg, only=args.grid)
@@ -744,7 +859,7 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.time() - t0:.3f}s rc={rc}")
     from paper_1903_08741_amd import _abi
-    ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN)
+    ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN | _abi.TIME_COARSE | _abi.TIME_FINE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -753,35 +868,52 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1000.0 * dt / args.steps
-    kt = ctx.kernel_timing()
+    kt = ctx.kernel_timing(_abi.TIME_SMOOTHER_DOWN)
+    kc = ctx.kernel_timing(_abi.TIME_COARSE)
+    kf = ctx.kernel_timing(_abi.TIME_FINE)
     ctx.set_kernel_timing(_abi.TIME_NONE)
     converged = sum(s["n"] * (2 if lv["n_coarse"] else 1) for s, lv in zip(sums, levels))
-    its_per_solve = {}
-    for s, lv in zip(sums, levels):
-        its_per_solve[lv["n_fine"]] = s["picard_its"] / (s["n"] + s["n_failed"]) / (2 if lv["n_coarse"] else 1)
-    for l, s in enumerate(sums):
-        log(f"level {l}: pairs {s['n']} failed {s['n_failed']} picard_its {s['picard_its']}")
+    per_level = level_report(sums, levels)
+    for r in per_level:
+        log(f"level {r['level']} ({r['grid']}^2): pairs {r['pairs']} failed {r['failed']} retried {r['retried']} "
+            f"picard_its {r['picard_its']}")
     failed = sum(s["n_failed"] for s in sums)
     picard = sum(s["picard_its"] for s in sums)
     gbs = kt["algo_bytes"] / (kt["total_ms"] * 1e-3) / 1e9 if kt["total_ms"] > 0 else 0.0
+    es = 4 if precision == rmg.MIXED else 8
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "traffic": None if vg else recorded_traffic(),
             "kernel": "k_down (nu1 fused red-black sweeps + residual + restriction, level-streaming path)",
+            "timing": "kernel execution time: each timed launch's event pair is recorded by its dispatch",
             "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
-            "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"])}
+            "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"]),
+            "compulsory_bytes_per_cell": 5.25 * es,
+            "sweep_model_bytes_per_cell": (2 * 20 + 17) * es / 4,
+            "frac_sweep_model": (gbs * (2 * 20 + 17) / 4 / 5.25) / HBM_PEAK_GBS}
+    roof_fine = None
+    if kf["total_ms"] > 0:
+        fg = kf["algo_bytes"] / (kf["total_ms"] * 1e-3) / 1e9
+        roof_fine = {"bound": "hbm", "kernel": "k_fine (FP64 outer residual, closure, level coefficients)",
+                     "achieved": fg, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fg / HBM_PEAK_GBS,
+                     "launches": kf["launches"], "avg_launch_us": 1e3 * kf["total_ms"] / kf["launches"],
+                     "cells_per_s": kf["cells"] / (kf["total_ms"] * 1e-3)}
     extras = {}
     if not args.no_extras and not vg:
         extras["per_grid"] = per_grid(torch, rmg, ctx, levels, opts, marg)
         if precision == rmg.MIXED:
-            fms, ffail = fp64_path(torch, rmg, ctx, levels, marg, args.max_picard, args.cycles,
-                                     opts.flags & rmg.FLAG_CONFINE)
+            fms, ffail = fp64_path(torch, rmg, ctx, levels, marg, opts)
             extras["fp64_path"] = {"ms_per_step": fms, "failed_pairs": ffail, "mixed_speedup": fms / ms}
+        extras["solver_variants"] = solver_variants(torch, rmg, ctx, levels, marg, opts, total)
         extras["roofline_large_batch"] = large_batch_roofline(torch, rmg, ctx, W, levels, marg)
     cpu = None
     if not args.no_cpu_baseline and not vg:
         t1 = time.time()
-        cpu = cpu_baseline(args.max_picard, args.cycles, its_per_solve)
+        cpu = cpu_baseline(dict(max_picard=args.max_picard, cycles_per_picard=args.cycles,
+                                cycle=args.cycle, fallback_cycles=args.fallback_cycles,
+                                fallback_max_picard=args.fallback_max_picard))
         log(f"cpu baseline {time.time() - t1:.1f}s")
+    fb = (f", failed samples restarted with {args.fallback_cycles} {args.cycle}(2,2) per Picard step "
+          f"(limit {args.fallback_max_picard})" if args.fallback_cycles else "")
     out = {
         "metric": METRIC,
         "value": converged / (ms / 1000.0),
@@ -797,17 +929,23 @@ def main():
         "data": ("synthetic (seeded KL fields: lognormal Ks, alpha, 1 + lognormal n)" if vg
                  else "synthetic (seeded KL lognormal Ks fields)"),
         "config": {"workload": ("mlmc 5 levels 32^2..512^2, 2048/512/128/32/8 samples, van Genuchten-Mualem "
-                                "with 3 KL fields (128 modes), n shifted by (L-l)*0.1, 50 steps dt=0.005, "
-                                "V(2,2) per Picard, eps 1e-8" if vg else
+                                "with 3 KL fields (128 modes), infiltration problem (eq. travellingwave, "
+                                "Ks_bl 0.2), n shifted by (L-l)*0.1, 50 steps dt=0.005, "
+                                f"{args.cycle}(2,2) x{args.cycles} per Picard, eps 1e-8" if vg else
                                 "mlmc 5 levels 16^2..256^2, 4096/1024/256/64/16 samples, Gardner, "
-                                "10 steps dt=0.01, V(2,2) per Picard, eps 1e-8"),
+                                f"10 steps dt=0.01, {args.cycle}(2,2) x{args.cycles} per Picard, eps 1e-8, "
+                                f"limit {args.max_picard}") + fb,
                    "solves_per_step": total, "converged_solves_per_step": converged,
                    "cells_per_step": sum(lv["xi"].shape[0] * (lv["n_fine"] ** 2 + lv["n_coarse"] ** 2)
                                          for lv in levels),
-                   "failed_pairs": failed,
+                   "failed_pairs": failed, "retried_pairs": sum(s["n_retried"] for s in sums),
+                   "levels": per_level,
                    "picard_iterations_per_step": picard, "precision": args.precision,
-                   "cycles_per_picard": args.cycles, "max_picard": args.max_picard, "confined": confine},
+                   "cycles_per_picard": args.cycles, "max_picard": args.max_picard,
+                   "fallback_cycles": args.fallback_cycles, "confine": args.confine},
         "roofline": roof,
+        "roofline_coarse": coarse_bound(kc),
+        "roofline_fine": roof_fine,
         "cpu_baseline": cpu,
     }
     out.update(extras)

@@ -121,7 +121,17 @@ typedef struct {
                                  the whole-sample classes to a quarter of the compute units and the
                                  streaming classes other than the largest grid to three quarters, so
                                  that the largest grid's chain of short launches finds free units
-                                 (helps when that chain is the critical path; results are identical) */
+                                 (helps when that chain is the critical path; results are identical);
+                                 bit 8: mlmc_level_estimate: never confine (overrides bit 7 and the
+                                 context's schedule tuning) */
+  int32_t fallback_cycles;    /* 0: none.  1..16: a sample that fails (iteration limit or non-finite
+                                 correction) restarts from its initial state with this many cycles per
+                                 Picard step and fallback_max_picard iterations per step; it fails only
+                                 if that attempt fails too.  Needs cycles_per_picard >= 1.  The
+                                 one-V-cycle modified Picard iteration stalls or oscillates on some
+                                 draws where two cycles per step converge; without a fallback such
+                                 samples are excluded from the level sums, which biases them. */
+  int32_t fallback_max_picard;/* Picard iterations per step of the fallback attempt, >= 1 */
   double eps_mg;              /* residual tolerance of cycles_per_picard = 0 (Section 4.2: 1e-5) */
   double eps_picard;          /* stop when ||dp||_inf < eps_picard (strict) */
 } rmg_solver_opts;
@@ -133,6 +143,9 @@ typedef struct {
   int32_t steps_done;   /* time steps completed */
   int32_t status;       /* rmg_sample_status */
   double final_dp_inf;  /* ||dp||_inf of the last Picard iteration */
+  int32_t attempts;     /* 1, or 2 when the sample restarted with the fallback setting (the
+                           counts above then cover both attempts) */
+  int32_t reserved;
 } rmg_sample_stats;
 
 /* Compensated (Neumaier) double-double sum: value = hi + lo. */
@@ -147,6 +160,7 @@ typedef struct {
   int64_t picard_its;           /* Picard iterations of both members of every pair, failed included */
   int64_t mg_cycles;            /* multigrid cycles, likewise */
   int64_t mg_cycles_coarse;     /* the part of mg_cycles spent by the coarse members */
+  int64_t n_retried;            /* pairs with a member that needed the fallback attempt (failed or not) */
   rmg_dd sY, sY2, sQf, sQf2, sQc, sQc2;
 } rmg_level_sums;
 
@@ -170,34 +184,60 @@ typedef struct {
  * unknown; lets bindings check their struct layouts against this build. */
 int64_t rmg_struct_size(const char* name);
 
-/* Kernel timing (diagnostics; used by the benchmark to price the smoother
- * against HBM bandwidth).  RMG_TIME_SMOOTHER_DOWN brackets the launches of the
- * level-streaming down-leg kernel (nu1 fused red-black sweeps + residual +
- * restriction, Section 4.2) with HIP events on the stream they run on, and counts
- * the fine cells those launches processed.  The streaming solver advances in
- * batches of eight Picard iterations; the first iteration of a timed batch is
- * launched eagerly and timed, the other iterations replay HIP graphs (events
- * recorded inside a graph cannot be timed).  Grid-size classes with fewer than
- * 2^22 cells per iteration time every eighth batch, larger ones every batch, so
- * the totals cover a uniform one-in-64 (one-in-8) sample of the launches.
- * Results do not depend on timing.  Algorithmic bytes per processed cell
- * (each array touched once): read f, the two face coefficients and C/dt, write
- * the iterate and a quarter of a coarse right-hand side (5.25 elements), plus
- * one element when the initial iterate is loaded rather than zero. */
-typedef enum { RMG_TIME_NONE = 0, RMG_TIME_SMOOTHER_DOWN = 1 } rmg_timed_kernel;
+/* Kernel timing (diagnostics; used by the benchmark to price the kernels against the
+ * hardware).  The selected kinds of level-streaming launches are timed with an event
+ * pair that the kernel's dispatch itself records (hipExtLaunchKernelGGL), so a pair
+ * brackets the kernel's execution on the device, not the queue time before it; the
+ * library also counts the work those launches did.  The streaming solver advances in
+ * batches of eight passes (a replayed HIP graph); the first pass of a timed batch is
+ * launched eagerly and timed (events of graph nodes cannot be timed).  Grid-size
+ * classes with fewer than 2^22 cells per pass time every eighth batch, larger ones
+ * every batch, so the totals cover a uniform one-in-64 (one-in-8) sample of the
+ * launches.  Results do not depend on timing.
+ *   RMG_TIME_SMOOTHER_DOWN: the down leg (nu1 fused red-black sweeps + residual +
+ *     restriction, Section 4.2).  units = fine cells processed; algorithmic bytes per
+ *     cell (each array touched once): read f, the two face coefficients and C/dt, write
+ *     the iterate and a quarter of a coarse right-hand side (5.25 elements), plus one
+ *     element when the initial iterate is loaded rather than zero.
+ *   RMG_TIME_COARSE: the one-workgroup-per-sample coarse cycle in LDS (and the fused
+ *     fine + coarse launch of a 64 x 64 class).  units = level cells the launches
+ *     visited (every level of the in-LDS hierarchy, W-cycles counting repeated visits);
+ *     algorithmic bytes = HBM bytes: the top level's f, faces, C/dt in and the
+ *     correction out (5 elements per top-level cell).
+ *   RMG_TIME_FINE: the fine kernel (FP64 outer residual, closure, fine and in-tile
+ *     coarse coefficients, Section 4.1).  units = fine cells; algorithmic bytes per cell:
+ *     read p, theta^n and the fields (8 (2 + F) bytes), write f, two faces and C/dt of
+ *     the finest level and of the coarser levels formed in the tile (4 elements x 4/3). */
+typedef enum {
+  RMG_TIME_NONE = 0,
+  RMG_TIME_SMOOTHER_DOWN = 1,
+  RMG_TIME_COARSE = 2,
+  RMG_TIME_FINE = 4
+} rmg_timed_kernel;
 typedef struct {
   int64_t launches;     /* timed launches */
-  int64_t cells;        /* fine cells processed by them */
-  double total_ms;      /* summed event-measured launch durations */
-  double algo_bytes;    /* algorithmic bytes of those launches */
+  int64_t cells;        /* work units of those launches (see rmg_timed_kernel) */
+  double total_ms;      /* summed durations of those launches on the device */
+  double algo_bytes;    /* algorithmic HBM bytes of those launches */
 } rmg_kernel_timing;
-/* Select the timed kernel (RMG_TIME_NONE disables timing) and reset the totals. */
+/* Select the timed kinds (a bit mask of rmg_timed_kernel; 0 disables timing) and reset
+ * the totals. */
 int rmg_set_kernel_timing(rmg_ctx* ctx, int which);
-/* Totals since the last rmg_set_kernel_timing (synchronises the device). */
-int rmg_get_kernel_timing(rmg_ctx* ctx, rmg_kernel_timing* out);
+/* Totals of one kind (a single rmg_timed_kernel bit) since the last
+ * rmg_set_kernel_timing (synchronises the device). */
+int rmg_get_kernel_timing(rmg_ctx* ctx, int kind, rmg_kernel_timing* out);
 
-/* Create a context on HIP device `hip_device`; *out receives it. */
-int rmg_ctx_create(rmg_ctx** out, int hip_device);
+/* Create a context on HIP device `hip_device`; *out receives it.
+ * tune_cache_path (nullable): a text file holding the autotuner's choices (streaming
+ * tile edges per grid-size class signature, the schedule per batched-call signature),
+ * keyed also by the device's architecture and compute-unit count.  It is read here if
+ * it exists and rewritten whenever the context makes a new choice, so a later process
+ * starts tuned; choices never change results.  NULL: tune in memory only. */
+int rmg_ctx_create(rmg_ctx** out, int hip_device, const char* tune_cache_path);
+/* Cap the context's workspace at `bytes` (0: no cap).  A call whose workspace would
+ * exceed the cap returns RMG_ENOMEM without allocating (a workspace already held above
+ * a new cap is released by the next call that needs to grow it). */
+int rmg_ctx_set_workspace_limit(rmg_ctx* ctx, int64_t bytes);
 /* Release the context and its workspace (waits for its device to be idle). */
 void rmg_ctx_destroy(rmg_ctx* ctx);
 /* Text of the last error on this context ("" if none); valid until the next call. */

@@ -20,9 +20,9 @@ from dataclasses import dataclass, field, fields as dc_fields
 
 from . import _abi
 from ._abi import (COST_TIME, COST_WORK, CYCLE_V, CYCLE_W, FLAG_COARSE_TOP_32, FLAG_CONFINE, FLAG_EAGER, FLAG_FORCE_STREAMING, FLAG_NO_AUTOTUNE,  # noqa: F401
-                   FLAG_STATE_GLOBAL, FLAG_TILES_16, FLAG_WHOLE_WHERE_FITS, FP64, GARDNER, LINEAR, MIXED,
-                   QOI_MEAN_SATURATION, RMG_ENOTCONV, RMG_OK, SAMPLE_MAXITER, SAMPLE_NONFINITE,
-                   SAMPLE_OK, VGM)
+                   FLAG_NO_CONFINE, FLAG_STATE_GLOBAL, FLAG_TILES_16, FLAG_WHOLE_WHERE_FITS, FP64, GARDNER, LINEAR,
+                   MIXED, QOI_MEAN_SATURATION, RMG_EINVAL, RMG_ENOMEM, RMG_ENOTCONV, RMG_OK, SAMPLE_MAXITER,
+                   SAMPLE_NONFINITE, SAMPLE_OK, TIME_COARSE, TIME_FINE, TIME_NONE, TIME_SMOOTHER_DOWN, VGM)
 
 __all__ = ["Problem", "SolverOpts", "Context", "RmgError", "sample_fields", "picard_mg_solve",
            "mlmc_level_estimate", "pc_mlmc", "optimal_samples", "picard_mg_adjoint", "outflux_qoi",
@@ -73,6 +73,8 @@ class SolverOpts:
     max_picard: int = 100
     coarsest_n: int = 4
     flags: int = 0
+    fallback_cycles: int = 0
+    fallback_max_picard: int = 0
     eps_mg: float = 1e-5
     eps_picard: float = 1e-8
 
@@ -106,14 +108,19 @@ def _check_dev(t, name, dtype=None, shape=None):
 class Context:
     """An rmg_ctx on one HIP device (owns the workspace)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache: str | None = None):
+        """tune_cache: optional file that persists the autotuner's choices across processes."""
         self._lib = _abi.lib()
         h = C.c_void_p()
-        rc = self._lib.rmg_ctx_create(C.byref(h), int(device))
+        rc = self._lib.rmg_ctx_create(C.byref(h), int(device), tune_cache.encode() if tune_cache else None)
         if rc != RMG_OK:
             raise RmgError(rc, f"rmg_ctx_create(device={device}) failed")
         self._h = h
         self.device = device
+
+    def set_workspace_limit(self, nbytes: int):
+        """Cap the context's workspace (0: no cap); calls that would exceed it raise RMG_ENOMEM."""
+        self._raise(self._lib.rmg_ctx_set_workspace_limit(self._h, int(nbytes)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -132,13 +139,13 @@ class Context:
         raise RmgError(rc, self._lib.rmg_last_error(self._h).decode())
 
     def set_kernel_timing(self, which: int):
-        """Time every launch of the selected kernel class (``_abi.TIME_*``) and reset the totals."""
+        """Time the launches of the selected kernel kinds (a mask of ``TIME_*``) and reset the totals."""
         self._raise(self._lib.rmg_set_kernel_timing(self._h, int(which)))
 
-    def kernel_timing(self) -> dict:
-        """Totals since set_kernel_timing: launches, cells, total_ms, algo_bytes."""
+    def kernel_timing(self, kind: int = TIME_SMOOTHER_DOWN) -> dict:
+        """Totals of one kind since set_kernel_timing: launches, cells (work units), total_ms, algo_bytes."""
         t = _abi.KernelTiming()
-        self._raise(self._lib.rmg_get_kernel_timing(self._h, C.byref(t)))
+        self._raise(self._lib.rmg_get_kernel_timing(self._h, int(kind), C.byref(t)))
         return {k: getattr(t, k) for k in ("launches", "cells", "total_ms", "algo_bytes")}
 
     # -- entry points ----------------------------------------------------------
@@ -296,7 +303,7 @@ class Context:
 
 
 def _decode_sums(s) -> dict:
-    d = {k: getattr(s, k) for k in ("n", "n_failed", "picard_its", "mg_cycles", "mg_cycles_coarse")}
+    d = {k: getattr(s, k) for k in ("n", "n_failed", "picard_its", "mg_cycles", "mg_cycles_coarse", "n_retried")}
     for k in ("sY", "sY2", "sQf", "sQf2", "sQc", "sQc2"):
         v = getattr(s, k)
         d[k] = (v.hi, v.lo)
@@ -317,7 +324,7 @@ def _decode_stats(raw):
     import numpy as np
     a = raw.cpu().numpy()
     dt = np.dtype([("picard_its", "<i4"), ("mg_cycles", "<i4"), ("steps_done", "<i4"), ("status", "<i4"),
-                   ("final_dp_inf", "<f8")])
+                   ("final_dp_inf", "<f8"), ("attempts", "<i4"), ("reserved", "<i4")])
     return a.view(dt).reshape(-1)
 
 

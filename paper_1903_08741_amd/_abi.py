@@ -25,12 +25,14 @@ FLAG_TILES_16 = 16
 FLAG_WHOLE_WHERE_FITS = 32
 FLAG_COARSE_TOP_32 = 64
 FLAG_CONFINE = 128
+FLAG_NO_CONFINE = 256
 
 COST_WORK, COST_TIME = 0, 1
 
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
-            "sample_fields", "picard_mg_solve", "mlmc_level_estimate", "rmg_set_kernel_timing",
-            "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples", "picard_mg_adjoint")
+            "rmg_ctx_set_workspace_limit", "sample_fields", "picard_mg_solve", "mlmc_level_estimate",
+            "rmg_set_kernel_timing", "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples",
+            "picard_mg_adjoint")
 
 
 class Marginal(C.Structure):
@@ -48,12 +50,14 @@ class Problem(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("cycle", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("cycles_per_picard", C.c_int32), ("max_picard", C.c_int32), ("coarsest_n", C.c_int32),
-                ("flags", C.c_int32), ("eps_mg", C.c_double), ("eps_picard", C.c_double)]
+                ("flags", C.c_int32), ("fallback_cycles", C.c_int32), ("fallback_max_picard", C.c_int32),
+                ("eps_mg", C.c_double), ("eps_picard", C.c_double)]
 
 
 class SampleStats(C.Structure):
     _fields_ = [("picard_its", C.c_int32), ("mg_cycles", C.c_int32), ("steps_done", C.c_int32),
-                ("status", C.c_int32), ("final_dp_inf", C.c_double)]
+                ("status", C.c_int32), ("final_dp_inf", C.c_double), ("attempts", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class DD(C.Structure):
@@ -62,7 +66,8 @@ class DD(C.Structure):
 
 class LevelSums(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_failed", C.c_int64), ("picard_its", C.c_int64),
-                ("mg_cycles", C.c_int64), ("mg_cycles_coarse", C.c_int64), ("sY", DD), ("sY2", DD), ("sQf", DD), ("sQf2", DD),
+                ("mg_cycles", C.c_int64), ("mg_cycles_coarse", C.c_int64), ("n_retried", C.c_int64),
+                ("sY", DD), ("sY2", DD), ("sQf", DD), ("sQf2", DD),
                 ("sQc", DD), ("sQc2", DD)]
 
 
@@ -103,7 +108,7 @@ class KernelTiming(C.Structure):
                 ("algo_bytes", C.c_double)]
 
 
-TIME_NONE, TIME_SMOOTHER_DOWN = 0, 1
+TIME_NONE, TIME_SMOOTHER_DOWN, TIME_COARSE, TIME_FINE = 0, 1, 2, 4
 
 STRUCTS = {"rmg_kernel_timing": KernelTiming, "rmg_problem": Problem, "rmg_solver_opts": SolverOpts, "rmg_sample_stats": SampleStats,
            "rmg_level_sums": LevelSums, "rmg_level": Level, "rmg_marginal": Marginal,
@@ -125,8 +130,10 @@ def lib():
     vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
     L.rmg_struct_size.argtypes = [C.c_char_p]
     L.rmg_struct_size.restype = i64
-    L.rmg_ctx_create.argtypes = [C.POINTER(vp), i32]
+    L.rmg_ctx_create.argtypes = [C.POINTER(vp), i32, C.c_char_p]
     L.rmg_ctx_create.restype = i32
+    L.rmg_ctx_set_workspace_limit.argtypes = [vp, i64]
+    L.rmg_ctx_set_workspace_limit.restype = i32
     L.rmg_ctx_destroy.argtypes = [vp]
     L.rmg_ctx_destroy.restype = None
     L.rmg_last_error.argtypes = [vp]
@@ -150,7 +157,7 @@ def lib():
     L.rmg_mlmc_optimal_samples.restype = i32
     L.rmg_set_kernel_timing.argtypes = [vp, i32]
     L.rmg_set_kernel_timing.restype = i32
-    L.rmg_get_kernel_timing.argtypes = [vp, C.POINTER(KernelTiming)]
+    L.rmg_get_kernel_timing.argtypes = [vp, i32, C.POINTER(KernelTiming)]
     L.rmg_get_kernel_timing.restype = i32
     for name, cls in STRUCTS.items():
         got = L.rmg_struct_size(name.encode())

@@ -329,6 +329,10 @@ __global__ void k_adj_init(SolveArgs a, StreamPlan pl, AdjArgs ad, const int32_t
     z.final_dp = 0.0;
     z.pend = 0;
     z.fresh = 0;
+    z.cpp = a.cpp;
+    z.cyc0 = 0;
+    z.jpass = 0;
+    z.attempt = 0;
     pl.state[s] = z;
     pl.dpmax[s] = 0ull;
   }
@@ -390,6 +394,8 @@ __global__ void k_adj_finish(SolveArgs a, StreamPlan pl, AdjArgs ad, const int32
     o.steps_done = P.n_steps - (st.status == RMG_SAMPLE_OK ? 0 : st.step);
     o.status = st.status;
     o.final_dp_inf = st.final_dp;
+    o.attempts = 1;
+    o.reserved = 0;
     stats[s] = o;
   }
 }

@@ -98,14 +98,15 @@ __global__ __launch_bounds__(kSumThreads) void k_level_sums(const double* qf, co
                                                             const rmg_sample_stats* sf,
                                                             const rmg_sample_stats* sc, rmg_level_sums* out) {
   __shared__ Neu part[6][kSumThreads];
-  __shared__ long long cnt[5][kSumThreads];
+  __shared__ long long cnt[6][kSumThreads];
   Neu acc[6];
   for (int k = 0; k < 6; ++k) acc[k] = Neu{0.0, 0.0};
-  long long ok = 0, bad = 0, its = 0, cyc = 0, cyc_c = 0;
+  long long ok = 0, bad = 0, its = 0, cyc = 0, cyc_c = 0, retried = 0;
   for (int64_t i = threadIdx.x; i < n; i += kSumThreads) {
     its += sf[i].picard_its + (sc ? sc[i].picard_its : 0);
     cyc += sf[i].mg_cycles + (sc ? sc[i].mg_cycles : 0);
     cyc_c += sc ? sc[i].mg_cycles : 0;
+    retried += (sf[i].attempts > 1 || (sc && sc[i].attempts > 1)) ? 1 : 0;
     const bool good = stf[i] == RMG_SAMPLE_OK && (!stc || stc[i] == RMG_SAMPLE_OK);
     if (!good) {
       ++bad;
@@ -126,14 +127,15 @@ __global__ __launch_bounds__(kSumThreads) void k_level_sums(const double* qf, co
   cnt[2][threadIdx.x] = its;
   cnt[3][threadIdx.x] = cyc;
   cnt[4][threadIdx.x] = cyc_c;
+  cnt[5][threadIdx.x] = retried;
   __syncthreads();
   if (threadIdx.x != 0) return;
   Neu tot[6];
-  long long c5[5] = {0, 0, 0, 0, 0};
+  long long c5[6] = {0, 0, 0, 0, 0, 0};
   for (int k = 0; k < 6; ++k) tot[k] = Neu{0.0, 0.0};
   for (int t = 0; t < kSumThreads; ++t) {
     for (int k = 0; k < 6; ++k) dd_acc(tot[k], part[k][t]);
-    for (int k = 0; k < 5; ++k) c5[k] += cnt[k][t];
+    for (int k = 0; k < 6; ++k) c5[k] += cnt[k][t];
   }
   rmg_level_sums o;
   o.n = c5[0];
@@ -141,6 +143,7 @@ __global__ __launch_bounds__(kSumThreads) void k_level_sums(const double* qf, co
   o.picard_its = c5[2];
   o.mg_cycles = c5[3];
   o.mg_cycles_coarse = c5[4];
+  o.n_retried = c5[5];
   rmg_dd* dst[6] = {&o.sY, &o.sY2, &o.sQf, &o.sQf2, &o.sQc, &o.sQc2};
   for (int k = 0; k < 6; ++k) {
     // renormalise: hi = fl(s + c), lo = the rounding error of that sum

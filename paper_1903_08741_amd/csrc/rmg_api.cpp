@@ -10,8 +10,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <new>
+#include <sstream>
 #include <string>
 #include <thread>
 #include <vector>
@@ -22,7 +24,7 @@
 
 using namespace rmg;
 
-constexpr int kTimerPairs = 4096;
+constexpr int kTimerPairs = 1024;  // event pairs per timed kind and class
 // Share of the compute units (whole XCDs of 32) the whole-sample classes of a batched
 // MLMC call may use while level-streaming classes run beside them: a whole-sample
 // workgroup holds its compute unit for milliseconds, and a streaming kernel's
@@ -49,10 +51,19 @@ constexpr int kTimerPairs = 4096;
 // Largest grid solved by the whole-sample kernel (one workgroup per sample).
 constexpr int kWholeMaxN = RMG_WHOLE_MAX_N;
 
+// What a timed class's work counters mean in bytes and cells (see rmg_timed_kernel).
+struct TimerMeta {
+  int es = 4;                    // bytes per smoother-precision element
+  double coarse_cells = 0.0;     // level cells one coarse-kernel cycle of a sample visits
+  double coarse_bytes = 0.0;     // HBM bytes of that cycle
+  double fine_bytes = 0.0;       // HBM bytes per fine-kernel cell
+};
+
 struct rmg_ctx {
   int device = 0;
   void* ws = nullptr;
   size_t ws_cap = 0;
+  size_t ws_limit = 0;         // 0: no cap
   int32_t* h_count = nullptr;  // pinned host mirror of the active-sample counters
   hipStream_t side[8] = {};
   hipEvent_t ev[8] = {};
@@ -60,11 +71,17 @@ struct rmg_ctx {
   hipEvent_t pev[16][4] = {};
   // one timer per concurrently running class (each on its own stream)
   KernelTimer timers[8] = {};
-  int timer_es[8] = {};
-  unsigned long long* d_tcells = nullptr;  // 8 x 2 counters
+  TimerMeta tmeta[8] = {};
+  unsigned long long* d_tcells = nullptr;  // 8 x kTimerCounters counters
   int timing = 0;
-  // autotuner: tile edges (level 0, coarser streaming levels) per class signature
-  std::map<std::string, std::pair<int, int>> tune;
+  // autotuner choices by key (device-qualified): streaming tile edges per class
+  // signature ("t0 t1"), the schedule of a batched call signature ("confine G")
+  std::map<std::string, std::string> tune;
+  std::string tune_path;   // persisted here when non-empty
+  std::string dev_key;     // architecture and compute units of the device
+  // schedule tuning in progress: call signature -> measured wall ms per candidate
+  std::map<std::string, std::vector<double>> sched_trials;
+  bool tuned_now = false;  // a class's tiles were tuned during the current call
   hipEvent_t tev[2] = {};
   // set-up of each streaming class done (the whole-sample launches wait for them)
   hipEvent_t iev[16] = {};
@@ -117,14 +134,18 @@ struct Arena {
 };
 
 int reserve(rmg_ctx* ctx, size_t bytes) {
-  if (bytes <= ctx->ws_cap) return RMG_OK;
+  if (bytes <= ctx->ws_cap && (ctx->ws_limit == 0 || ctx->ws_cap <= ctx->ws_limit)) return RMG_OK;
+  if (ctx->ws_limit && bytes > ctx->ws_limit)
+    return fail(ctx, RMG_ENOMEM, "workspace of %zu bytes needed, above the context's limit of %zu bytes", bytes,
+                ctx->ws_limit);
   if (ctx->ws) {
     (void)hipDeviceSynchronize();
     (void)hipFree(ctx->ws);
     ctx->ws = nullptr;
     ctx->ws_cap = 0;
   }
-  const size_t want = bytes + bytes / 8 + (1 << 20);
+  size_t want = bytes + bytes / 8 + (1 << 20);
+  if (ctx->ws_limit && want > ctx->ws_limit) want = ctx->ws_limit;
   if (hipMalloc(&ctx->ws, want) != hipSuccess) {
     ctx->ws = nullptr;
     return fail(ctx, RMG_ENOMEM, "workspace allocation of %zu bytes failed", want);
@@ -163,6 +184,10 @@ int check_opts(rmg_ctx* ctx, const rmg_solver_opts* o, int n) {
   if (!(o->eps_picard > 0.0)) return fail(ctx, RMG_EINVAL, "eps_picard must be > 0");
   if (o->coarsest_n != 2 && o->coarsest_n != 4)
     return fail(ctx, RMG_EINVAL, "coarsest_n must be 2 or 4");
+  if (o->fallback_cycles < 0 || o->fallback_cycles > 16)
+    return fail(ctx, RMG_EINVAL, "fallback_cycles must be in 0..16");
+  if (o->fallback_cycles > 0 && (o->cycles_per_picard == 0 || o->fallback_max_picard < 1))
+    return fail(ctx, RMG_EINVAL, "a fallback needs cycles_per_picard >= 1 and fallback_max_picard >= 1");
   if (n < o->coarsest_n) return fail(ctx, RMG_EINVAL, "n=%d below coarsest_n=%d", n, o->coarsest_n);
   return RMG_OK;
 }
@@ -218,6 +243,8 @@ void class_carve(ClassJob& j, Arena& ar) {
 
 void class_plan(ClassJob& j, const rmg_solver_opts* o) {
   j.fp64 = o->precision == RMG_FP64;
+  j.a.fb_cpp = o->fallback_cycles;
+  j.a.fb_max_picard = o->fallback_cycles > 0 ? o->fallback_max_picard : 0;
   const int n = j.a.n;
   j.whole = !(o->flags & 1) && (n <= kWholeMaxN || (o->flags & 32)) &&
             whole_sample_lds_bytes(n, o->coarsest_n, j.fp64, j.a.F, nullptr) > 0;
@@ -231,10 +258,45 @@ void class_plan(ClassJob& j, const rmg_solver_opts* o) {
 }
 
 std::string tune_key(const ClassJob& j) {
-  char b[160];
-  snprintf(b, sizeof b, "n=%d S=%lld fp64=%d nu=%d,%d cpp=%d F=%d", j.a.n, (long long)j.a.S, (int)j.fp64,
-           j.a.nu1, j.a.nu2, j.a.cpp, j.a.F);
+  char b[192];
+  snprintf(b, sizeof b, "tiles n=%d S=%lld fp64=%d nu=%d,%d cpp=%d fb=%d F=%d g=%d", j.a.n, (long long)j.a.S,
+           (int)j.fp64, j.a.nu1, j.a.nu2, j.a.cpp, j.a.fb_cpp, j.a.F, j.a.gamma);
   return b;
+}
+
+// The tune cache file: one "key<TAB>value" line per choice, keys qualified by the device.
+void load_tune_cache(rmg_ctx* ctx) {
+  if (ctx->tune_path.empty()) return;
+  std::ifstream in(ctx->tune_path);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t t = line.find('\t');
+    if (t == std::string::npos) continue;
+    ctx->tune[line.substr(0, t)] = line.substr(t + 1);
+  }
+}
+
+void save_tune_cache(const rmg_ctx* ctx) {
+  if (ctx->tune_path.empty()) return;
+  const std::string tmp = ctx->tune_path + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return;  // an unwritable cache only costs tuning time in later processes
+    for (const auto& kv : ctx->tune) out << kv.first << '\t' << kv.second << '\n';
+  }
+  (void)std::rename(tmp.c_str(), ctx->tune_path.c_str());
+}
+
+bool tune_get(const rmg_ctx* ctx, const std::string& key, std::string* val) {
+  auto it = ctx->tune.find(ctx->dev_key + " " + key);
+  if (it == ctx->tune.end()) return false;
+  *val = it->second;
+  return true;
+}
+
+void tune_put(rmg_ctx* ctx, const std::string& key, const std::string& val) {
+  ctx->tune[ctx->dev_key + " " + key] = val;
+  save_tune_cache(ctx);
 }
 
 void set_tiles(ClassJob& j, int ts0, int tsr) {
@@ -247,11 +309,14 @@ void set_tiles(ClassJob& j, int ts0, int tsr) {
 // shape computes the same values).  Choices are cached per class signature.
 int autotune_class(rmg_ctx* ctx, ClassJob& j) {
   const std::string key = tune_key(j);
-  auto it = ctx->tune.find(key);
-  if (it != ctx->tune.end()) {
-    set_tiles(j, it->second.first, it->second.second);
+  std::string val;
+  int t0 = 0, t1 = 0;
+  if (tune_get(ctx, key, &val) && sscanf(val.c_str(), "%d %d", &t0, &t1) == 2 && (t0 == 16 || t0 == 32) &&
+      (t1 == 16 || t1 == 32)) {
+    set_tiles(j, t0, t1);
     return RMG_OK;
   }
+  ctx->tuned_now = true;
   KernelTimer* saved = j.pl.timer;
   j.pl.timer = nullptr;
   // The first candidate is the default; another one replaces it only when it is
@@ -264,10 +329,10 @@ int autotune_class(rmg_ctx* ctx, ClassJob& j) {
     set_tiles(j, c[0], c[1]);
     const StreamPlan odd = flip(j.pl);
     HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
-    HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream));
-    HIP_TRY(ctx, launch_stream_iteration(j.a, odd, j.stream));
+    HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream, j.a.cpp));
+    HIP_TRY(ctx, launch_stream_iteration(j.a, odd, j.stream, j.a.cpp));
     HIP_TRY(ctx, hipEventRecord(ctx->tev[0], j.stream));
-    for (int i = 0; i < 4; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, (i & 1) ? odd : j.pl, j.stream));
+    for (int i = 0; i < 4; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, (i & 1) ? odd : j.pl, j.stream, j.a.cpp));
     HIP_TRY(ctx, hipEventRecord(ctx->tev[1], j.stream));
     HIP_TRY(ctx, hipEventSynchronize(ctx->tev[1]));
     float ms = 0.f;
@@ -280,44 +345,76 @@ int autotune_class(rmg_ctx* ctx, ClassJob& j) {
       b1 = c[1];
     }
   }
-  ctx->tune[key] = {b0, b1};
+  char cv[32];
+  snprintf(cv, sizeof cv, "%d %d", b0, b1);
+  tune_put(ctx, key, cv);
   set_tiles(j, b0, b1);
   j.pl.timer = saved;
   HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
   return RMG_OK;
 }
 
-// Add the durations of the timed launches recorded before `upto` (all complete).
-int harvest_timer(rmg_ctx* ctx, KernelTimer* t, int64_t upto) {
+// Add the durations of the timed launches recorded before upto[k] in ring k (all complete).
+struct RingMarks {
+  int64_t tail[kTimedKinds] = {};
+};
+RingMarks ring_marks(const KernelTimer* t) {
+  RingMarks m;
+  if (t)
+    for (int k = 0; k < kTimedKinds; ++k) m.tail[k] = t->ring[k].tail;
+  return m;
+}
+int harvest_timer(rmg_ctx* ctx, KernelTimer* t, const RingMarks& upto) {
   if (!t) return RMG_OK;
-  for (; t->head < upto; ++t->head) {
-    const int q = (int)(t->head % t->cap);
-    float ms = 0.f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ms, t->ev[2 * q], t->ev[2 * q + 1]));
-    t->total_ms += ms;
-    ++t->launches;
+  for (int k = 0; k < kTimedKinds; ++k) {
+    EventRing& r = t->ring[k];
+    for (; r.head < upto.tail[k]; ++r.head) {
+      const int q = (int)(r.head % r.cap);
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, r.ev[2 * q], r.ev[2 * q + 1]));
+      r.total_ms += ms;
+      ++r.launches;
+    }
   }
   return RMG_OK;
 }
 
+// Timer `ti` for a streaming class: reset its rings, record what its counters mean.
+KernelTimer* attach_timer(rmg_ctx* ctx, int ti, const ClassJob& j) {
+  KernelTimer* t = &ctx->timers[ti];
+  for (auto& r : t->ring) r.head = r.tail = 0;
+  TimerMeta& mt = ctx->tmeta[ti];
+  mt.es = j.fp64 ? 8 : 4;
+  const int lt = j.pl.ltop, m = j.a.n >> lt;
+  double cells = 0.0, visits = 1.0;
+  for (int l = lt; l < j.a.nlev; ++l, visits *= j.a.gamma) cells += visits * (double)(j.a.n >> l) * (j.a.n >> l);
+  mt.coarse_cells = cells;
+  mt.coarse_bytes = 5.0 * mt.es * (double)m * m;
+  mt.fine_bytes = 8.0 * (2 + j.a.F) + 4.0 * mt.es * 4.0 / 3.0;
+  return t;
+}
+
 // Run every class to completion.  Whole-sample classes are single launches.  A
-// streaming class advances in batches of G Picard iterations (a replayed HIP graph,
-// or eager launches) of alternating plan parity (G is even, so every batch starts
-// with the even plan and ends with the odd one); each batch ends with a 4-byte
-// read-back of the class's active-sample count (of its last iteration) and an event.  D batches stay in flight per class, so the
-// device never waits for the host; batches issued after the count reached zero
-// find no active sample and do nothing.  Classes are polled independently.
-// With kernel timing on, the first iteration of a timed batch is launched eagerly
-// with its timed launches bracketed by events (events recorded by graph nodes
-// cannot be timed) and the other G - 1 replay a second graph.  An eager iteration
-// costs a roughly fixed extra host and queue time, so classes with short iterations
-// (fewer than kDenseCells cells per iteration) time every kTimedEvery-th batch and
-// the others every batch: a uniform sample of the launches, one in G * kTimedEvery
-// or one in G.
-int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
-  constexpr int G = 8, D = 3, kTimedEvery = 8;
+// streaming class advances in batches of G passes (a replayed HIP graph, or eager
+// launches) of alternating plan parity (G is even, so every batch starts with the even
+// plan and ends with the odd one); each batch ends with an 8-byte read-back of the
+// class's counters (active samples, and those of them in the fallback attempt, after
+// its last pass) and an event.  A pass runs J cycle slots: J = the primary cycle count,
+// or, once the read-back shows a sample in the fallback attempt, the larger of the
+// primary and fallback counts (the kernels take each sample's cycles from its state,
+// so the switch, seen a few batches late, never changes results).  D batches stay in
+// flight per class, so the device never waits for the host; batches issued after the
+// count reached zero find no active sample and do nothing.  Classes are polled
+// independently.  With kernel timing on, the first pass of a timed batch is launched
+// eagerly with its timed launches' events recorded by their dispatches (events recorded
+// by graph nodes cannot be timed) and the other G - 1 replay a second graph.  An eager
+// pass costs a roughly fixed extra host and queue time, so classes with short passes
+// (fewer than kDenseCells cells per pass) time every kTimedEvery-th batch and the others
+// every batch: a uniform sample of the launches, one in G * kTimedEvery or one in G.
+int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs, int G = 8) {
+  constexpr int D = 3, kTimedEvery = 8;
   constexpr int64_t kDenseCells = int64_t(1) << 22;
-  static_assert(G % 2 == 0, "a batch must end on the odd plan (double-buffered per-sample state)");
+  if (G < 2 || G % 2 != 0) return fail(ctx, RMG_EINVAL, "internal: odd batch length");
   const bool timing = ctx->timing != 0;
   if (jobs.size() > 16) return fail(ctx, RMG_EINVAL, "too many grid-size classes");
   int ti = 0;
@@ -325,10 +422,7 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     j.pl.timer = nullptr;
     j.pl.tcells = nullptr;
     if (ctx->timing && !j.whole && ti < 8) {
-      j.pl.timer = &ctx->timers[ti];
-      j.pl.timer->head = j.pl.timer->tail = 0;
-      ctx->timer_es[ti] = j.fp64 ? 8 : 4;
-      ++ti;
+      j.pl.timer = attach_timer(ctx, ti++, j);
     }
   }
   // Streaming classes first: their set-up (and a first call's synchronous tile
@@ -356,9 +450,13 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
     HIP_TRY(ctx, launch_whole_sample(j.a, j.fp64, j.stream));
     j.done = true;
   }
-  // per class: a graph of the batch's G iterations, and (timing) one of its last G - 1
-  std::vector<hipGraphExec_t> execs(2 * jobs.size(), nullptr);
-  std::vector<hipGraph_t> graphs(2 * jobs.size(), nullptr);
+  // cycle slots per pass: primary, and with a sample in the fallback attempt
+  auto slots = [](const ClassJob& j, int v) { return v == 0 ? j.a.cpp : std::max(j.a.cpp, j.a.fb_cpp); };
+  auto nvar = [](const ClassJob& j) { return j.a.fb_cpp > j.a.cpp ? 2 : 1; };
+  // per class and slot variant v: a graph of the batch's G passes (index 4c + 2v) and,
+  // with timing, one of its last G - 1 (4c + 2v + 1)
+  std::vector<hipGraphExec_t> execs(4 * jobs.size(), nullptr);
+  std::vector<hipGraph_t> graphs(4 * jobs.size(), nullptr);
   auto cleanup = [&]() {
     for (auto& e : execs)
       if (e) (void)hipGraphExecDestroy(e);
@@ -372,70 +470,64 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
       StreamPlan untimed = j.pl;
       untimed.timer = nullptr;
       const StreamPlan untimed_odd = flip(untimed);
-      for (int first = 0; first < (timing ? 2 : 1); ++first) {
-        const char* what = "hipStreamBeginCapture";
-        hipError_t e = hipStreamBeginCapture(j.stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) what = "captured iteration launches";
-        for (int i = first; i < G && e == hipSuccess; ++i)
-          e = launch_stream_iteration(j.a, (i & 1) ? untimed_odd : untimed, j.stream);
-        hipGraph_t g = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(j.stream, &g);
-        graphs[2 * c + first] = g;
-        if (e == hipSuccess) {
-          e = e2;
-          what = "hipStreamEndCapture";
+      for (int v = 0; v < nvar(j); ++v)
+        for (int first = 0; first < (timing ? 2 : 1); ++first) {
+          const size_t gi = 4 * c + 2 * v + first;
+          const char* what = "hipStreamBeginCapture";
+          hipError_t e = hipStreamBeginCapture(j.stream, hipStreamCaptureModeThreadLocal);
+          if (e == hipSuccess) what = "captured pass launches";
+          for (int i = first; i < G && e == hipSuccess; ++i)
+            e = launch_stream_iteration(j.a, (i & 1) ? untimed_odd : untimed, j.stream, slots(j, v));
+          hipGraph_t g = nullptr;
+          const hipError_t e2 = hipStreamEndCapture(j.stream, &g);
+          graphs[gi] = g;
+          if (e == hipSuccess) {
+            e = e2;
+            what = "hipStreamEndCapture";
+          }
+          if (e == hipSuccess) {
+            e = hipGraphInstantiate(&execs[gi], g, nullptr, nullptr, 0);
+            what = "hipGraphInstantiate";
+          }
+          if (e != hipSuccess) {
+            cleanup();
+            return fail(ctx, RMG_EHIP, "graph capture of the Picard pass failed in %s: %s", what,
+                        hipGetErrorString(e));
+          }
         }
-        if (e == hipSuccess) {
-          e = hipGraphInstantiate(&execs[2 * c + first], g, nullptr, nullptr, 0);
-          what = "hipGraphInstantiate";
-        }
-        if (e != hipSuccess) {
-          cleanup();
-          return fail(ctx, RMG_EHIP, "graph capture of the Picard iteration failed in %s: %s", what,
-                      hipGetErrorString(e));
-        }
-      }
     }
   }
-  // every sample stops after at most n_steps * max_picard iterations
+  // every sample stops after at most n_steps * (max_picard * cpp + fallback limit * its
+  // cycles) passes
   std::vector<int64_t> issued(jobs.size(), 0), retired(jobs.size(), 0);
-  std::vector<std::array<int64_t, D>> mark(jobs.size());
+  std::vector<int> var(jobs.size(), 0);
+  std::vector<std::array<RingMarks, D>> mark(jobs.size());
   auto bound = [&](const ClassJob& j) {
     const int64_t steps = std::max(j.a.cp.prob[0].n_steps, j.a.cp.prob[1].n_steps);
-    return steps * (int64_t)j.a.max_picard + (int64_t)(D + 1) * G;
+    return steps * ((int64_t)j.a.max_picard * std::max(1, j.a.cpp) + (int64_t)j.a.fb_max_picard * j.a.fb_cpp) +
+           (int64_t)(D + 1) * G;
   };
-#ifdef RMG_HOST_STATS
-  double host_issue_s = 0.0;
-  long n_issue = 0, n_poll = 0;
-#endif
   auto issue = [&](size_t c) -> hipError_t {
-#ifdef RMG_HOST_STATS
-    const auto t0_ = std::chrono::steady_clock::now();
-    struct Acc {
-      double& s;
-      std::chrono::steady_clock::time_point t;
-      ~Acc() { s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count(); }
-    } acc_{host_issue_s, t0_};
-    ++n_issue;
-#endif
     ClassJob& j = jobs[c];
     const int k = (int)(issued[c] % D);
+    const int v = var[c];
     StreamPlan untimed = j.pl;
     untimed.timer = nullptr;
     const StreamPlan untimed_odd = flip(untimed);
     hipError_t e = hipSuccess;
     const bool timed = timing && ((int64_t)j.a.S * j.a.n * j.a.n >= kDenseCells || issued[c] % kTimedEvery == 0);
-    if (timed) e = launch_stream_iteration(j.a, j.pl, j.stream);
+    if (timed) e = launch_stream_iteration(j.a, j.pl, j.stream, slots(j, v));
     if (use_graphs) {
-      if (e == hipSuccess) e = hipGraphLaunch(execs[2 * c + (timed ? 1 : 0)], j.stream);
+      if (e == hipSuccess) e = hipGraphLaunch(execs[4 * c + 2 * v + (timed ? 1 : 0)], j.stream);
     } else {
       for (int i = timed ? 1 : 0; i < G && e == hipSuccess; ++i)
-        e = launch_stream_iteration(j.a, (i & 1) ? untimed_odd : untimed, j.stream);
+        e = launch_stream_iteration(j.a, (i & 1) ? untimed_odd : untimed, j.stream, slots(j, v));
     }
     if (e == hipSuccess)
-      e = hipMemcpyAsync(j.h_count + k, flip(j.pl).active_count, sizeof(int32_t), hipMemcpyDeviceToHost, j.stream);
+      e = hipMemcpyAsync(j.h_count + 2 * k, flip(j.pl).active_count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         j.stream);
     if (e == hipSuccess) e = hipEventRecord(ctx->pev[c][k], j.stream);
-    mark[c][k] = j.pl.timer ? j.pl.timer->tail : 0;
+    mark[c][k] = ring_marks(j.pl.timer);
     ++issued[c];
     return e;
   };
@@ -463,7 +555,8 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
       }
       progressed = true;
       if ((rc = harvest_timer(ctx, j.pl.timer, mark[c][k])) != RMG_OK) break;
-      const int32_t left = ((volatile int32_t*)j.h_count)[k];
+      const int32_t left = ((volatile int32_t*)j.h_count)[2 * k];
+      const int32_t in_fallback = ((volatile int32_t*)j.h_count)[2 * k + 1];
       ++retired[c];
       if (left == 0) {
         e = launch_stream_finish(j.a, flip(j.pl), j.stream);
@@ -472,27 +565,22 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs) {
         --active;
         continue;
       }
+      if (in_fallback > 0 && nvar(j) == 2) var[c] = 1;
       if (issued[c] * G > bound(j)) {
-        rc = fail(ctx, RMG_EHIP, "samples still active after %lld iterations", (long long)(issued[c] * G));
+        rc = fail(ctx, RMG_EHIP, "samples still active after %lld passes", (long long)(issued[c] * G));
         break;
       }
       e = issue(c);
       if (e != hipSuccess) rc = fail(ctx, RMG_EHIP, "iteration launch failed: %s", hipGetErrorString(e));
     }
     if (!progressed) std::this_thread::yield();
-#ifdef RMG_HOST_STATS
-    ++n_poll;
-#endif
   }
-#ifdef RMG_HOST_STATS
-  fprintf(stderr, "[rmg host] issues %ld, %.1f us each, polls %ld\n", n_issue, 1e6 * host_issue_s / (n_issue ? n_issue : 1), n_poll);
-#endif
   // leave nothing of this call running on an error; collect the last timed launches
   for (auto& j : jobs) {
     if (j.whole) continue;
     const hipError_t e = hipStreamSynchronize(j.stream);
     if (e != hipSuccess && rc == RMG_OK) rc = fail(ctx, RMG_EHIP, "stream synchronize: %s", hipGetErrorString(e));
-    if (rc == RMG_OK && j.pl.timer) rc = harvest_timer(ctx, j.pl.timer, j.pl.timer->tail);
+    if (rc == RMG_OK && j.pl.timer) rc = harvest_timer(ctx, j.pl.timer, ring_marks(j.pl.timer));
   }
   cleanup();
   return rc;
@@ -526,7 +614,7 @@ int64_t rmg_struct_size(const char* name) {
   return -1;
 }
 
-int rmg_ctx_create(rmg_ctx** out, int hip_device) {
+int rmg_ctx_create(rmg_ctx** out, int hip_device, const char* tune_cache_path) {
   if (!out) return RMG_EINVAL;
   *out = nullptr;
   int ndev = 0;
@@ -534,10 +622,25 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device) {
   rmg_ctx* c = new (std::nothrow) rmg_ctx();
   if (!c) return RMG_ENOMEM;
   c->device = hip_device;
+  // 8 counters per class: two per batch in flight
   if (hipSetDevice(hip_device) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_count, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->h_count, 256 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return RMG_EHIP;
+  }
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+      rmg_ctx_destroy(c);
+      return RMG_EHIP;
+    }
+    char dk[128];
+    snprintf(dk, sizeof dk, "[%s cu=%d]", prop.gcnArchName, prop.multiProcessorCount);
+    c->dev_key = dk;
+  }
+  if (tune_cache_path && *tune_cache_path) {
+    c->tune_path = tune_cache_path;
+    load_tune_cache(c);
   }
   for (auto& s : c->side) {
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
@@ -595,68 +698,104 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device) {
       return RMG_EHIP;
     }
   }
-  if (hipMalloc((void**)&c->d_tcells, 16 * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_tcells, 0, 16 * sizeof(unsigned long long)) != hipSuccess) {
+  constexpr size_t ncnt = 8 * kTimerCounters;
+  if (hipMalloc((void**)&c->d_tcells, ncnt * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_tcells, 0, ncnt * sizeof(unsigned long long)) != hipSuccess) {
     rmg_ctx_destroy(c);
     return RMG_EHIP;
   }
-  for (int t = 0; t < 8; ++t) c->timers[t].d_cells = c->d_tcells + 2 * t;
+  for (int t = 0; t < 8; ++t) c->timers[t].d_cells = c->d_tcells + kTimerCounters * t;
   *out = c;
   return RMG_OK;
 }
 
+int rmg_ctx_set_workspace_limit(rmg_ctx* c, int64_t bytes) {
+  if (!c) return RMG_EINVAL;
+  c->err.clear();
+  if (bytes < 0) return fail(c, RMG_EINVAL, "workspace limit must be >= 0");
+  c->ws_limit = (size_t)bytes;
+  return RMG_OK;
+}
+
 static void free_timer_events(rmg_ctx* c) {
-  for (auto& t : c->timers) {
-    if (!t.ev) continue;
-    for (int q = 0; q < 2 * t.cap; ++q)
-      if (t.ev[q]) (void)hipEventDestroy(t.ev[q]);
-    delete[] t.ev;
-    t.ev = nullptr;
-    t.cap = 0;
-  }
+  for (auto& t : c->timers)
+    for (auto& r : t.ring) {
+      if (!r.ev) continue;
+      for (int q = 0; q < 2 * r.cap; ++q)
+        if (r.ev[q]) (void)hipEventDestroy(r.ev[q]);
+      delete[] r.ev;
+      r.ev = nullptr;
+      r.cap = 0;
+    }
 }
 
 int rmg_set_kernel_timing(rmg_ctx* c, int which) {
   if (!c) return RMG_EINVAL;
   c->err.clear();
-  if (which != RMG_TIME_NONE && which != RMG_TIME_SMOOTHER_DOWN)
-    return fail(c, RMG_EINVAL, "unknown timed kernel %d", which);
+  constexpr int all = RMG_TIME_SMOOTHER_DOWN | RMG_TIME_COARSE | RMG_TIME_FINE;
+  if (which & ~all) return fail(c, RMG_EINVAL, "unknown timed kernel mask %d", which);
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipDeviceSynchronize());
-  if (which != RMG_TIME_NONE) {
-    for (auto& t : c->timers) {
-      if (t.ev) continue;
-      t.ev = new (std::nothrow) hipEvent_t[2 * kTimerPairs]();
-      if (!t.ev) return fail(c, RMG_ENOMEM, "timer event pool");
-      t.cap = kTimerPairs;
-      for (int q = 0; q < 2 * kTimerPairs; ++q) HIP_TRY(c, hipEventCreate(&t.ev[q]));
+  const int bit[kTimedKinds] = {RMG_TIME_SMOOTHER_DOWN, RMG_TIME_COARSE, RMG_TIME_FINE};
+  for (auto& t : c->timers)
+    for (int k = 0; k < kTimedKinds; ++k) {
+      EventRing& r = t.ring[k];
+      if (!(which & bit[k]) || r.ev) continue;
+      r.ev = new (std::nothrow) hipEvent_t[2 * kTimerPairs]();
+      if (!r.ev) return fail(c, RMG_ENOMEM, "timer event pool");
+      r.cap = kTimerPairs;
+      for (int q = 0; q < 2 * kTimerPairs; ++q) HIP_TRY(c, hipEventCreate(&r.ev[q]));
     }
-  }
   for (auto& t : c->timers) {
     t.which = which;
-    t.head = t.tail = 0;
-    t.launches = 0;
-    t.total_ms = 0.0;
+    for (int k = 0; k < kTimedKinds; ++k) {
+      EventRing& r = t.ring[k];
+      r.head = r.tail = 0;
+      r.launches = 0;
+      r.total_ms = 0.0;
+      // a ring of a kind that is not selected stays unused (room() is false without events)
+      if (!(which & bit[k]) && r.ev) {
+        for (int q = 0; q < 2 * r.cap; ++q) (void)hipEventDestroy(r.ev[q]);
+        delete[] r.ev;
+        r.ev = nullptr;
+        r.cap = 0;
+      }
+    }
   }
-  HIP_TRY(c, hipMemset(c->d_tcells, 0, 16 * sizeof(unsigned long long)));
+  HIP_TRY(c, hipMemset(c->d_tcells, 0, 8 * kTimerCounters * sizeof(unsigned long long)));
   c->timing = which;
   return RMG_OK;
 }
 
-int rmg_get_kernel_timing(rmg_ctx* c, rmg_kernel_timing* out) {
+int rmg_get_kernel_timing(rmg_ctx* c, int kind, rmg_kernel_timing* out) {
   if (!c || !out) return RMG_EINVAL;
   c->err.clear();
+  int k;
+  if (kind == RMG_TIME_SMOOTHER_DOWN) k = 0;
+  else if (kind == RMG_TIME_COARSE) k = 1;
+  else if (kind == RMG_TIME_FINE) k = 2;
+  else return fail(c, RMG_EINVAL, "kind %d is not a single timed kernel", kind);
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipDeviceSynchronize());
-  unsigned long long cells[16];
-  HIP_TRY(c, hipMemcpy(cells, c->d_tcells, sizeof cells, hipMemcpyDeviceToHost));
+  unsigned long long cnt[8 * kTimerCounters];
+  HIP_TRY(c, hipMemcpy(cnt, c->d_tcells, sizeof cnt, hipMemcpyDeviceToHost));
   rmg_kernel_timing r = {0, 0, 0.0, 0.0};
   for (int t = 0; t < 8; ++t) {
-    r.launches += c->timers[t].launches;
-    r.total_ms += c->timers[t].total_ms;
-    r.cells += (int64_t)(cells[2 * t] + cells[2 * t + 1]);
-    const double es = c->timer_es[t];
-    r.algo_bytes += es * (5.25 * (double)cells[2 * t] + 6.25 * (double)cells[2 * t + 1]);
+    const EventRing& ring = c->timers[t].ring[k];
+    const TimerMeta& m = c->tmeta[t];
+    const unsigned long long* q = cnt + kTimerCounters * t;
+    r.launches += ring.launches;
+    r.total_ms += ring.total_ms;
+    if (k == 0) {
+      r.cells += (int64_t)(q[0] + q[1]);
+      r.algo_bytes += m.es * (5.25 * (double)q[0] + 6.25 * (double)q[1]);
+    } else if (k == 1) {
+      r.cells += (int64_t)((double)q[2] * m.coarse_cells);
+      r.algo_bytes += (double)q[2] * m.coarse_bytes;
+    } else {
+      r.cells += (int64_t)q[4];
+      r.algo_bytes += (double)q[4] * m.fine_bytes;
+    }
   }
   *out = r;
   return RMG_OK;
@@ -822,6 +961,7 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
   ClassJob aj = fj;
   rmg_solver_opts aopts = *opts;
   aopts.flags |= 1 | 8;  // level streaming, fixed tiles
+  aopts.fallback_cycles = 0;
   class_plan(aj, &aopts);
   aj.a.cpp = std::max(1, opts->cycles_per_picard);
 
@@ -892,9 +1032,7 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
   // while the event ring has room; it is drained at every poll)
   KernelTimer* tm = nullptr;
   if (ctx->timing) {
-    tm = &ctx->timers[1];
-    tm->head = tm->tail = 0;
-    ctx->timer_es[1] = aj.fp64 ? 8 : 4;
+    tm = attach_timer(ctx, 1, aj);
   }
   aj.pl.timer = tm;
   for (int seg = (K == 1 ? 0 : nst / K - 1); seg >= 0; --seg) {
@@ -930,7 +1068,7 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
       its += 8;
       HIP_TRY(ctx, hipMemcpyAsync(ctx->h_count, aj.pl.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
-      if ((rc = harvest_timer(ctx, tm, tm ? tm->tail : 0))) return rc;
+      if ((rc = harvest_timer(ctx, tm, ring_marks(tm)))) return rc;
       if (((volatile int32_t*)ctx->h_count)[0] == 0) break;
       if (its > bound) return fail(ctx, RMG_EHIP, "adjoint samples still active after %lld iterations", (long long)its);
     }
@@ -1093,12 +1231,52 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
       if (nside == 7) return fail(ctx, RMG_EINVAL, "more than seven level-streaming grid sizes");
       jobs[c].stream = ctx->side[nside++];
     }
-    jobs[c].h_count = ctx->h_count + 4 * (int)c;
+    jobs[c].h_count = ctx->h_count + 8 * (int)c;
   }
   for (int q = 0; q < nside; ++q) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[q], ctx->ev[0], 0));
-  // flag bit 7: the whole-sample classes move to the restricted stream when streaming
-  // classes run beside them (whether that helps depends on which class is critical)
-  const bool wmasked = ctx->wstream && any_whole && nside > 0 && (opts->flags & 128);
+  // Schedule of the call: whether the whole-sample classes move to the restricted stream
+  // while streaming classes run beside them (flag bit 7 forces it, bit 8 forbids it;
+  // whether it helps depends on which class is critical), and the passes per batch G.
+  // Otherwise the choice is tuned per call signature across calls: each candidate runs
+  // one whole call and is timed, then the fastest (a later candidate must beat the
+  // first by 5 %) is kept and written to the tune cache.  Results never depend on it.
+  const bool can_confine = ctx->wstream && any_whole && nside > 0;
+  const bool tune_sched = (opts->flags & (8 | 16)) == 0;
+  std::vector<std::pair<int, int>> cands;  // (confine, G)
+  for (int G : {8, 16}) {
+    if (!tune_sched && G != 8) continue;
+    if (!can_confine || (opts->flags & 256)) {
+      cands.push_back({0, G});
+    } else if (opts->flags & 128) {
+      cands.push_back({1, G});
+    } else {
+      cands.push_back({0, G});
+      cands.push_back({1, G});
+    }
+  }
+  std::string skey = "sched";
+  for (auto& j : jobs) skey += " {" + tune_key(j) + (j.whole ? " whole" : "") + "}";
+  {
+    char fb[64];
+    snprintf(fb, sizeof fb, " flags=%d", opts->flags & ~(8 | 16));
+    skey += fb;
+  }
+  int sched_cand = -1;  // index being tried in this call, or -1 if the choice is settled
+  std::pair<int, int> sched = cands[0];
+  if (cands.size() > 1) {
+    std::string val;
+    int c0 = 0, g0 = 0;
+    if (tune_get(ctx, skey, &val) && sscanf(val.c_str(), "%d %d", &c0, &g0) == 2 && (c0 == 0 || can_confine) &&
+        (g0 == 8 || g0 == 16)) {
+      sched = {c0, g0};
+    } else {
+      sched_cand = (int)ctx->sched_trials[skey].size();
+      sched = cands[sched_cand];
+    }
+  }
+  const auto t_sched0 = std::chrono::steady_clock::now();
+  ctx->tuned_now = false;
+  const bool wmasked = can_confine && sched.first;
   std::vector<hipStream_t> sused(ctx->side, ctx->side + nside);
   if (wmasked) {
     HIP_TRY(ctx, hipStreamWaitEvent(ctx->wstream, ctx->ev[0], 0));
@@ -1117,7 +1295,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
         }
     }
   }
-  if ((rc = run_classes(ctx, jobs, !(opts->flags & 2)))) return rc;
+  if ((rc = run_classes(ctx, jobs, !(opts->flags & 2), sched.second))) return rc;
   for (int q = 0; q < nside; ++q) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1 + q], sused[q]));
     HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1 + q], 0));
@@ -1163,6 +1341,19 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
   }
   HIP_TRY(ctx, hipMemcpyAsync(h_out, d_sums, sizeof(rmg_level_sums) * n_levels, hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
+  if (sched_cand >= 0 && !ctx->tuned_now) {  // a call that also tuned tiles is not a fair trial
+    auto& tr = ctx->sched_trials[skey];
+    tr.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_sched0).count());
+    if (tr.size() == cands.size()) {
+      size_t best = 0;
+      for (size_t q = 1; q < tr.size(); ++q)
+        if (tr[q] < 0.95 * tr[0] && tr[q] < tr[best]) best = q;
+      char cv[32];
+      snprintf(cv, sizeof cv, "%d %d", cands[best].first, cands[best].second);
+      tune_put(ctx, skey, cv);
+      ctx->sched_trials.erase(skey);
+    }
+  }
   for (int l = 0; l < n_levels; ++l)
     if (h_out[l].n_failed) return fail(ctx, RMG_ENOTCONV, "level %d: %lld failed pairs", l, (long long)h_out[l].n_failed);
   return RMG_OK;

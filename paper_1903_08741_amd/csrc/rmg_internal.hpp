@@ -20,13 +20,36 @@ constexpr int kTile = 32;       // output tile edge of the level-streaming kerne
 constexpr int coarse_top(bool fp64) { return fp64 ? 32 : RMG_COARSE_TOP_F32; }
 
 // Per-sample iteration state of the level-streaming path (device memory).
+// A Picard iteration takes cpp multigrid cycles.  The forward streaming path launches
+// J cycle slots per pass (k_fine, then J cycles); a sample runs its cycles cyc0,
+// cyc0 + 1, ... in the slots of consecutive passes, so samples whose cycle counts
+// differ share one launch sequence (slot j of a pass is cycle cyc0 + j of the sample,
+// skipped when cyc0 + j >= cpp).
 struct SampleState {
   int32_t active, new_step, step, it;
   int32_t status, tot_its, cycles, nanflag;
   double final_dp;
-  int32_t pend;   // adjoint: the step above `step` converged and its gradient term is pending
-  int32_t fresh;  // streaming forward: no iteration has run yet (no stopping test pending)
+  int32_t pend;    // adjoint: the step above `step` converged and its gradient term is pending
+  int32_t fresh;   // streaming forward: no iteration has run yet (no stopping test pending)
+  int32_t cpp;     // cycles per Picard iteration of the current attempt
+  int32_t cyc0;    // cycles of the current iteration done before this pass
+  int32_t jpass;   // cycle slots of the pass that last wrote this state
+  int32_t attempt; // 0: primary setting; 1: fallback setting (restarted from the initial state)
 };
+
+// Slot argument of the cycle kernels: kUniform runs the cycle for every active sample
+// with the launch's own u_zero / final flags (adjoint); slot j >= 0 takes them from the
+// sample's state (cycle cyc0 + j of its iteration).
+constexpr int kUniform = -1;
+__device__ __forceinline__ bool slot_runs(const SampleState& st, int slot) {
+  return st.active && (slot < 0 || st.cyc0 + slot < st.cpp);
+}
+__device__ __forceinline__ bool slot_first(const SampleState& st, int slot, int uniform_flag) {
+  return slot < 0 ? uniform_flag != 0 : st.cyc0 + slot == 0;
+}
+__device__ __forceinline__ bool slot_last(const SampleState& st, int slot, int uniform_flag) {
+  return slot < 0 ? uniform_flag != 0 : st.cyc0 + slot + 1 == st.cpp;
+}
 
 // Problems of one grid-size class: samples [0, seg_split) use prob[0], the rest prob[1].
 struct ClassProblems {
@@ -55,6 +78,8 @@ struct SolveArgs {
   const double* fields;
   ClassProblems cp;
   int nu1, nu2, cpp, max_picard;
+  int fb_cpp, fb_max_picard;  // fallback attempt (fb_cpp = 0: none): a sample that fails with
+                              // cpp / max_picard restarts from its initial state with these
   int gamma;  // coarse cycles per level visit: 1 = V-cycle, 2 = W-cycle
   int state_global;  // whole-sample kernel: keep the FP64 state in global memory even if LDS fits
   int fuse_top;      // level streaming with the coarse kernel's top level the finest: one launch
@@ -95,17 +120,31 @@ struct AdjArgs {
 size_t whole_sample_lds_bytes(int n, int nc, bool fp64, int F, bool* state_in_lds);
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st);
 
-// Optional timing of the down-leg smoother launches (fused nu1 sweeps, residual and
-// restriction): HIP events around each launch on its own stream, and device counters
-// of the cells the timed launches processed ([0]: zero initial iterate, [1]: loaded).
+// Optional timing of the streaming kernels.  A timed launch goes out through
+// hipExtLaunchKernelGGL with an event pair that the dispatch itself records, so the
+// pair brackets the kernel's execution (not the queue time before it).  One ring of
+// event pairs per timed kernel kind; device counters of the work the timed launches
+// did (d_cells[0]: down-leg cells with a zero initial iterate, [1]: with a loaded
+// iterate, [2]: coarse-kernel sample launches, [4]: fine-kernel cells).
+struct EventRing {
+  hipEvent_t* ev = nullptr;  // cap event pairs
+  int cap = 0;
+  int64_t head = 0, tail = 0;  // pairs harvested / recorded so far (tail - head <= cap in flight)
+  int64_t launches = 0;
+  double total_ms = 0.0;
+  bool room() const { return ev && tail - head < cap; }
+  hipEvent_t* next() {
+    hipEvent_t* e = ev + 2 * (tail % cap);
+    ++tail;
+    return e;
+  }
+};
+constexpr int kTimedKinds = 3;  // ring 0: down leg, 1: coarse kernel, 2: fine kernel
+constexpr int kTimerCounters = 8;
 struct KernelTimer {
-  int which;      // 0: off, 1: down-leg smoother
-  hipEvent_t* ev;      // ring of cap event pairs
-  int cap;
-  int64_t head, tail;  // pairs harvested / recorded so far (tail - head <= cap in flight)
-  unsigned long long* d_cells;
-  int64_t launches;
-  double total_ms;
+  int which = 0;  // bit mask of rmg_timed_kernel
+  EventRing ring[kTimedKinds];
+  unsigned long long* d_cells = nullptr;  // kTimerCounters device counters
 };
 
 // Level-streaming path.
@@ -123,8 +162,8 @@ struct StreamPlan {
   SampleState* state_prev;
   unsigned long long* dpmax;
   unsigned long long* dpmax_prev;
-  int32_t* active_count;
-  int32_t* count_next;  // the counter of the next iteration (cleared by this one)
+  int32_t* active_count;  // [0]: active samples, [1]: of them in the fallback attempt
+  int32_t* count_next;    // the counters of the next iteration (cleared by this one)
   KernelTimer* timer;               // host object, never dereferenced on the device
   unsigned long long* tcells;       // device counters of a timed launch, else null
 };
@@ -141,17 +180,18 @@ inline StreamPlan flip(const StreamPlan& p) {
 hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 // Kernel attributes of the streaming kernels (call once before launching or capturing).
 hipError_t prepare_stream(const SolveArgs& a, const StreamPlan& pl);
-// One Picard iteration of every active sample: stream operations only, capturable.
-// Successive iterations must alternate the plan's parity (pl, flip(pl), pl, ...),
-// starting with the plan given to launch_stream_init; the state after an iteration
-// is in that iteration's plan's `state` (its stopping test is taken by the next
-// iteration, or is pending: the loop ends after an iteration in which no sample was
-// active, counted in that iteration's active_count).
-hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
+// One pass of every active sample (the fine kernel, then J cycle slots; a sample whose
+// iteration takes cpp <= J cycles completes one Picard iteration per pass): stream
+// operations only, capturable.  Successive passes must alternate the plan's parity
+// (pl, flip(pl), pl, ...), starting with the plan given to launch_stream_init; the
+// state after a pass is in that pass's plan's `state` (its stopping test is taken by
+// the next pass, or is pending: the loop ends after a pass in which no sample was
+// active, counted in that pass's active_count).
+hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st, int J);
 hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
-// The multigrid cycles of one iteration (down legs, coarse kernel, up legs; the finest
-// up leg adds the correction to a.p): what launch_stream_iteration runs between the
-// fine residual and the control kernel.
+// The a.cpp multigrid cycles of one iteration of every active sample (down legs, coarse
+// kernel, up legs; the last cycle's finest up leg adds the correction to a.p), with
+// uniform flags: the adjoint's fixed-point iteration.
 hipError_t launch_stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st);
 
 // Adjoint (streaming path).  a.p must point at ad.mu.

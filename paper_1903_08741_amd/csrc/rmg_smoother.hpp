@@ -230,11 +230,15 @@ constexpr size_t blk_lds_bytes(int ts, int hb) {
 // Down leg on a streaming level l: nu1 red-black sweeps, residual, restriction.
 // Halo: nu1 + 1 blocks (2 nu1 + 2 >= 2 nu1 + 1 cells: the residual of a tile cell
 // depends on data up to 2 nu1 + 1 cells away).
+// slot: kUniform, or the cycle slot of the pass (the finest level's u_zero then follows
+// from the sample's state: zero on the first cycle of its Picard iteration).
 template <class R, int TS, int NB>
-__global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero) {
+__global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero_, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.y;
-  if (!pl.state[s].active) return;
+  const SampleState sst = pl.state[s];
+  if (!slot_runs(sst, slot)) return;
+  const int u_zero = l == 0 ? (int)slot_first(sst, slot, u_zero_) : u_zero_;
   const int m = a.n >> l, mc = m >> 1;
   // timed launches count the cells they process: once per active sample (one
   // counter update per workgroup would serialise thousands of atomics on one address)
@@ -288,12 +292,15 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
 // Up leg on a streaming level l: prolongation of level l+1 (one coarse value per
 // block), nu2 sweeps; on the finest level (final != 0) the Picard update p += dp
 // and ||dp||_inf instead of a store.  Halo: nu2 blocks (2 nu2 cells).
+// slot as for k_down: on the finest level the Picard update follows the sample's last cycle.
 template <class R, int TS, int NB>
-__global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final_) {
+__global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final__, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kBlock / 64];
   const int64_t s = blockIdx.y;
-  if (!pl.state[s].active) return;
+  const SampleState sst = pl.state[s];
+  if (!slot_runs(sst, slot)) return;
+  const int final_ = l == 0 ? (int)slot_last(sst, slot, final__) : final__;
   const int m = a.n >> l, mc = m >> 1;
   const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
   const int ntx = m / TS;

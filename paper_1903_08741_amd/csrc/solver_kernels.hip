@@ -11,6 +11,7 @@
 //     the one-workgroup-per-sample coarse V-cycle in LDS (k_coarse_v) and the
 //     stopping test of the previous iteration at the start of k_fine.
 // Section 4.1 (modified Picard) and Section 4.2 (cell-centred multigrid).
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "rmg_device.hpp"
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   __syncthreads();
 
   int step = 0, it = 0, new_step = 1, status = RMG_SAMPLE_OK, tot_its = 0, cycles = 0;
+  int attempt = 0, cpp = a.cpp, maxp = a.max_picard;  // the fallback attempt changes both
   double dp = 0.0;
   const LdsLevel<R> L0 = lev[0];
   for (;;) {
@@ -174,8 +176,8 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     for (;;) {
       lds_cycle_whole<R, NT>(lev, a.nlev, a.nu1, a.nu2, a.gamma, ncyc == 0, ncyc == 0);
       ++ncyc;
-      if (a.cpp > 0) {
-        if (ncyc == a.cpp) break;
+      if (cpp > 0) {
+        if (ncyc == cpp) break;
         continue;
       }
       double rmax = 0.0;
@@ -208,21 +210,33 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
     ++it;
     ++tot_its;
     cycles += ncyc;
+    int fail = RMG_SAMPLE_OK;
     if (anybad > 0.0) {
-      status = RMG_SAMPLE_NONFINITE;
-      break;
-    }
-    if (dp < a.eps) {
+      fail = RMG_SAMPLE_NONFINITE;
+    } else if (dp < a.eps) {
       ++step;
       it = 0;
       new_step = 1;
       if (step == P.n_steps) break;
     } else {
       new_step = 0;
-      if (it >= a.max_picard) {
-        status = RMG_SAMPLE_MAXITER;
-        break;
+      if (it >= maxp) fail = RMG_SAMPLE_MAXITER;
+    }
+    if (fail != RMG_SAMPLE_OK) {
+      if (a.fb_cpp > 0 && attempt == 0) {
+        // fallback: restart from the initial state with the fallback's cycles and limit
+        attempt = 1;
+        cpp = a.fb_cpp;
+        maxp = a.fb_max_picard;
+        step = 0;
+        it = 0;
+        new_step = 1;
+        for (int c = threadIdx.x; c < N; c += NT) p[c] = a.p0 ? a.p0[s * a.p0_stride + c] : initial_head(P, c >> lg, n);
+        __syncthreads();
+        continue;
       }
+      status = fail;
+      break;
     }
   }
   __syncthreads();
@@ -243,6 +257,8 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
       st.steps_done = step;
       st.status = status;
       st.final_dp_inf = dp;
+      st.attempts = attempt + 1;
+      st.reserved = 0;
       a.stats[s] = st;
     }
   }
@@ -347,73 +363,123 @@ __global__ void k_stream_init(SolveArgs a, StreamPlan pl) {
     z.final_dp = 0.0;
     z.pend = 0;
     z.fresh = 1;
+    z.cpp = a.cpp;
+    z.cyc0 = 0;
+    z.jpass = 0;
+    z.attempt = 0;
     pl.state[s] = z;
     pl.state_prev[s] = z;
     pl.dpmax[s] = 0ull;
     pl.dpmax_prev[s] = 0ull;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *pl.active_count = 0;
-    *pl.count_next = 0;
+    pl.active_count[0] = pl.active_count[1] = 0;
+    pl.count_next[0] = pl.count_next[1] = 0;
   }
 }
 
 // The stopping test and step bookkeeping of one sample after a Picard iteration
 // whose ||dp||_inf is dp (Section 4.1: stop the step when ||dp||_inf < eps_PI;
-// Section 4.3: give up after max_picard iterations in a step).
-__device__ __forceinline__ void control_step(SampleState& st, double dp, const SolveArgs& a, const rmg_problem& P) {
+// Section 4.3: give up after max_picard iterations in a step).  A sample that fails
+// with the primary setting while a fallback is configured is not given up: it
+// restarts from its initial state with the fallback's cycles per Picard iteration
+// and iteration limit (the return value is true then; iteration and cycle totals
+// keep counting).
+__device__ __forceinline__ bool control_step(SampleState& st, double dp, const SolveArgs& a, const rmg_problem& P) {
   st.it += 1;
   st.tot_its += 1;
-  st.cycles += a.cpp;
+  st.cycles += st.cpp;
   st.final_dp = dp;
+  int fail;
   if (st.nanflag) {
-    st.status = RMG_SAMPLE_NONFINITE;
-    st.active = 0;
+    fail = RMG_SAMPLE_NONFINITE;
   } else if (dp < a.eps) {
     st.step += 1;
     st.it = 0;
     st.new_step = 1;
     if (st.step == P.n_steps) st.active = 0;
+    return false;
   } else {
     st.new_step = 0;
-    if (st.it >= a.max_picard) {
-      st.status = RMG_SAMPLE_MAXITER;
-      st.active = 0;
-    }
+    if (st.it < (st.attempt ? a.fb_max_picard : a.max_picard)) return false;
+    fail = RMG_SAMPLE_MAXITER;
   }
+  if (a.fb_cpp > 0 && st.attempt == 0) {
+    st.attempt = 1;
+    st.cpp = a.fb_cpp;
+    st.step = 0;
+    st.it = 0;
+    st.new_step = 1;
+    st.nanflag = 0;
+    return true;
+  }
+  st.status = fail;
+  st.active = 0;
+  return false;
+}
+
+// Pressure head of cell c = j n + i before the first step: the optional caller-given
+// initial state, else the problem's initial condition.
+__device__ __forceinline__ double start_head(const SolveArgs& a, const rmg_problem& P, int64_t s, int64_t c, int j,
+                                             int n) {
+  return a.p0 ? a.p0[s * a.p0_stride + c] : initial_head(P, j, n);
 }
 
 // Outer residual + fine coefficients for one tile, then the coarser levels
 // 1 .. ltop of the same tile by in-tile coarsening (cells of level l inside a
 // 32 x 32 fine tile are complete for 2^l <= 32).
+// Start of a pass (J cycle slots follow): the stopping test of a sample whose iteration
+// ended in the previous pass, the cycle count of one whose iteration is still running.
+// Every workgroup of the sample takes the same decision; the first one stores it and
+// clears this pass's maximum.  Returns whether the sample restarts from its initial state.
+__device__ __forceinline__ bool pass_control(SampleState& st, const SolveArgs& a, const StreamPlan& pl,
+                                             const rmg_problem& P, int64_t s, int J, bool store) {
+  bool restart = false;
+  if (st.fresh) {
+    st.fresh = 0;
+    st.cyc0 = 0;
+  } else if (st.active) {
+    const int done = st.cyc0 + st.jpass;
+    if (done >= st.cpp) {
+      restart = control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
+      st.cyc0 = 0;
+    } else {
+      st.cyc0 = done;
+    }
+  }
+  st.jpass = J;
+  if (store) {
+    pl.state[s] = st;
+    pl.dpmax[s] = 0ull;
+    if (st.active) {
+      atomicAdd(pl.active_count, 1);
+      if (st.attempt) atomicAdd(pl.active_count + 1, 1);
+    }
+    if (s == 0) pl.count_next[0] = pl.count_next[1] = 0;
+  }
+  return restart;
+}
+
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
+__global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl, int J) {
   __shared__ double sp[34 * 34], sK[34 * 34];
   __shared__ R bufA[3 * 32 * 32 + 32], bufB[3 * 16 * 16 + 16];
   const int64_t s = blockIdx.y;
   const rmg_problem P = class_problem(a.cp, s);
-  // stopping test of the previous iteration (every workgroup of the sample takes the
-  // same decision; the first one stores it and clears this iteration's maximum)
   SampleState st = pl.state_prev[s];
-  if (st.fresh)
-    st.fresh = 0;
-  else if (st.active)
-    control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    pl.state[s] = st;
-    pl.dpmax[s] = 0ull;
-    if (st.active) atomicAdd(pl.active_count, 1);
-    if (s == 0) *pl.count_next = 0;
-  }
-  if (!st.active) return;
+  const bool restart = pass_control(st, a, pl, P, s, J, blockIdx.x == 0 && threadIdx.x == 0);
+  // a sample in the middle of its iteration keeps the coefficients formed at its start
+  if (!st.active || st.cyc0 > 0) return;
   const int new_step = st.new_step;
   const int n = a.n;
+  if (pl.tcells && blockIdx.x == 0 && threadIdx.x == 0)  // timed: cells (once per sample)
+    atomicAdd(pl.tcells, (unsigned long long)n * (unsigned long long)n);
   const int T = n < kTile ? n : kTile, TL = T + 2;
   const int ntx = n / T;
   const int tile = xcd_tile();
   const int x0 = (tile % ntx) * T, y0 = (tile / ntx) * T;
   const int64_t N = (int64_t)n * n;
-  const double* p = a.p + s * N;
+  double* p = a.p + s * N;
   double* thold = a.theta_old + s * N;
   // The tile's own cells (T = 32 or n, a power of two; k = threadIdx.x + q kBlock):
   // pressure head and closure once per cell, K and p to LDS for the neighbours, the
@@ -431,7 +497,13 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
       const int lj = k >> lgT, li = k & (T - 1);
       const int64_t c = (int64_t)(y0 + lj) * n + x0 + li;
       if (!new_step) pth[q] = thold[c];
-      const double pv = p[c];
+      double pv;
+      if (restart) {  // a restart re-initialises the head (every workgroup of the sample reads
+        pv = start_head(a, P, s, c, y0 + lj, n);  // it from the initial state, not from p)
+        p[c] = pv;
+      } else {
+        pv = p[c];
+      }
       const CellFields cf = load_fields(a.fields, a.F, N, s, c);
       const Closure cl = closure(P, pv, cf.Ks, cf.alpha, cf.nvg);
       const int le = (lj + 1) * TL + li + 1;
@@ -459,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl) {
     double pv = 0.0, K = 0.0;
     if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
       const int64_t c = (int64_t)gj * n + gi;
-      pv = p[c];
+      pv = restart ? start_head(a, P, s, c, gj, n) : p[c];
       const CellFields cf = load_fields(a.fields, a.F, N, s, c);
       K = closure(P, pv, cf.Ks, cf.alpha, cf.nvg).K;
     }
@@ -533,11 +605,17 @@ template <> struct Vec16<float> { using T = float4; };
 template <> struct Vec16<double> { using T = double2; };
 
 template <class R, int NT>
-__global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero, int final_) {
+__global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero_, int final_, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.x;
-  if (!pl.state[s].active) return;
+  const SampleState sst = pl.state[s];
+  if (!slot_runs(sst, slot)) return;
   const int lt = pl.ltop;
+  // on the finest level (lt = 0) the first and last cycle of the sample's iteration
+  // follow from its state in a cycle slot; on coarser levels from the enclosing cycle
+  const int u_zero = lt == 0 ? slot_first(sst, slot, u_zero_) : u_zero_;
+  const int fin = lt == 0 && slot_last(sst, slot, final_);
+  if (pl.tcells && threadIdx.x == 0) atomicAdd(pl.tcells, 1ull);  // timed: sample launches
   const int m = a.n >> lt;
   const int nlev = a.nlev - lt;
   const int M2 = m * m;
@@ -594,7 +672,7 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   for (int i = threadIdx.x; i < m; i += NT) T.cs[M2 + i] = CT[i];
   __syncthreads();
   lds_cycle_coarse<R, NT>(lev, nlev, a.nu1, a.nu2, a.gamma, u_zero != 0, true);
-  if (lt > 0 || !final_) {
+  if (!fin) {
     for (int v = threadIdx.x; v < nv; v += NT) {
       V o;
       R* oe = (R*)&o;
@@ -642,17 +720,11 @@ __global__ __launch_bounds__(NT) void k_fine_coarse(SolveArgs a, StreamPlan pl) 
   const int64_t s = blockIdx.x;
   const rmg_problem P = class_problem(a.cp, s);
   SampleState st = pl.state_prev[s];
-  if (st.fresh)
-    st.fresh = 0;
-  else if (st.active)
-    control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
-  if (threadIdx.x == 0) {
-    pl.state[s] = st;
-    pl.dpmax[s] = 0ull;
-    if (st.active) atomicAdd(pl.active_count, 1);
-    if (s == 0) *pl.count_next = 0;
-  }
+  // every launch is a whole Picard iteration of its sample (all its cycles)
+  st.jpass = st.cpp;
+  const bool restart = pass_control(st, a, pl, P, s, st.cpp, threadIdx.x == 0);
   if (!st.active) return;
+  if (pl.tcells && threadIdx.x == 0) atomicAdd(pl.tcells, 1ull);  // timed: sample launches
   constexpr int M2 = M * M, TL = M + 2, LG = M == 64 ? 6 : M == 32 ? 5 : 4, Q = M2 / NT;
   static_assert((1 << LG) == M, "unsupported grid size");
   const int nlev = a.nlev;
@@ -665,7 +737,7 @@ __global__ __launch_bounds__(NT) void k_fine_coarse(SolveArgs a, StreamPlan pl) 
                 "the staging fits in the top level's place");
   double* sp = (double*)rbase;  // 8-byte aligned: rbase follows NT / 64 + 1 doubles
   double* sK = sp + TL * TL;
-  const double* pg = a.p + s * M2;
+  double* pg = a.p + s * M2;
   double* thold = a.theta_old + s * M2;
   double cth[Q], cC[Q], pth[Q];
 #pragma unroll
@@ -674,7 +746,13 @@ __global__ __launch_bounds__(NT) void k_fine_coarse(SolveArgs a, StreamPlan pl) 
     const int lj = c >> LG, li = c & (M - 1);
     pth[q] = 0.0;
     if (!new_step) pth[q] = thold[c];
-    const double pv = pg[c];
+    double pv;
+    if (restart) {
+      pv = start_head(a, P, s, c, lj, M);
+      pg[c] = pv;
+    } else {
+      pv = pg[c];
+    }
     const CellFields cf = load_fields(a.fields, a.F, (int64_t)M2, s, c);
     const Closure cl = closure(P, pv, cf.Ks, cf.alpha, cf.nvg);
     const int le = (lj + 1) * TL + li + 1;
@@ -742,7 +820,7 @@ __global__ __launch_bounds__(NT) void k_fine_coarse(SolveArgs a, StreamPlan pl) 
     if (q == Q - 1 && (c >> LG) == M - 1) T.cs[M2 + (c & (M - 1))] = rct;
   }
   __syncthreads();
-  for (int cyc = 0; cyc < a.cpp; ++cyc) lds_cycle_coarse<R, NT>(lev, nlev, a.nu1, a.nu2, a.gamma, cyc == 0, cyc == 0);
+  for (int cyc = 0; cyc < st.cpp; ++cyc) lds_cycle_coarse<R, NT>(lev, nlev, a.nu1, a.nu2, a.gamma, cyc == 0, cyc == 0);
   double* p = a.p + s * M2;
   double mx = 0.0, bad = 0.0;
   for (int c = threadIdx.x; c < M2; c += NT) {
@@ -780,6 +858,8 @@ __global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPla
       o.steps_done = st.step;
       o.status = st.status;
       o.final_dp_inf = st.final_dp;
+      o.attempts = st.attempt + 1;
+      o.reserved = 0;
       a.stats[s] = o;
     }
   }
@@ -805,45 +885,60 @@ static size_t coarse_lds(int m, int nc, bool fp64) {
 }
 
 // Down and up kernels by tile edge and blocks per thread (nu <= 4: at most 3 blocks).
+// A timed launch (ev != null) goes through hipExtLaunchKernelGGL with the event pair
+// recorded by the dispatch itself: the events then bracket the kernel's execution, not
+// the queue time before it.
+template <class K, class... Args>
+static void launch_k(K kern, dim3 grid, dim3 blk, size_t lds, hipStream_t st, hipEvent_t* ev, Args... args) {
+  if (ev)
+    hipExtLaunchKernelGGL(kern, grid, blk, (uint32_t)lds, st, ev[0], ev[1], 0u, args...);
+  else
+    hipLaunchKernelGGL(kern, grid, blk, lds, st, args...);
+}
+
 template <class R>
-static void launch_down(int ts, dim3 grid, hipStream_t st, const SolveArgs& a, const StreamPlan& pl, int l,
-                        int u_zero) {
+static void launch_down(int ts, dim3 grid, hipStream_t st, hipEvent_t* ev, const SolveArgs& a,
+                        const StreamPlan& pl, int l, int u_zero, int slot) {
   const int hb = a.nu1 + 1, nb = blk_nb(ts, hb);
   const size_t lds = blk_lds_bytes<R>(ts, hb);
+  const dim3 b(kBlock);
   if (ts == 16) {
     if (nb <= 1)
-      hipLaunchKernelGGL((k_down<R, 16, 1>), grid, dim3(kBlock), lds, st, a, pl, l, u_zero);
+      launch_k(k_down<R, 16, 1>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
     else
-      hipLaunchKernelGGL((k_down<R, 16, 2>), grid, dim3(kBlock), lds, st, a, pl, l, u_zero);
+      launch_k(k_down<R, 16, 2>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
   } else {
     if (nb <= 2)
-      hipLaunchKernelGGL((k_down<R, 32, 2>), grid, dim3(kBlock), lds, st, a, pl, l, u_zero);
+      launch_k(k_down<R, 32, 2>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
     else
-      hipLaunchKernelGGL((k_down<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, l, u_zero);
+      launch_k(k_down<R, 32, 3>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
   }
 }
 
 template <class R>
 static void launch_up(int ts, dim3 grid, hipStream_t st, const SolveArgs& a, const StreamPlan& pl, int l,
-                      int final_) {
+                      int final_, int slot) {
   const int hb = a.nu2, nb = blk_nb(ts, hb);
   const size_t lds = blk_lds_bytes<R>(ts, hb);
   if (ts == 16) {
-    hipLaunchKernelGGL((k_up<R, 16, 1>), grid, dim3(kBlock), lds, st, a, pl, l, final_);
+    hipLaunchKernelGGL((k_up<R, 16, 1>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
   } else {
     if (nb <= 1)
-      hipLaunchKernelGGL((k_up<R, 32, 1>), grid, dim3(kBlock), lds, st, a, pl, l, final_);
+      hipLaunchKernelGGL((k_up<R, 32, 1>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
     else if (nb == 2)
-      hipLaunchKernelGGL((k_up<R, 32, 2>), grid, dim3(kBlock), lds, st, a, pl, l, final_);
+      hipLaunchKernelGGL((k_up<R, 32, 2>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
     else
-      hipLaunchKernelGGL((k_up<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, l, final_);
+      hipLaunchKernelGGL((k_up<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
   }
 }
 static_assert(blk_nb(16, 5) <= 2 && blk_nb(16, 4) <= 1 && blk_nb(32, 5) <= 3 && blk_nb(32, 4) <= 3,
               "blocks per thread of the instantiated down/up kernels (nu <= 4)");
 
+// Cycles from the finest level: `ncyc` cycles with uniform flags (slot = kUniform: cycle
+// k starts from zero iff k = 0 and applies the Picard update iff k = ncyc - 1), or one
+// cycle in cycle slot `slot` (flags from each sample's state).
 template <class R>
-static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st, int ncyc, int slot) {
   const bool fp64 = sizeof(R) == 8;
   const int n = a.n;
   const int nc = n >> (a.nlev - 1);
@@ -854,28 +949,30 @@ static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStr
   // the Picard iteration, whose finest up leg applies the Picard update.
   auto cycle = [&](auto&& self, int l, bool zero, bool last) -> void {
     if (err != hipSuccess) return;
+    KernelTimer* tm = pl.timer;
     if (l == pl.ltop) {
-      hipLaunchKernelGGL((k_coarse_v<R, kCoarseThreads>), dim3((unsigned)a.S), dim3(kCoarseThreads), lcv, st, a,
-                         pl, zero ? 1 : 0, last ? 1 : 0);
+      const bool timed = tm && (tm->which & RMG_TIME_COARSE) && tm->ring[1].room();
+      hipEvent_t* ev = timed ? tm->ring[1].next() : nullptr;
+      StreamPlan plx = pl;
+      plx.tcells = timed ? tm->d_cells + 2 : nullptr;
+      launch_k(k_coarse_v<R, kCoarseThreads>, dim3((unsigned)a.S), dim3(kCoarseThreads), lcv, st, ev, a, plx,
+               zero ? 1 : 0, last ? 1 : 0, slot);
       return;
     }
     const int m = n >> l, ts = pl.ts[l];
     const unsigned tiles = (unsigned)((m / ts) * (m / ts));
-    KernelTimer* tm = pl.timer;
-    const bool timed = tm && tm->which == 1 && tm->tail - tm->head < tm->cap;
-    const int q = timed ? (int)(tm->tail % tm->cap) : 0;
+    const bool timed = tm && (tm->which & RMG_TIME_SMOOTHER_DOWN) && tm->ring[0].room();
+    hipEvent_t* ev = timed ? tm->ring[0].next() : nullptr;
     StreamPlan plx = pl;
     plx.tcells = timed ? tm->d_cells : nullptr;
-    if (timed && (err = hipEventRecord(tm->ev[2 * q], st)) != hipSuccess) return;
-    launch_down<R>(ts, dim3(tiles, (unsigned)a.S), st, a, plx, l, zero ? 1 : 0);
-    if (timed) {
-      if ((err = hipEventRecord(tm->ev[2 * q + 1], st)) != hipSuccess) return;
-      ++tm->tail;
-    }
+    launch_down<R>(ts, dim3(tiles, (unsigned)a.S), st, ev, a, plx, l, zero ? 1 : 0, slot);
     for (int k = 0; k < a.gamma; ++k) self(self, l + 1, k == 0, last);
-    launch_up<R>(ts, dim3(tiles, (unsigned)a.S), st, a, pl, l, (l == 0 && last) ? 1 : 0);
+    launch_up<R>(ts, dim3(tiles, (unsigned)a.S), st, a, pl, l, (l == 0 && last) ? 1 : 0, slot);
   };
-  for (int cyc = 0; cyc < a.cpp; ++cyc) cycle(cycle, 0, cyc == 0, cyc == a.cpp - 1);
+  if (slot >= 0)
+    cycle(cycle, 0, false, false);
+  else
+    for (int cyc = 0; cyc < ncyc; ++cyc) cycle(cycle, 0, cyc == 0, cyc == ncyc - 1);
   return err;
 }
 
@@ -897,23 +994,32 @@ static bool fused_fine_coarse(const SolveArgs& a, const StreamPlan& pl) {
 }
 
 template <class R>
-static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
+static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st, int J) {
   const dim3 blk(kBlock);
   const int n = a.n;
+  KernelTimer* tm = pl.timer;
   if constexpr (sizeof(R) == 4) {
     if (fused_fine_coarse<R>(a, pl)) {
-      hipLaunchKernelGGL((k_fine_coarse<R, kCoarseThreads, kFusedM>), dim3((unsigned)a.S), dim3(kCoarseThreads),
-                         fine_coarse_lds(n, n >> (a.nlev - 1)), st, a, pl);
+      const bool timed = tm && (tm->which & RMG_TIME_COARSE) && tm->ring[1].room();
+      StreamPlan plx = pl;
+      plx.tcells = timed ? tm->d_cells + 2 : nullptr;
+      launch_k(k_fine_coarse<R, kCoarseThreads, kFusedM>, dim3((unsigned)a.S), dim3(kCoarseThreads),
+               fine_coarse_lds(n, n >> (a.nlev - 1)), st, timed ? tm->ring[1].next() : nullptr, a, plx);
       return hipGetLastError();
     }
   }
   {
     const int T = n < kTile ? n : kTile;
     const unsigned tiles = (unsigned)((n / T) * (n / T));
-    hipLaunchKernelGGL(k_fine<R>, dim3(tiles, (unsigned)a.S), blk, 0, st, a, pl);
+    const bool timed = tm && (tm->which & RMG_TIME_FINE) && tm->ring[2].room();
+    StreamPlan plx = pl;
+    plx.tcells = timed ? tm->d_cells + 4 : nullptr;
+    launch_k(k_fine<R>, dim3(tiles, (unsigned)a.S), blk, 0, st, timed ? tm->ring[2].next() : nullptr, a, plx, J);
   }
-  const hipError_t err = stream_cycles<R>(a, pl, st);
-  if (err != hipSuccess) return err;
+  for (int j = 0; j < J; ++j) {
+    const hipError_t err = stream_cycles<R>(a, pl, st, 1, j);
+    if (err != hipSuccess) return err;
+  }
   return hipGetLastError();
 }
 
@@ -936,12 +1042,13 @@ hipError_t prepare_stream(const SolveArgs& a, const StreamPlan& pl) {
   return pl.fp64 ? set_stream_lds<double>(a, pl) : set_stream_lds<float>(a, pl);
 }
 
-hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
-  return pl.fp64 ? stream_iteration<double>(a, pl, st) : stream_iteration<float>(a, pl, st);
+hipError_t launch_stream_iteration(const SolveArgs& a, const StreamPlan& pl, hipStream_t st, int J) {
+  return pl.fp64 ? stream_iteration<double>(a, pl, st, J) : stream_iteration<float>(a, pl, st, J);
 }
 
 hipError_t launch_stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
-  const hipError_t e = pl.fp64 ? stream_cycles<double>(a, pl, st) : stream_cycles<float>(a, pl, st);
+  const hipError_t e = pl.fp64 ? stream_cycles<double>(a, pl, st, a.cpp, kUniform)
+                               : stream_cycles<float>(a, pl, st, a.cpp, kUniform);
   return e != hipSuccess ? e : hipGetLastError();
 }
 

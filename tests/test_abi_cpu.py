@@ -52,7 +52,7 @@ def test_null_context_is_rejected():
     _lib_path()
     L = _abi.lib()
     assert L.sample_fields(None, 16, 1, 8, None, None, None, 1, None, None) == _abi.RMG_EINVAL
-    assert L.rmg_ctx_create(None, 0) == _abi.RMG_EINVAL
+    assert L.rmg_ctx_create(None, 0, None) == _abi.RMG_EINVAL
 
 
 def test_host_kl_setup_matches_oracle():

@@ -43,6 +43,7 @@ def vg_problem(n_shift=0.0, alpha_shift=0.0, n_steps=N_STEPS):
     g = W.VG_INFILTRATION
     gpu = rmg.Problem(model=rmg.VGM, n_steps=n_steps, theta_r=g["theta_r"], theta_s=g["theta_s"],
                       h_top=g["h_top"], h_bottom=g["h_bottom"], h_init=g["h_init"], dt=g["dt"],
+                      init_profile=1, init_rate=g["init_rate"],
                       vg_n_shift=n_shift, vg_alpha_shift=alpha_shift)
     orc = dict(g, n_steps=n_steps)
     return gpu, orc

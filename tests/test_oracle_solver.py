@@ -253,3 +253,21 @@ def test_infiltration_initial_profile():
         assert abs(col[-1] + 0.4) < 1e-15 and abs(col[n // 2:] + 0.4).max() < 1e-9
         assert -0.4 * (1.0 - np.exp(-40.0 / n)) == pytest.approx(col[0], rel=1e-14)
     assert np.all(picard.initial_head(dict(W.GARDNER_INFILTRATION), 4) == -10.0)
+
+
+def test_fallback_attempt_reaches_the_fixed_point(kl_basis_small):
+    """A first attempt forced to fail (two Picard iterations allowed) is replaced by a second
+    attempt from the initial state with two V(2,2) per step; it converges to the sparse-LU
+    fixed point, and the reported counts are the failed attempt's followed by the second's."""
+    n = 16
+    Ks = _field(kl_basis_small, n, 9)
+    prob = dict(W.GARDNER_INFILTRATION, n_steps=2)
+    opts = dict(W.SOLVER, eps_picard=1e-13, max_picard=2, fallback_cycles=2, fallback_max_picard=400)
+    r = picard.solve(prob, {"Ks": Ks}, n, opts, mode="mg")
+    fixed = picard.solve(prob, {"Ks": Ks}, n, dict(W.SOLVER, eps_picard=1e-13, max_picard=400), mode="direct")
+    second = picard.solve(prob, {"Ks": Ks}, n, dict(W.SOLVER, eps_picard=1e-13, max_picard=400, cycles_per_picard=2),
+                          mode="mg")
+    assert r["status"] == 0 and r["attempts"] == 2 and fixed["status"] == 0
+    assert r["picard"] == [2] + second["picard"]
+    assert r["cycles"] == 2 + second["cycles"]
+    assert np.max(np.abs(r["p"] - fixed["p"])) <= 1e-10 * np.max(np.abs(fixed["p"]))

@@ -56,8 +56,11 @@ MLMC_5LEVEL = dict(workload_id=1, grids=(16, 32, 64, 128, 256),
 SMOOTHER_ROOF = dict(workload_id=9, n=512, n_samples=64)
 
 # van Genuchten-Mualem workload with three random fields and parametric
-# continuation (Section 2.1 eqs. Sw, sc_van, Krw; Section 3; Section 5.2):
-#   Ks    = exp(G_K),                 G_K a KL field of sigma^2 = 1.5;
+# continuation (Section 2.1 eqs. Sw, sc_van, Krw; Section 3; Section 5.2), on the
+# problem every MLMC experiment of Section 6 uses: the infiltration problem of
+# eq. travellingwave (p0 = -0.4 (1 - exp(-80 z)), p = -0.4 on top, 0.1 at the bottom,
+# no flux on the sides) with the baseline conductivity Ks_bl = 0.2:
+#   Ks    = 0.2 exp(G_K),             G_K a KL field of sigma^2 = 1.5;
 #   alpha = exp(mu_a + s_a G_a),      mean 2;
 #   n     = 1 + exp(mu_n + s_n G_n),  mean 1.6;
 # every G a unit-variance KL field of the exponential kernel with correlation
@@ -66,11 +69,13 @@ SMOOTHER_ROOF = dict(workload_id=9, n=512, n_samples=64)
 # (+-0.2 and +-0.05) with lognormal laws.  Continuation: level l of L + 1 solves
 # with n shifted by (L - l) * 0.1 (milder on coarse levels); the coarse member of
 # a level-l pair uses level l - 1's shift, as the fine member of pair l - 1 does.
+# Time grid: 50 steps of dt = 0.005 (T = 0.25; Section 6 integrates to T = 0.2).
 VG_SA2 = 0.003328
 VG_SN2 = 0.002312
+VG_KS_BASELINE = 0.2
 VG_FIELDS = dict(
     corr_len=0.2, n_modes=128,
-    marginals=((0.0, 0.0, float(np.sqrt(1.5))),                                   # Ks
+    marginals=((0.0, float(np.log(VG_KS_BASELINE)), float(np.sqrt(1.5))),        # Ks
                (0.0, float(np.log(2.0) - VG_SA2 / 2), float(np.sqrt(VG_SA2))),    # alpha
                (1.0, float(np.log(0.6) - VG_SN2 / 2), float(np.sqrt(VG_SN2)))),   # n
 )
@@ -78,9 +83,10 @@ VG_INFILTRATION = dict(
     model="vg",
     theta_r=0.05,
     theta_s=0.5,
-    h_top=0.0,
-    h_bottom=-10.0,
-    h_init=-10.0,
+    h_top=-0.4,
+    h_bottom=0.1,
+    h_init=-0.4,
+    init_rate=80.0,
     dt=0.005,
     n_steps=50,
 )
@@ -102,12 +108,12 @@ TRAVELLING_WAVE = dict(model="vg", theta_r=0.05, theta_s=0.5, h_top=-0.4, h_bott
                        init_rate=80.0, dt=1.0 / 64.0, n_steps=7, ks_baseline=0.2)
 SWEEP = dict(workload_id=4, n=32, samples_per_pair=64, n_modes=64, eps=1e-5, eps_mg=1e-5, max_picard=50)
 
-# Adaptive PC_MLMC (Algorithm 1) on the van Genuchten fields above: levels 32^2 .. 32 * 2^L
-# with n shifted by (L - l) * 0.1 on level l, warm-up pairs per level, tolerance eps of the
-# sampling error; dt = 0.005 as in MLMC_VG (the full hierarchy runs 6 levels to 1024^2 with
-# 100 steps and eps = 1e-3; the default benchmark run is the first four levels, 20 steps).
+# Adaptive PC_MLMC (Algorithm 1) on the van Genuchten workload above: six levels 32^2 ..
+# 1024^2 with n shifted by (L - l) * 0.1 on level l, 100 steps of dt = 0.0025 (the same
+# T = 0.25 as MLMC_VG), RMSE target 1e-3 (sampling tolerance and the eq. discErr bias
+# estimate), warm-up pairs per level.
 PC_MLMC_VG = dict(workload_id=5, grids=(32, 64, 128, 256, 512, 1024), warmup=(64, 32, 16, 8, 4, 4),
-                  n_shift_grad=0.1, n_steps_full=100, eps_full=1e-3)
+                  n_shift_grad=0.1, n_steps_full=100, dt_full=0.0025, eps_full=1e-3)
 
 # Adjoint sensitivities: the Gardner problem on 128 x 128 with 20 steps, Ks = exp(G) from a
 # 100-term KL expansion of the same covariance as KS_FIELD, 1024 samples; the quantity is
