@@ -627,6 +627,75 @@ def pcmlmc_eps_sweep(args, torch, rmg, W):
     print(json.dumps(res), flush=True)
 
 
+# ------------------------------------------------------------ KL field sampling
+def kl_bench(args, torch, rmg, W):
+    """The KL field sampling kernel (FP64 matrix-core GEMM G = xi B plus the lognormal
+    transform) at the two shapes the workloads sample: the adjoint workload's 1024 samples
+    of 128^2 with 100 modes, and the 5-level MLMC call's fields (every grid's fine and coarse
+    members, 64 modes).  One step = both shapes once.  FLOPs: 2 rows x modes x cells per
+    call (the exp epilogue not counted); bytes: basis + coefficients in, fields out."""
+    from paper_1903_08741_amd import kl_setup
+    dev = torch.device("cuda:0")
+    f = W.KS_FIELD
+    marg = [(0.0, f["log_mean"], f["scale"])]
+    jobs = []
+    cfg = W.ADJOINT_128
+    _, t3 = kl_setup.kl_tables(f["sigma2"], f["corr_len"], cfg["n_modes"], [cfg["n"]])
+    jobs.append((cfg["n"], torch.from_numpy(t3[cfg["n"]]).to(dev),
+                 torch.from_numpy(W.xi_draws(cfg["workload_id"], 0, range(cfg["n_samples"]), 1,
+                                             cfg["n_modes"])).to(dev)))
+    grids, samples = W.MLMC_5LEVEL["grids"], W.MLMC_5LEVEL["samples"]
+    _, t1 = kl_setup.kl_tables(f["sigma2"], f["corr_len"], f["n_modes"], list(grids))
+    for l, n in enumerate(grids):
+        S = samples[l] + (samples[l + 1] if l + 1 < len(grids) else 0)
+        jobs.append((n, torch.from_numpy(t1[n]).to(dev),
+                     torch.from_numpy(W.xi_draws(W.MLMC_5LEVEL["workload_id"], l, range(S), 1,
+                                                 f["n_modes"])).to(dev)))
+    outs = [torch.empty((x.shape[0], 1, n * n), dtype=torch.float64, device=dev) for n, _, x in jobs]
+    ctx = rmg.default_context(0)
+
+    def step():
+        for (n, B, x), o in zip(jobs, outs):
+            ctx.sample_fields(n, B, x, marg, out=o)
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(jobs))]
+    per = [0.0] * len(jobs)
+    for _ in range(args.steps):
+        for k, ((n, B, x), o) in enumerate(zip(jobs, outs)):
+            ev[2 * k].record()
+            ctx.sample_fields(n, B, x, marg, out=o)
+            ev[2 * k + 1].record()
+        torch.cuda.synchronize()
+        for k in range(len(jobs)):
+            per[k] += ev[2 * k].elapsed_time(ev[2 * k + 1])
+    rows = []
+    tot_ms = tot_flop = tot_bytes = 0.0
+    for k, (n, B, x) in enumerate(jobs):
+        ms = per[k] / args.steps
+        S, M, N = x.shape[0], x.shape[2], n * n
+        flop = 2.0 * S * M * N
+        byt = 8.0 * (M * N + S * M + S * N)
+        rows.append({"n": n, "rows": S, "modes": M, "ms": ms, "tflops": flop / ms / 1e9, "gbs": byt / ms / 1e6})
+        tot_ms, tot_flop, tot_bytes = tot_ms + ms, tot_flop + flop, tot_bytes + byt
+    big = rows[0]
+    res = {
+        "metric": "KL field sampling FP64 matrix-core TFLOP/s (G = xi B, then exp)",
+        "value": big["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": tot_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded standard normals; KL bases of the workloads)",
+        "config": {"workload": "sample_fields: 1024 x 100 modes x 128^2 (the adjoint workload) and the 5-level "
+                               "MLMC call's fields (64 modes, 16^2..256^2)", "shapes": rows,
+                   "mlmc_fields_ms": sum(r["ms"] for r in rows[1:])},
+        "roofline": {"bound": "mfma", "achieved": big["tflops"], "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": big["tflops"] / 78.6, "traffic": None, "kernel": "k_kl_fields (1024 x 100 x 16384)",
+                     "hbm_gbs": big["gbs"]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 # ------------------------------------------------------------ robustness sweep
 def sweep_bench(args, torch, rmg, W):
     """Section 4.3's robustness sweep as one batched solve: the 20 x 20 (alpha, n) pairs of
@@ -760,7 +829,7 @@ def coarse_bound(kt, levels_visited_per_launch=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("gardner", "vg", "adjoint", "sweep", "pcmlmc"), default="gardner",
+    ap.add_argument("--workload", choices=("gardner", "vg", "adjoint", "sweep", "pcmlmc", "kl"), default="gardner",
                     help="gardner: the 5-level Gardner MLMC workload (default); vg: the van Genuchten "
                          "workload with three fields and continuation (5 levels 32^2..512^2, infiltration "
                          "problem); adjoint: outflux gradients of 1024 samples of 128^2 (100 KL modes, 20 "
@@ -815,6 +884,9 @@ def main():
         return
     if args.workload == "sweep":
         sweep_bench(args, torch, rmg, W)
+        return
+    if args.workload == "kl":
+        kl_bench(args, torch, rmg, W)
         return
     if args.workload == "pcmlmc":
         if args.eps_sweep:

@@ -45,7 +45,8 @@ typedef enum {
 } rmg_status;
 
 /* Per-sample outcome (Section 4.3: a sample fails when the Picard iteration
- * exceeds its iteration limit at some time step). */
+ * exceeds its iteration limit at some time step).  NONFINITE: a correction was not
+ * finite, or the sample's fields hold a non-finite value (such a sample is not solved). */
 typedef enum {
   RMG_SAMPLE_OK = 0,
   RMG_SAMPLE_MAXITER = 1,
@@ -101,8 +102,9 @@ typedef struct {
   int32_t cycle;              /* rmg_cycle: V (one coarse cycle per level visit) or W (two) */
   int32_t nu1, nu2;           /* pre/post red-black Gauss-Seidel sweeps, each 0..4, not both 0 */
   int32_t cycles_per_picard;  /* fixed number of cycles per Picard step, 1..16; 0: cycle until
-                                 max_c |f - A dp| < eps_mg (at most 200 cycles; the residual in the
-                                 smoother precision; whole-sample grids only, otherwise RMG_EINVAL) */
+                                 max_c |f - A dp| < eps_mg (Section 4.2; at most 200 cycles; the residual
+                                 on the finest level in the smoother precision, checked after every
+                                 cycle) */
   int32_t max_picard;         /* Picard iterations allowed per time step, >= 1 */
   int32_t coarsest_n;         /* coarsest grid size, 2 or 4, solved exactly in FP64 */
   int32_t flags;              /* bit 0: force the level-streaming path (no whole-sample-in-LDS kernel);
@@ -337,6 +339,22 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
                       int32_t* d_status, rmg_sample_stats* d_stats, hipStream_t stream);
 
 /*
+ * picard_mg_outflux - the quantity of picard_mg_adjoint without its gradient: the forward
+ * solve of the same samples (fields from d_xi through eqs. KLexp, RandK), keeping every
+ * step's pressure head in the workspace (S (n_steps + 1) n^2 doubles), and
+ *   Q = sum_{k=1}^{n_steps} dt F(p^k),  F(p) = h sum_i K_i0 ((p_i0 - h_bottom) / (h/2) + 1),
+ * reduced in the same order as picard_mg_adjoint, so for the same inputs and options the
+ * two return the same Q bit for bit.  d_q [S] (NaN for a failed sample), d_status [S],
+ * d_stats [S] or NULL.  Arguments, ranges and errors as picard_mg_adjoint (without the
+ * checkpoint and adjoint tolerance arguments).  This is the forward pass of the
+ * differentiable outflux in the Python binding; its backward pass calls picard_mg_adjoint.
+ */
+int picard_mg_outflux(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+                      int n_modes, const double* d_basis, const rmg_marginal* h_marg, const double* d_xi,
+                      int64_t S, double* d_q, int32_t* d_status, rmg_sample_stats* d_stats,
+                      hipStream_t stream);
+
+/*
  * Adaptive multilevel estimator with parametric continuation (PC_MLMC,
  * Section 5.1: Algorithm 1, eqs. errMLMC, MLMCopt and MLMCSAMP; bias estimate
  * eq. discErr of Section 6).
@@ -392,12 +410,16 @@ typedef struct {
   double mean;                  /* multilevel estimate of E[Q_L] (eq. MLMCestimator) */
   double var;                   /* multilevel estimate of V[Q_L] (eq. ML_var) */
   double sampling_err2;         /* sum_l V_l / N_l with N_l the successful pairs (eq. MLMCVar) */
-  double bias;                  /* sqrt(mean over pairs of Y_L^2) / (2^a - 1) (eq. discErr, s = 2) */
+  double bias;                  /* eq. discErr with s = 2: sqrt(mean of (Q_{h_L} - Q_{h_{L-1}})^2) / (2^a - 1),
+                                   both grids under the finest level's parameter set Theta_L (eq.
+                                   numErr); when level L's coarse member uses Theta_{L-1}
+                                   (continuation), from bias_pairs further pairs of level L */
   double total_cost;            /* sum_l drawn_l W_l */
   double wall_ms;               /* wall time of the whole call */
   int32_t rounds;               /* updates of N_l performed */
   int32_t converged;            /* 1 if sampling_err2 <= eps^2 with no pair left to draw */
   int64_t calls;                /* batched mlmc_level_estimate calls made */
+  int64_t bias_pairs;           /* pairs of level L drawn for the bias (numbers drawn_L, ...), or 0 */
 } rmg_pc_result;
 
 /*

@@ -23,9 +23,13 @@ Readings where the paper is silent:
   - W_l in work units is multigrid cycles times cells of both members of a pair
     (Section 4.3 measures cost in cycles), over the pairs drawn in the warm-up
     (failed pairs included: their work was spent);
-  - the bias estimate applies eq. discErr with mesh ratio s = 2 to the finest
-    correction: sqrt(mean of Y_L^2) / (2^a - 1), the scalar-QoI form of its
-    L2(Omega; D) norm.
+  - the bias estimate applies eq. discErr with mesh ratio s = 2 to the finest grid
+    and the next coarser one under the same parameter set Theta_L (eq. numErr fixes
+    Theta_L): sqrt(mean of (Q_{h_L} - Q_{h_{L-1}})^2) / (2^a - 1), the scalar-QoI form
+    of its L2(Omega; D) norm.  With continuation the finest level's own pairs compare
+    Theta_L with Theta_{L-1}, so max(2, N_L) further pairs of the finest level (numbers
+    continuing its numbering, failed ones replaced) are solved with Theta_L on both
+    grids; without continuation at the top the level's own pairs serve.
 """
 from __future__ import annotations
 
@@ -36,7 +40,7 @@ import numpy as np
 from . import mlmc
 
 
-def run(sample_pair, grids, warmup, eps, bias_rate=1.0, max_rounds=50, max_pairs=1 << 40):
+def run(sample_pair, grids, warmup, eps, bias_rate=1.0, max_rounds=50, max_pairs=1 << 40, bias_pair=None):
     """Algorithm 1.
 
     sample_pair(level, i) -> (q_fine, q_coarse, cycles_fine, cycles_coarse) for pair i of
@@ -44,8 +48,11 @@ def run(sample_pair, grids, warmup, eps, bias_rate=1.0, max_rounds=50, max_pairs
         failed solve), cycles_* their multigrid cycle counts.
     grids: [(n_fine, n_coarse)] per level, n_coarse = 0 on level 0.
     warmup: N*_l per level.
+    bias_pair(i) -> (q_fine, q_coarse) of pair i of the finest level with the finest
+        level's parameter set on both grids; None when the hierarchy has no continuation
+        at the top (the finest level's pairs then serve for the bias).
     Returns dict(levels=[dict(drawn, target, W, V, mean, sums, q_fine, q_coarse)], mean,
-    var, sampling_err2, bias, rounds, converged).
+    var, sampling_err2, bias, bias_pairs, rounds, converged).
     """
     L = len(grids)
     qf = [[] for _ in range(L)]
@@ -98,8 +105,21 @@ def run(sample_pair, grids, warmup, eps, bias_rate=1.0, max_rounds=50, max_pairs
     est = mlmc.combine(S)
     V = [max(0.0, v) for v in est["level_var"]]
     err2 = math.fsum(V[l] / S[l]["n"] for l in range(L))
-    bias = (math.sqrt(S[-1]["sY2"] / S[-1]["n"]) / (2.0 ** bias_rate - 1.0)) if L > 1 else float("nan")
+    bias, nb = float("nan"), 0
+    if L > 1:
+        sb = S[-1]
+        if bias_pair is not None:
+            bf, bc = [], []
+            want = max(2, target[-1])
+            while mlmc.level_sums(bf, bc)["n"] < want and drawn[-1] + nb < max_pairs:
+                a, b = bias_pair(drawn[-1] + nb)
+                bf.append(a)
+                bc.append(b)
+                nb += 1
+            sb = mlmc.level_sums(bf, bc)
+        if sb["n"]:
+            bias = math.sqrt(sb["sY2"] / sb["n"]) / (2.0 ** bias_rate - 1.0)
     levels = [dict(drawn=drawn[l], target=target[l], W=W[l], V=V[l], mean=mlmc.mc_mean(S[l]), sums=S[l],
                    q_fine=np.array(qf[l]), q_coarse=np.array(qc[l]) if l else None) for l in range(L)]
-    return dict(levels=levels, mean=est["mean"], var=est["var"], sampling_err2=err2, bias=bias, rounds=rounds,
-                converged=converged and err2 <= eps * eps * (1 + 1e-12))
+    return dict(levels=levels, mean=est["mean"], var=est["var"], sampling_err2=err2, bias=bias, bias_pairs=nb,
+                rounds=rounds, converged=converged and err2 <= eps * eps * (1 + 1e-12))

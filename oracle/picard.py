@@ -115,6 +115,11 @@ def solve(problem, fields, n, opts, mode="mg", p0=None, record=False):
     Returns dict(p, status, picard (per-step counts of every attempt), cycles, dp_last,
     outflux, history, attempts).
     """
+    if not all(np.all(np.isfinite(v)) for v in fields.values()):
+        # input validation: fields with a non-finite value are not solved
+        p = initial_head(problem, n) if p0 is None else np.array(p0, dtype=np.float64)
+        return dict(p=p, status=STATUS_NONFINITE, picard=[], cycles=0, dp_last=float("nan"), outflux=0.0,
+                    history=[], attempts=1)
     r = _integrate(problem, fields, n, opts, mode, p0, record)
     r["attempts"] = 1
     fb = opts.get("fallback_cycles", 0)

@@ -246,6 +246,28 @@ class Context:
         st = _decode_stats(stats)
         return dict(q=q, grad=grad, status=status, stats_forward=st[:S], stats_adjoint=st[S:], rc=rc)
 
+    def picard_mg_outflux(self, n, basis, xi, marginal, problem: Problem, opts: SolverOpts, stream=None):
+        """Time-integrated bottom outflux Q per sample by the forward solve alone (the Q of
+        picard_mg_adjoint, bit for bit).  Returns dict(q [S], status [S], stats, rc)."""
+        torch = _torch()
+        S, M = xi.shape
+        _check_dev(xi, "xi", torch.float64, (S, M))
+        _check_dev(basis, "basis", torch.float64, (M, n * n))
+        dev = xi.device
+        q = torch.empty(S, dtype=torch.float64, device=dev)
+        status = torch.empty(S, dtype=torch.int32, device=dev)
+        stats = torch.empty(S * C.sizeof(_abi.SampleStats), dtype=torch.uint8, device=dev)
+        pr = problem.c()
+        pr.qoi = _abi.QOI_BOTTOM_OUTFLUX
+        op = opts.c()
+        mg = _abi.Marginal(*marginal)
+        rc = self._lib.picard_mg_outflux(self._h, int(n), C.byref(pr), C.byref(op), int(M),
+                                         C.c_void_p(basis.data_ptr()), C.byref(mg), C.c_void_p(xi.data_ptr()),
+                                         int(S), C.c_void_p(q.data_ptr()), C.c_void_p(status.data_ptr()),
+                                         C.c_void_p(stats.data_ptr()), _stream_ptr(stream))
+        self._raise(rc, allow_notconv=True)
+        return dict(q=q, status=status, stats=_decode_stats(stats), rc=rc)
+
     def pc_mlmc(self, levels, marginals, opts: SolverOpts, eps: float, xi_source, bias_rate=1.0,
                 cost_model=_abi.COST_WORK, max_rounds=50, max_pairs=1 << 40, max_pairs_per_call=0,
                 stream=None):
@@ -295,7 +317,7 @@ class Context:
             raise failure[0]
         self._raise(rc, allow_notconv=True)
         out = {k: getattr(res, k) for k in ("mean", "var", "sampling_err2", "bias", "total_cost", "wall_ms",
-                                            "rounds", "converged", "calls")}
+                                            "rounds", "converged", "calls", "bias_pairs")}
         out["levels"] = [dict(drawn=o.drawn, target=o.target, W=o.W, V=o.V, mean=o.mean,
                               sums=_decode_sums(o.sums)) for o in lout]
         out["rc"] = rc
@@ -360,22 +382,28 @@ def _make_outflux_fn():
     class OutfluxFn(torch.autograd.Function):
         """Q(xi) = time-integrated bottom outflux of every sample, differentiable in xi.
 
-        The C entry point runs the forward solve and the adjoint sweep (with its
-        checkpoints) in one call, so the forward pass stores dQ/dxi and the backward
-        pass only scales it by the incoming gradient."""
+        The forward pass is the forward solve alone (picard_mg_outflux); the backward pass
+        runs the discrete adjoint (picard_mg_adjoint: forward with checkpoints, then the
+        adjoint sweep) for the saved inputs and scales dQ/dxi by the incoming gradient.  A
+        forward under torch.no_grad() therefore costs one forward solve."""
 
         @staticmethod
         def forward(ctx, xi, basis, n, marginal, problem, opts, ckpt_every, eps_adjoint):
-            out = picard_mg_adjoint(n, basis, xi.detach().contiguous(), marginal, problem, opts,
-                                    ckpt_every=ckpt_every, eps_adjoint=eps_adjoint)
-            ctx.save_for_backward(out["grad"])
+            xd = xi.detach().contiguous()
+            dev = xd.device.index or 0
+            out = default_context(dev).picard_mg_outflux(n, basis, xd, marginal, problem, opts)
+            ctx.save_for_backward(xd, basis)
+            ctx.args = (n, marginal, problem, opts, ckpt_every, eps_adjoint)
             ctx.status = out["status"]
             return out["q"]
 
         @staticmethod
         def backward(ctx, gq):
-            (grad,) = ctx.saved_tensors
-            return gq[:, None] * grad, None, None, None, None, None, None, None
+            xd, basis = ctx.saved_tensors
+            n, marginal, problem, opts, ckpt_every, eps_adjoint = ctx.args
+            out = picard_mg_adjoint(n, basis, xd, marginal, problem, opts, ckpt_every=ckpt_every,
+                                    eps_adjoint=eps_adjoint)
+            return gq[:, None] * out["grad"], None, None, None, None, None, None, None
 
     return OutfluxFn
 

@@ -32,7 +32,7 @@ COST_WORK, COST_TIME = 0, 1
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
             "rmg_ctx_set_workspace_limit", "sample_fields", "picard_mg_solve", "mlmc_level_estimate",
             "rmg_set_kernel_timing", "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples",
-            "picard_mg_adjoint")
+            "picard_mg_adjoint", "picard_mg_outflux")
 
 
 class Marginal(C.Structure):
@@ -96,7 +96,8 @@ class PcLevelOut(C.Structure):
 class PcResult(C.Structure):
     _fields_ = [("mean", C.c_double), ("var", C.c_double), ("sampling_err2", C.c_double),
                 ("bias", C.c_double), ("total_cost", C.c_double), ("wall_ms", C.c_double),
-                ("rounds", C.c_int32), ("converged", C.c_int32), ("calls", C.c_int64)]
+                ("rounds", C.c_int32), ("converged", C.c_int32), ("calls", C.c_int64),
+                ("bias_pairs", C.c_int64)]
 
 
 # int (*rmg_xi_source)(void* user, int level, int64_t first, int64_t count, double* h_xi)
@@ -149,6 +150,9 @@ def lib():
     L.picard_mg_adjoint.argtypes = [vp, i32, C.POINTER(Problem), C.POINTER(SolverOpts), i32, vp,
                                     C.POINTER(Marginal), vp, i64, i32, C.c_double, vp, vp, vp, vp, vp]
     L.picard_mg_adjoint.restype = i32
+    L.picard_mg_outflux.argtypes = [vp, i32, C.POINTER(Problem), C.POINTER(SolverOpts), i32, vp,
+                                    C.POINTER(Marginal), vp, i64, vp, vp, vp, vp]
+    L.picard_mg_outflux.restype = i32
     L.pc_mlmc.argtypes = [vp, i32, C.POINTER(PcLevel), i32, i32, C.POINTER(Marginal), C.POINTER(SolverOpts),
                           C.POINTER(PcOpts), XiSource, vp, C.POINTER(PcLevelOut), C.POINTER(PcResult), vp]
     L.pc_mlmc.restype = i32

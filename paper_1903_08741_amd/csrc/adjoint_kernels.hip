@@ -473,6 +473,23 @@ hipError_t launch_adj_grad_final(const SolveArgs& a, const StreamPlan& pl, const
   return hipGetLastError();
 }
 
+// Q = sum_k dt F(p^k) of the forward solve alone (the sum of k_adj_finish, in the same
+// order), NaN for a sample the forward solve did not converge on.
+__global__ void k_outflux_total(SolveArgs a, AdjArgs ad, const int32_t* fwd_status, double* q) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  const rmg_problem& P = class_problem(a.cp, s);
+  double Q = 0.0;
+  for (int k = 0; k < ad.n_steps; ++k) Q += P.dt * ad.qn[s * ad.n_steps + k];
+  q[s] = fwd_status[s] == RMG_SAMPLE_OK ? Q : __longlong_as_double(0x7ff8000000000000ll);
+}
+
+hipError_t launch_outflux_total(const SolveArgs& a, const AdjArgs& ad, const int32_t* fwd_status, double* q,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_outflux_total, dim3(per_sample_blocks(a.S)), dim3(kBlock), 0, st, a, ad, fwd_status, q);
+  return hipGetLastError();
+}
+
 hipError_t launch_adj_outflux(const SolveArgs& a, const AdjArgs& ad, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_outflux, dim3((unsigned)a.S, (unsigned)(ad.hi - ad.lo + 1)), dim3(kBlock), 0, st, a,
                      ad);

@@ -212,7 +212,7 @@ size_t class_ws_bytes(const ClassJob& j) {
   size_t b = 256 + 8 * (size_t)S * n * n;  // theta_old
   if (!j.whole) {
     for (int l = 0; l <= j.pl.ltop; ++l) b += 256 * 7 + level_bytes(n >> l, S, j.fp64);
-    b += 6 * 256 + 2 * (sizeof(SampleState) * S + 8 * S + 8);
+    b += 7 * 256 + 2 * (sizeof(SampleState) * S + 8 * S + 8) + 8 * S;
   }
   return b;
 }
@@ -239,6 +239,7 @@ void class_carve(ClassJob& j, Arena& ar) {
   j.pl.dpmax_prev = (unsigned long long*)ar.take(8 * S);
   j.pl.active_count = (int32_t*)ar.take(8);
   j.pl.count_next = (int32_t*)ar.take(8);
+  j.pl.mgres = j.a.cpp == 0 ? (unsigned long long*)ar.take(8 * S) : nullptr;
 }
 
 void class_plan(ClassJob& j, const rmg_solver_opts* o) {
@@ -329,10 +330,11 @@ int autotune_class(rmg_ctx* ctx, ClassJob& j) {
     set_tiles(j, c[0], c[1]);
     const StreamPlan odd = flip(j.pl);
     HIP_TRY(ctx, launch_stream_init(j.a, j.pl, j.stream));
-    HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream, j.a.cpp));
-    HIP_TRY(ctx, launch_stream_iteration(j.a, odd, j.stream, j.a.cpp));
+    const int J = std::max(1, j.a.cpp);
+    HIP_TRY(ctx, launch_stream_iteration(j.a, j.pl, j.stream, J));
+    HIP_TRY(ctx, launch_stream_iteration(j.a, odd, j.stream, J));
     HIP_TRY(ctx, hipEventRecord(ctx->tev[0], j.stream));
-    for (int i = 0; i < 4; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, (i & 1) ? odd : j.pl, j.stream, j.a.cpp));
+    for (int i = 0; i < 4; ++i) HIP_TRY(ctx, launch_stream_iteration(j.a, (i & 1) ? odd : j.pl, j.stream, J));
     HIP_TRY(ctx, hipEventRecord(ctx->tev[1], j.stream));
     HIP_TRY(ctx, hipEventSynchronize(ctx->tev[1]));
     float ms = 0.f;
@@ -451,7 +453,9 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs, int 
     j.done = true;
   }
   // cycle slots per pass: primary, and with a sample in the fallback attempt
-  auto slots = [](const ClassJob& j, int v) { return v == 0 ? j.a.cpp : std::max(j.a.cpp, j.a.fb_cpp); };
+  auto slots = [](const ClassJob& j, int v) {
+    return v == 0 ? std::max(1, j.a.cpp) : std::max(j.a.cpp, j.a.fb_cpp);
+  };
   auto nvar = [](const ClassJob& j) { return j.a.fb_cpp > j.a.cpp ? 2 : 1; };
   // per class and slot variant v: a graph of the batch's G passes (index 4c + 2v) and,
   // with timing, one of its last G - 1 (4c + 2v + 1)
@@ -504,8 +508,8 @@ int run_classes(rmg_ctx* ctx, std::vector<ClassJob>& jobs, bool use_graphs, int 
   std::vector<std::array<RingMarks, D>> mark(jobs.size());
   auto bound = [&](const ClassJob& j) {
     const int64_t steps = std::max(j.a.cp.prob[0].n_steps, j.a.cp.prob[1].n_steps);
-    return steps * ((int64_t)j.a.max_picard * std::max(1, j.a.cpp) + (int64_t)j.a.fb_max_picard * j.a.fb_cpp) +
-           (int64_t)(D + 1) * G;
+    const int64_t cyc = j.a.cpp > 0 ? j.a.cpp : kMaxMgCycles;
+    return steps * ((int64_t)j.a.max_picard * cyc + (int64_t)j.a.fb_max_picard * j.a.fb_cpp) + (int64_t)(D + 1) * G;
   };
   auto issue = [&](size_t c) -> hipError_t {
     ClassJob& j = jobs[c];
@@ -881,9 +885,6 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
   j.a.status = d_status;
   j.a.stats = d_stats;
   class_plan(j, opts);
-  if (!j.whole && opts->cycles_per_picard == 0)
-    return fail(ctx, RMG_EINVAL, "grid %d: the residual-controlled cycle count (cycles_per_picard = 0) is built "
-                "for the whole-sample kernel only (grids up to 32 x 32, or 64 x 64 with flag bit 5)", j.a.n);
   // the solve runs on a context stream ordered after the caller's stream (a
   // captured graph cannot be recorded on the legacy default stream)
   j.stream = ctx->side[0];
@@ -956,8 +957,6 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
   fj.a.eps = opts->eps_picard;
   fj.a.eps_mg = opts->eps_mg;
   class_plan(fj, opts);
-  if (!fj.whole && opts->cycles_per_picard == 0)
-    return fail(ctx, RMG_EINVAL, "grid %d: cycles_per_picard = 0 needs the whole-sample kernel", n);
   ClassJob aj = fj;
   rmg_solver_opts aopts = *opts;
   aopts.flags |= 1 | 8;  // level streaming, fixed tiles
@@ -1089,6 +1088,105 @@ int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg
   return RMG_OK;
 }
 
+int picard_mg_outflux(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts, int n_modes,
+                      const double* d_basis, const rmg_marginal* h_marg, const double* d_xi, int64_t S,
+                      double* d_q, int32_t* d_status, rmg_sample_stats* d_stats, hipStream_t stream) {
+  if (!ctx) return RMG_EINVAL;
+  ctx->err.clear();
+  if (!pow2_in(n, 4, 1024)) return fail(ctx, RMG_EINVAL, "n=%d must be a power of two in 4..1024", n);
+  if (S < 1 || S > 65535) return fail(ctx, RMG_EINVAL, "S=%lld not in 1..65535", (long long)S);
+  if (n_modes < 1 || n_modes > 1024) return fail(ctx, RMG_EINVAL, "n_modes=%d not in 1..1024", n_modes);
+  if (!problem || !d_basis || !h_marg || !d_xi || !d_q || !d_status) return fail(ctx, RMG_EINVAL, "NULL pointer");
+  if (problem->model != RMG_GARDNER && problem->model != RMG_LINEAR)
+    return fail(ctx, RMG_EINVAL, "the outflux entry point supports the Gardner and linear closures only");
+  if (problem->qoi != RMG_QOI_BOTTOM_OUTFLUX)
+    return fail(ctx, RMG_EINVAL, "problem->qoi must be RMG_QOI_BOTTOM_OUTFLUX (%d)", (int)RMG_QOI_BOTTOM_OUTFLUX);
+  rmg_problem fprob = *problem;
+  fprob.qoi = RMG_QOI_MEAN_SATURATION;
+  int rc = check_problem(ctx, &fprob, 1);
+  if (rc) return rc;
+  if ((rc = check_opts(ctx, opts, n))) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int64_t N = (int64_t)n * n;
+  const int nst = problem->n_steps, slots = nst + 1;
+  std::vector<ClassJob> fjobs(1);
+  ClassJob& fj = fjobs[0];
+  fj.a.n = n;
+  fj.a.lg = ilog2i(n);
+  fj.a.nlev = ilog2i(n) - ilog2i(opts->coarsest_n) + 1;
+  fj.a.F = 1;
+  fj.a.S = S;
+  fj.a.cp.prob[0] = fprob;
+  fj.a.cp.prob[1] = fprob;
+  fj.a.cp.seg_split = S;
+  fj.a.nu1 = opts->nu1;
+  fj.a.nu2 = opts->nu2;
+  fj.a.gamma = opts->cycle == RMG_CYCLE_W ? 2 : 1;
+  fj.a.cpp = opts->cycles_per_picard;
+  fj.a.max_picard = opts->max_picard;
+  fj.a.eps = opts->eps_picard;
+  fj.a.eps_mg = opts->eps_mg;
+  class_plan(fj, opts);
+  // every step's pressure head is kept (the history is what the outflux is summed from)
+  double *fields = nullptr, *p = nullptr, *fq = nullptr, *hist = nullptr, *qn = nullptr;
+  rmg_sample_stats* fstats = nullptr;
+  auto carve_all = [&](Arena& ar) {
+    fields = (double*)ar.take(8 * S * N);
+    p = (double*)ar.take(8 * S * N);
+    fq = (double*)ar.take(8 * S);
+    fstats = (rmg_sample_stats*)ar.take(sizeof(rmg_sample_stats) * S);
+    hist = (double*)ar.take(8 * S * slots * N);
+    qn = (double*)ar.take(8 * S * nst);
+    class_carve(fj, ar);
+  };
+  Arena dry;
+  carve_all(dry);
+  if ((rc = reserve(ctx, dry.off + 256))) return rc;
+  Arena ar;
+  ar.base = (char*)ctx->ws;
+  ar.cap = ctx->ws_cap;
+  carve_all(ar);
+  if (ar.off > ar.cap) return fail(ctx, RMG_ENOMEM, "internal error: workspace accounting (%zu > %zu)", ar.off, ar.cap);
+  hipStream_t st = ctx->side[0];
+  fj.stream = st;
+  fj.h_count = ctx->h_count;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
+  HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->ev[0], 0));
+  HIP_TRY(ctx, launch_kl_fields((int)N, n_modes, S, 1, d_basis, d_xi, h_marg, fields, st));
+  fj.a.fields = fields;
+  fj.a.p = p;
+  fj.a.qoi = fq;
+  fj.a.status = d_status;
+  fj.a.stats = d_stats ? d_stats : fstats;
+  fj.a.p_hist = hist;
+  fj.a.hist_every = 1;
+  fj.a.hist_slots = slots;
+  if ((rc = run_classes(ctx, fjobs, !(opts->flags & 2)))) return rc;
+  AdjArgs ad{};
+  ad.hist = hist;
+  ad.slots = slots;
+  ad.base = 0;
+  ad.lo = 1;
+  ad.hi = nst;
+  ad.n_steps = nst;
+  ad.qn = qn;
+  HIP_TRY(ctx, launch_adj_outflux(fj.a, ad, st));
+  HIP_TRY(ctx, launch_outflux_total(fj.a, ad, d_status, d_q, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
+  HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1], 0));
+  int32_t sv[1024];
+  bool all_ok = true;
+  for (int64_t s0 = 0; s0 < S && all_ok; s0 += 1024) {
+    const int64_t k = std::min<int64_t>(1024, S - s0);
+    HIP_TRY(ctx, hipMemcpyAsync(sv, d_status + s0, sizeof(int32_t) * k, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    for (int64_t q = 0; q < k; ++q)
+      if (sv[q] != RMG_SAMPLE_OK) all_ok = false;
+  }
+  if (!all_ok) return fail(ctx, RMG_ENOTCONV, "some samples did not converge");
+  return RMG_OK;
+}
+
 int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fields, int n_modes,
                         const rmg_marginal* h_marg, const rmg_solver_opts* opts, rmg_level_sums* h_out,
                         double* d_qoi_out, hipStream_t stream) {
@@ -1164,9 +1262,6 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
     j.a.eps = opts->eps_picard;
   j.a.eps_mg = opts->eps_mg;
     class_plan(j, opts);
-    if (!j.whole && opts->cycles_per_picard == 0)
-      return fail(ctx, RMG_EINVAL, "grid %d: the residual-controlled cycle count (cycles_per_picard = 0) is "
-                  "built for the whole-sample kernel only (grids up to 32 x 32, or 64 x 64 with flag bit 5)", n);
     jobs.push_back(j);
     jn.push_back(n);
   }

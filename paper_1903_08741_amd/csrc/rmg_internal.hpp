@@ -10,6 +10,9 @@ namespace rmg {
 
 constexpr int kMaxLevels = 12;
 constexpr int kMaxMgCycles = 200;  // cap of the residual-controlled cycle count
+// the per-sample cycle count of residual-controlled cycling: above the cap, so that no
+// cycle slot is ever the sample's last (the residual check applies the correction)
+constexpr int kMgCpp = kMaxMgCycles + 1;
 constexpr int kTile = 32;       // output tile edge of the level-streaming kernels
 #ifndef RMG_COARSE_TOP_F32
 #define RMG_COARSE_TOP_F32 64
@@ -35,6 +38,8 @@ struct SampleState {
   int32_t cyc0;    // cycles of the current iteration done before this pass
   int32_t jpass;   // cycle slots of the pass that last wrote this state
   int32_t attempt; // 0: primary setting; 1: fallback setting (restarted from the initial state)
+  int32_t mgdone;  // residual-controlled cycling (cpp option 0): the iteration's correction
+                   // met eps_mg (or the cycle cap) and was applied in the pass that wrote this
 };
 
 // Slot argument of the cycle kernels: kUniform runs the cycle for every active sample
@@ -47,6 +52,8 @@ __device__ __forceinline__ bool slot_runs(const SampleState& st, int slot) {
 __device__ __forceinline__ bool slot_first(const SampleState& st, int slot, int uniform_flag) {
   return slot < 0 ? uniform_flag != 0 : st.cyc0 + slot == 0;
 }
+// (with residual-controlled cycling no cycle is known to be the last one: the correction
+// is applied by the residual check after each cycle, so slot_last is false there)
 __device__ __forceinline__ bool slot_last(const SampleState& st, int slot, int uniform_flag) {
   return slot < 0 ? uniform_flag != 0 : st.cyc0 + slot + 1 == st.cpp;
 }
@@ -162,6 +169,7 @@ struct StreamPlan {
   SampleState* state_prev;
   unsigned long long* dpmax;
   unsigned long long* dpmax_prev;
+  unsigned long long* mgres;  // residual-controlled cycling: max |f - A dp| of the pass's cycle
   int32_t* active_count;  // [0]: active samples, [1]: of them in the fallback attempt
   int32_t* count_next;    // the counters of the next iteration (cleared by this one)
   KernelTimer* timer;               // host object, never dereferenced on the device
@@ -203,6 +211,9 @@ hipError_t launch_adj_iteration(const SolveArgs& a, const StreamPlan& pl, const 
 // Gradient terms still pending when the segment's loop ended.
 hipError_t launch_adj_grad_final(const SolveArgs& a, const StreamPlan& pl, const AdjArgs& ad, hipStream_t st);
 hipError_t launch_adj_outflux(const SolveArgs& a, const AdjArgs& ad, hipStream_t st);
+// Q[s] = sum_k dt qn[s][k] of a forward solve (NaN where fwd_status is not OK).
+hipError_t launch_outflux_total(const SolveArgs& a, const AdjArgs& ad, const int32_t* fwd_status, double* q,
+                                hipStream_t st);
 hipError_t launch_adj_finish(const SolveArgs& a, const StreamPlan& pl, const AdjArgs& ad, const int32_t* fwd_status,
                              double* q, int32_t* status, rmg_sample_stats* stats, hipStream_t st);
 // dQ/dxi[s][j] = sum_c B[j][c] g[s][c] scale (Ks - shift) / Ks (NaN for failed samples).

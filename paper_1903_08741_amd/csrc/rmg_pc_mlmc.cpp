@@ -291,8 +291,48 @@ int pc_mlmc(rmg_ctx* ctx, int n_levels, const rmg_pc_level* L, int n_fields, int
   res->mean = val(mean);
   res->var = val(var);
   res->sampling_err2 = err2;
-  const rmg_level_sums& sl = out[n_levels - 1].sums;
-  res->bias = n_levels > 1 ? std::sqrt(val(sl.sY2) / (double)sl.n) / (std::pow(2.0, pc->bias_rate) - 1.0) : NAN;
+  // Bias (eq. discErr with s = 2): the finest grid against the next coarser one under the
+  // same parameter set Theta_L (eq. numErr fixes Theta_L).  With continuation the finest
+  // level's coarse member solves Theta_{L-1}, so further pairs of the finest level (their
+  // numbers continue the level's) are solved with Theta_L on both grids, as many as the
+  // level's N_L (at least 2); without it the level's own pairs serve.
+  res->bias = NAN;
+  if (n_levels > 1) {
+    const int lt = n_levels - 1;
+    rmg_level_sums bs{};
+    if (std::memcmp(&L[lt].coarse, &L[lt].fine, sizeof(rmg_problem)) == 0) {
+      bs = out[lt].sums;
+    } else {
+      const int64_t want = std::max<int64_t>(2, out[lt].target);
+      while (bs.n < want && out[lt].drawn + res->bias_pairs < pc->max_pairs) {
+        const int64_t first = out[lt].drawn + res->bias_pairs;
+        const int64_t cnt = std::min({want - bs.n, cap[lt], pc->max_pairs - first});
+        double* h = st.h + xoff[lt];
+        if (xi(user, lt, first, cnt, h) != 0)
+          return err(ctx, RMG_EINVAL, "pc_mlmc: the random-input source failed (level %d, pairs %lld..%lld)", lt,
+                     (long long)first, (long long)(first + cnt - 1));
+        if (hipMemcpyAsync(st.d + xoff[lt], h, 8 * cnt * row, hipMemcpyHostToDevice, stream) != hipSuccess)
+          return err(ctx, RMG_EHIP, "pc_mlmc: random-input copy failed");
+        rmg_level e{};
+        e.n_fine = L[lt].n_fine;
+        e.n_coarse = L[lt].n_coarse;
+        e.n_samples = cnt;
+        e.fine = L[lt].fine;
+        e.coarse = L[lt].fine;
+        e.d_basis_fine = L[lt].d_basis_fine;
+        e.d_basis_coarse = L[lt].d_basis_coarse;
+        e.d_xi = st.d + xoff[lt];
+        rmg_level_sums sb{};
+        const int rc = mlmc_level_estimate(ctx, 1, &e, n_fields, n_modes, h_marg, opts, &sb, nullptr, stream);
+        if (rc != RMG_OK && rc != RMG_ENOTCONV) return rc;
+        ++res->calls;
+        accumulate(bs, sb);
+        res->bias_pairs += cnt;
+        cost += (double)cnt * out[lt].W;
+      }
+    }
+    if (bs.n > 0) res->bias = std::sqrt(val(bs.sY2) / (double)bs.n) / (std::pow(2.0, pc->bias_rate) - 1.0);
+  }
   res->total_cost = cost;
   res->converged = converged && err2 <= pc->eps * pc->eps * (1.0 + 1e-12);
   res->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();

@@ -14,6 +14,8 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "rmg_device.hpp"
 #include "rmg_internal.hpp"
 #include "rmg_lds.hpp"
@@ -100,7 +102,13 @@ __global__ __launch_bounds__(NT) void k_whole_sample(SolveArgs a) {
   int attempt = 0, cpp = a.cpp, maxp = a.max_picard;  // the fallback attempt changes both
   double dp = 0.0;
   const LdsLevel<R> L0 = lev[0];
-  for (;;) {
+  // a sample whose fields hold a non-finite value is not solved (input validation)
+  double fbad = 0.0;
+  for (int c = threadIdx.x; c < N; c += NT)
+    for (int f = 0; f < F; ++f)
+      if (!isfinite(fld[f * N + c])) fbad = 1.0;
+  if (block_max<NT>(fbad, red) > 0.0) status = RMG_SAMPLE_NONFINITE;
+  while (status == RMG_SAMPLE_OK) {
     // conductivity at every cell (FP64)
     for (int c0 = threadIdx.x; c0 < N; c0 += kUnroll * NT) {
       double pv[kUnroll], k0[kUnroll], k1[kUnroll], k2[kUnroll];
@@ -363,10 +371,11 @@ __global__ void k_stream_init(SolveArgs a, StreamPlan pl) {
     z.final_dp = 0.0;
     z.pend = 0;
     z.fresh = 1;
-    z.cpp = a.cpp;
+    z.cpp = a.cpp > 0 ? a.cpp : kMgCpp;
     z.cyc0 = 0;
     z.jpass = 0;
     z.attempt = 0;
+    z.mgdone = 0;
     pl.state[s] = z;
     pl.state_prev[s] = z;
     pl.dpmax[s] = 0ull;
@@ -440,7 +449,17 @@ __device__ __forceinline__ bool pass_control(SampleState& st, const SolveArgs& a
     st.cyc0 = 0;
   } else if (st.active) {
     const int done = st.cyc0 + st.jpass;
-    if (done >= st.cpp) {
+    if (a.cpp == 0) {  // residual-controlled cycling: the residual check applied the correction
+      if (st.mgdone) {
+        st.cpp = done;  // cycles of the iteration, for the totals
+        restart = control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
+        st.cpp = kMgCpp;
+        st.cyc0 = 0;
+        st.mgdone = 0;
+      } else {
+        st.cyc0 = done;
+      }
+    } else if (done >= st.cpp) {
       restart = control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
       st.cyc0 = 0;
     } else {
@@ -451,6 +470,7 @@ __device__ __forceinline__ bool pass_control(SampleState& st, const SolveArgs& a
   if (store) {
     pl.state[s] = st;
     pl.dpmax[s] = 0ull;
+    if (pl.mgres) pl.mgres[s] = 0ull;
     if (st.active) {
       atomicAdd(pl.active_count, 1);
       if (st.attempt) atomicAdd(pl.active_count + 1, 1);
@@ -837,6 +857,67 @@ __global__ __launch_bounds__(NT) void k_fine_coarse(SolveArgs a, StreamPlan pl) 
   }
 }
 
+// Residual-controlled cycling on the streaming path (Section 4.2: cycle until
+// max_c |f - A dp| < eps_mg): after each cycle, the correction equation's residual on
+// the finest level in the smoother precision (the per-cell arithmetic of
+// residual_value / st5, as the whole-sample kernel's check), reduced per sample.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_mg_residual(SolveArgs a, StreamPlan pl) {
+  __shared__ double red[kBlock / 64];
+  const int64_t s = blockIdx.y;
+  const SampleState st = pl.state[s];
+  if (!slot_runs(st, 0)) return;
+  const int m = a.n, lg = a.lg;
+  const int64_t M2 = (int64_t)m * m;
+  const R* F = (const R*)pl.lv.f[0] + s * M2;
+  const R* CW = (const R*)pl.lv.cw[0] + s * M2;
+  const R* CS = (const R*)pl.lv.cs[0] + s * M2;
+  const R* CDT = (const R*)pl.lv.cdt[0] + s * M2;
+  const R* CT = (const R*)pl.lv.ctop[0] + s * m;
+  const R* U = (const R*)(pl.ltop == 0 ? pl.lv.u[0] : pl.lv.ub[0]) + s * M2;
+  double mx = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x; c < M2; c += (int64_t)gridDim.x * kBlock) {
+    const int j = (int)(c >> lg), i = (int)(c - ((int64_t)j << lg));
+    const R z = (R)0;
+    const St5<R> t = st5<R>(CDT[c], CW[c], i < m - 1 ? CW[c + 1] : z, CS[c], j < m - 1 ? CS[c + m] : CT[i],
+                            i > 0 ? U[c - 1] : z, i < m - 1 ? U[c + 1] : z, j > 0 ? U[c - m] : z,
+                            j < m - 1 ? U[c + m] : z);
+    mx = fmax(mx, fabs((double)residual_value<R>(F[c], U[c], t)));
+  }
+  mx = block_max<kBlock>(mx, red);
+  if (threadIdx.x == 0) atomic_max_nonneg(pl.mgres + s, mx);
+}
+
+// The correction of a sample whose residual met eps_mg (or that reached the cycle cap)
+// is applied: p += dp, ||dp||_inf and the non-finite flag as the finest up leg does, and
+// the state records that the iteration's cycling is over.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_mg_apply(SolveArgs a, StreamPlan pl) {
+  __shared__ double red[kBlock / 64];
+  const int64_t s = blockIdx.y;
+  const SampleState st = pl.state[s];
+  if (!slot_runs(st, 0)) return;
+  const double r = __longlong_as_double((long long)pl.mgres[s]);
+  if (!(r < a.eps_mg) && st.cyc0 + 1 < kMaxMgCycles) return;
+  const int64_t M2 = (int64_t)a.n * a.n;
+  const R* U = (const R*)(pl.ltop == 0 ? pl.lv.u[0] : pl.lv.ub[0]) + s * M2;
+  double* p = a.p + s * M2;
+  double mx = 0.0, bad = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)kBlock + threadIdx.x; c < M2; c += (int64_t)gridDim.x * kBlock) {
+    const double d = (double)U[c];
+    p[c] += d;
+    mx = fmax(mx, fabs(d));
+    if (!isfinite(d)) bad = 1.0;
+  }
+  mx = block_max<kBlock>(mx, red);
+  bad = block_max<kBlock>(bad, red);
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(pl.dpmax + s, mx);
+    if (bad > 0.0) atomicOr(&pl.state[s].nanflag, 1);
+    if (blockIdx.x == 0) pl.state[s].mgdone = 1;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_stream_finish(SolveArgs a, StreamPlan pl) {
   __shared__ double red[kBlock];
   const int64_t s = blockIdx.x;
@@ -870,11 +951,29 @@ size_t level_bytes(int m, int64_t S, bool fp64) {
   return es * (size_t)S * (6 * (size_t)m * m + (size_t)m);
 }
 
+// Input validation: a sample whose fields hold a non-finite value is marked
+// RMG_SAMPLE_NONFINITE and never iterated (both parities of its state).
+__global__ __launch_bounds__(kBlock) void k_check_fields(SolveArgs a, StreamPlan pl) {
+  __shared__ double red[kBlock / 64];
+  const int64_t s = blockIdx.x;
+  const int64_t FN = (int64_t)a.F << (2 * a.lg);
+  const double* fld = a.fields + s * FN;
+  double bad = 0.0;
+  for (int64_t e = threadIdx.x; e < FN; e += kBlock)
+    if (!isfinite(fld[e])) bad = 1.0;
+  bad = block_max<kBlock>(bad, red);
+  if (threadIdx.x == 0 && bad > 0.0) {
+    pl.state[s].active = pl.state_prev[s].active = 0;
+    pl.state[s].status = pl.state_prev[s].status = RMG_SAMPLE_NONFINITE;
+  }
+}
+
 hipError_t launch_stream_init(const SolveArgs& a, const StreamPlan& pl, hipStream_t st) {
   const int64_t tot = a.S * (int64_t)a.n * a.n;
   int64_t blocks = (tot + kBlock - 1) / kBlock;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_stream_init, dim3((unsigned)blocks), dim3(kBlock), 0, st, a, pl);
+  hipLaunchKernelGGL(k_check_fields, dim3((unsigned)a.S), dim3(kBlock), 0, st, a, pl);
   return hipGetLastError();
 }
 
@@ -990,7 +1089,7 @@ static bool fine_coarse_fits(const SolveArgs& a, const StreamPlan& pl) {
 // class is its call's only streaming class.
 template <class R>
 static bool fused_fine_coarse(const SolveArgs& a, const StreamPlan& pl) {
-  return a.fuse_top && fine_coarse_fits<R>(a, pl);
+  return a.fuse_top && a.cpp > 0 && fine_coarse_fits<R>(a, pl);
 }
 
 template <class R>
@@ -1019,6 +1118,12 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
   for (int j = 0; j < J; ++j) {
     const hipError_t err = stream_cycles<R>(a, pl, st, 1, j);
     if (err != hipSuccess) return err;
+  }
+  if (a.cpp == 0) {  // residual-controlled cycling: one cycle per pass, then the check
+    const int64_t M2 = (int64_t)n * n;
+    const unsigned g = (unsigned)std::min<int64_t>((M2 + kBlock - 1) / kBlock, 256);
+    hipLaunchKernelGGL(k_mg_residual<R>, dim3(g, (unsigned)a.S), blk, 0, st, a, pl);
+    hipLaunchKernelGGL(k_mg_apply<R>, dim3(g, (unsigned)a.S), blk, 0, st, a, pl);
   }
   return hipGetLastError();
 }

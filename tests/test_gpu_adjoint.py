@@ -150,3 +150,22 @@ def test_invalid_adjoint_arguments_raise():
         rmg.picard_mg_adjoint(n, B, xi, MARG, gprob(3), rmg.SolverOpts(), ckpt_every=2)
     with pytest.raises(rmg.RmgError):
         rmg.picard_mg_adjoint(n, B, xi, MARG, rmg.Problem(model=rmg.VGM), rmg.SolverOpts())
+
+
+@pytest.mark.parametrize("precision", [rmg.FP64, rmg.MIXED])
+def test_forward_only_outflux_equals_the_adjoints_q(precision):
+    """picard_mg_outflux (the autograd Function's forward pass: the forward solve alone)
+    returns the same Q as picard_mg_adjoint, bit for bit, with and without checkpoints."""
+    n, M, n_steps = 64, 6, 4
+    xi = torch.from_numpy(W.normal_array([27], (5, M))).to(DEV)
+    B = torch.from_numpy(basis(M)[n]).to(DEV)
+    opts = rmg.SolverOpts(precision=precision, max_picard=300)
+    ctx = rmg.default_context()
+    fwd = ctx.picard_mg_outflux(n, B, xi, MARG, gprob(n_steps), opts)
+    for ck in (1, 2):
+        ref = rmg.picard_mg_adjoint(n, B, xi, MARG, gprob(n_steps), opts, ckpt_every=ck)
+        assert torch.equal(fwd["q"], ref["q"]), ck
+        assert torch.equal(fwd["status"], ref["status"])
+    with torch.no_grad():
+        q = rmg.outflux_qoi(xi, B, n, MARG, gprob(n_steps), opts)
+    assert torch.equal(q, fwd["q"])

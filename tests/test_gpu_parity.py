@@ -193,16 +193,21 @@ def test_w_cycle_matches_twin_oracle(n, precision, flags, tol):
             assert int(out["stats"]["mg_cycles"][i]) == sum(r["picard"])
 
 
-@pytest.mark.parametrize("n,precision,tol", [(16, rmg.FP64, 1e-10), (32, rmg.FP64, 1e-10), (32, rmg.MIXED, 1e-8)])
-def test_paper_mode_w_cycles_to_eps_mg_match_twin_oracle(n, precision, tol):
+@pytest.mark.parametrize("n,precision,tol,flags", [(16, rmg.FP64, 1e-10, 0), (32, rmg.FP64, 1e-10, 0),
+                                                   (32, rmg.MIXED, 1e-8, 0), (64, rmg.FP64, 1e-10, 0),
+                                                   (64, rmg.MIXED, 1e-8, rmg.FLAG_COARSE_TOP_32),
+                                                   (128, rmg.MIXED, 1e-8, 0)])
+def test_paper_mode_w_cycles_to_eps_mg_match_twin_oracle(n, precision, tol, flags):
     """The paper's multigrid setting (Section 4.2): W(2,2) cycles repeated until the
-    correction equation's residual max |f - A dp| is below eps_mg = 1e-5.  FP64: the same
-    cycle count as the oracle in every Picard step (summed over the solve)."""
+    correction equation's residual max |f - A dp| is below eps_mg = 1e-5, on the
+    whole-sample kernel (16^2, 32^2) and on the level-streaming path (64^2, 128^2: the
+    residual checked by its own kernel after every cycle).  FP64: the same cycle count as
+    the oracle in every Picard step (summed over the solve)."""
     S = 3
-    say(f"paper mode W + eps_mg n={n} precision={precision}")
+    say(f"paper mode W + eps_mg n={n} precision={precision} flags={flags}")
     B, xi, fields = _fields(n, S, wid=15)
     prob = rmg.Problem(n_steps=3)
-    opts = rmg.SolverOpts(precision=precision, cycle=rmg.CYCLE_W, cycles_per_picard=0, eps_mg=1e-5)
+    opts = rmg.SolverOpts(precision=precision, cycle=rmg.CYCLE_W, cycles_per_picard=0, eps_mg=1e-5, flags=flags)
     out = rmg.picard_mg_solve(n, fields, prob, opts)
     torch.cuda.synchronize()
     h = out["h"].cpu().numpy()
@@ -217,11 +222,24 @@ def test_paper_mode_w_cycles_to_eps_mg_match_twin_oracle(n, precision, tol):
         assert int(out["stats"]["mg_cycles"][i]) > int(out["stats"]["picard_its"][i])
 
 
-def test_eps_mg_mode_is_rejected_on_streaming_grids():
-    _, _, fields = _fields(128, 1, wid=16)
-    with pytest.raises(rmg.RmgError) as e:
-        rmg.picard_mg_solve(128, fields, rmg.Problem(n_steps=1), rmg.SolverOpts(cycles_per_picard=0))
-    assert e.value.code == -1
+@pytest.mark.parametrize("precision", [rmg.FP64, rmg.MIXED])
+def test_eps_mg_streaming_equals_whole_sample_bitwise(precision):
+    """Residual-controlled cycling on a 32^2 grid: the whole-sample kernel (the check inside
+    its cycle loop) and the streaming path forced onto the grid (a residual kernel and an
+    apply kernel after every cycle) perform the same operations: bit-identical results and
+    cycle counts, for V- and W-cycles."""
+    n, S = 32, 4
+    say(f"eps_mg streaming vs whole n={n} precision={precision}")
+    _, _, fields = _fields(n, S, wid=16)
+    prob = rmg.Problem(n_steps=2)
+    for cyc in (rmg.CYCLE_V, rmg.CYCLE_W):
+        base = dict(precision=precision, cycle=cyc, cycles_per_picard=0, eps_mg=1e-5)
+        a = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(**base))
+        b = rmg.picard_mg_solve(n, fields, prob, rmg.SolverOpts(flags=rmg.FLAG_FORCE_STREAMING, **base))
+        torch.cuda.synchronize()
+        assert torch.equal(a["h"], b["h"])
+        assert (a["stats"]["mg_cycles"] == b["stats"]["mg_cycles"]).all()
+        assert (a["stats"]["picard_its"] == b["stats"]["picard_its"]).all()
 
 
 def test_w_cycle_streaming_equals_whole_sample_bitwise():

@@ -75,8 +75,16 @@ def oracle_run():
         rc = oracle_solve(nc, oracle_fields(B[nc], xi), _oprob(l - 1), opts)
         return rf["qoi"], rc["qoi"], rf["cycles"], rc["cycles"]
 
+    def bias_pair(i):
+        # the finest level's pair i with its own parameter set on both grids (eq. numErr)
+        L = len(GRIDS) - 1
+        xi = W.xi_draws(WID, L, [i], 1, W.KS_FIELD["n_modes"])[0, 0]
+        nf, nc = GRIDS[L]
+        return (oracle_solve(nf, oracle_fields(B[nf], xi), _oprob(L), opts)["qoi"],
+                oracle_solve(nc, oracle_fields(B[nc], xi), _oprob(L), opts)["qoi"])
+
     say("oracle PC_MLMC run")
-    return opc.run(sample, GRIDS, WARM, EPS)
+    return opc.run(sample, GRIDS, WARM, EPS, bias_pair=bias_pair)
 
 
 def _run(cap, cost=rmg.COST_WORK, precision=rmg.FP64):
@@ -108,6 +116,7 @@ def test_pc_mlmc_takes_the_oracles_decisions(oracle_run, gpu_runs, cap):
     assert abs(r["var"] - o["var"]) <= 1e-9 * abs(o["var"])
     assert abs(r["sampling_err2"] - o["sampling_err2"]) <= 1e-8 * o["sampling_err2"]
     assert r["sampling_err2"] <= EPS ** 2
+    assert r["bias_pairs"] == o["bias_pairs"] > 0
     assert abs(r["bias"] - o["bias"]) <= 1e-8 * o["bias"]
 
 
@@ -119,7 +128,9 @@ def test_pc_mlmc_draw_numbering_and_batching(gpu_runs):
             if cap:
                 assert count <= cap
             nxt[level] += count
-        assert nxt == [x["drawn"] for x in r["levels"]]
+        # the bias pairs continue the finest level's numbering
+        assert nxt == [x["drawn"] + (r["bias_pairs"] if l == len(GRIDS) - 1 else 0)
+                       for l, x in enumerate(r["levels"])]
 
 
 def test_pc_mlmc_sums_are_the_sums_of_the_drawn_pairs(gpu_runs):

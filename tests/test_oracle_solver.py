@@ -271,3 +271,16 @@ def test_fallback_attempt_reaches_the_fixed_point(kl_basis_small):
     assert r["picard"] == [2] + second["picard"]
     assert r["cycles"] == 2 + second["cycles"]
     assert np.max(np.abs(r["p"] - fixed["p"])) <= 1e-10 * np.max(np.abs(fixed["p"]))
+
+
+def test_non_finite_fields_are_rejected_without_solving():
+    """A field with a NaN or infinite value is invalid input: status NONFINITE, no iteration
+    (a NaN conductivity would otherwise act as an impermeable cell through the guarded
+    harmonic mean)."""
+    n = 8
+    Ks = np.ones((n, n))
+    for bad in (np.nan, np.inf):
+        f = Ks.copy()
+        f[3, 4] = bad
+        r = picard.solve(dict(W.GARDNER_INFILTRATION, n_steps=2), {"Ks": f}, n, dict(W.SOLVER), mode="mg")
+        assert r["status"] == picard.STATUS_NONFINITE and r["picard"] == [] and r["cycles"] == 0

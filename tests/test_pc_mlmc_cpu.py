@@ -135,3 +135,29 @@ def test_library_eq_mlmcsamp_rejects_bad_input(V, W, eps):
     rmg = _lib_or_skip()
     with pytest.raises(rmg.RmgError):
         rmg.optimal_samples(eps, V, W)
+
+
+def test_bias_uses_the_finest_parameter_set_on_both_grids():
+    """Case C's hierarchy with continuation at the top: the finest level's own pairs
+    (Y1 = 0, 0.2, ...) mix the parameter change into Y; the bias of eq. discErr (s = 2,
+    a = 1) comes from further pairs of level 1 with Theta_L on both grids, numbered after
+    the level's pairs: differences 0.03, -0.04 (the second of three draws fails) give
+    sqrt((0.03^2 + 0.04^2) / 2) / (2 - 1) = 0.035355...; N_L = 2 such pairs are taken.
+    Without a bias_pair source the level's own pairs give sqrt(mean Y1^2) = sqrt(0.02)."""
+    def s(l, i):
+        if l == 0:
+            return (float(2 * (i % 2)), None, 1, 0)
+        return (1.0 + 0.2 * (i % 2), 1.0, 1, 1)
+
+    asked = []
+
+    def bp(i):
+        asked.append(i)
+        k = len(asked) - 1
+        return [(1.03, 1.0), (np.nan, 1.0), (0.96, 1.0)][k]
+
+    r = pc_mlmc.run(s, [(2, 0), (5, 2)], [2, 2], 0.5, bias_pair=bp)
+    assert r["levels"][1]["drawn"] == 2 and asked == [2, 3, 4] and r["bias_pairs"] == 3
+    assert r["bias"] == pytest.approx(math.sqrt((0.03 ** 2 + 0.04 ** 2) / 2), rel=1e-12)
+    r0 = pc_mlmc.run(s, [(2, 0), (5, 2)], [2, 2], 0.5)
+    assert r0["bias"] == pytest.approx(math.sqrt(0.02), rel=1e-12) and r0["bias_pairs"] == 0
