@@ -281,6 +281,25 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
                     rmg_sample_stats* d_stats, hipStream_t stream);
 
 /*
+ * picard_mg_solve_noalloc - picard_mg_solve for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: under stream capture, in tight serving
+ * loops, in harnesses that forbid it).  Same arguments, results and errors as
+ * picard_mg_solve, computed by the same kernels; the workspace is a fixed device array
+ * of 64 MiB that each GPU holds from the library's first use until the process ends,
+ * and the Picard passes are launched eagerly (no graph is instantiated).  A solve whose
+ * workspace would exceed the array returns RMG_EINVAL with the bytes it needs (the
+ * whole-sample grids up to 32 x 32 need about 8 n^2 bytes per sample, the streaming
+ * grids about 8 n^2 + 6 n^2 sizeof(smoother element) x 4/3).  Every call on one GPU
+ * shares that array: calls that overlap in time on one GPU (several host threads or
+ * streams) race and give wrong results; serialise them.  The array keeps the last
+ * call's contents; every value a call reads from it is written by that call first.
+ */
+int picard_mg_solve_noalloc(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+                            const double* d_fields, int64_t S,
+                            double* d_h_out, double* d_qoi, int32_t* d_status,
+                            rmg_sample_stats* d_stats, hipStream_t stream);
+
+/*
  * mlmc_level_estimate - one batched evaluation of n_levels MLMC levels
  * (Section 5.1 eqs. MLMCestimator, SMC, ML_var).  For level l and pair i the
  * fine solve (n_fine, fine problem) and the coarse solve (n_coarse, coarse

@@ -168,8 +168,9 @@ class Context:
         self._raise(rc)
         return out
 
-    def picard_mg_solve(self, n, fields, problem: Problem, opts: SolverOpts, stream=None):
-        """Solve S samples on an n x n grid; returns dict(h, qoi, status, stats, rc)."""
+    def picard_mg_solve(self, n, fields, problem: Problem, opts: SolverOpts, stream=None, noalloc=False):
+        """Solve S samples on an n x n grid; returns dict(h, qoi, status, stats, rc).
+        noalloc: the allocation-free entry point (workspace in the library's fixed device array)."""
         torch = _torch()
         S = fields.shape[0]
         _check_dev(fields, "fields", torch.float64, (S, problem.n_fields, n * n))
@@ -179,7 +180,8 @@ class Context:
         status = torch.empty(S, dtype=torch.int32, device=dev)
         stats = torch.empty((S, C.sizeof(_abi.SampleStats)), dtype=torch.uint8, device=dev)
         pr, op = problem.c(), opts.c()
-        rc = self._lib.picard_mg_solve(self._h, n, C.byref(pr), C.byref(op), C.c_void_p(fields.data_ptr()),
+        fn = self._lib.picard_mg_solve_noalloc if noalloc else self._lib.picard_mg_solve
+        rc = fn(self._h, n, C.byref(pr), C.byref(op), C.c_void_p(fields.data_ptr()),
                                        S, C.c_void_p(h.data_ptr()), C.c_void_p(qoi.data_ptr()),
                                        C.c_void_p(status.data_ptr()), C.c_void_p(stats.data_ptr()),
                                        _stream_ptr(stream))

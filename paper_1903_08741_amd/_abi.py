@@ -30,7 +30,8 @@ FLAG_NO_CONFINE = 256
 COST_WORK, COST_TIME = 0, 1
 
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
-            "rmg_ctx_set_workspace_limit", "sample_fields", "picard_mg_solve", "mlmc_level_estimate",
+            "rmg_ctx_set_workspace_limit", "sample_fields", "picard_mg_solve", "picard_mg_solve_noalloc",
+            "mlmc_level_estimate",
             "rmg_set_kernel_timing", "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples",
             "picard_mg_adjoint", "picard_mg_outflux")
 
@@ -144,6 +145,8 @@ def lib():
     L.picard_mg_solve.argtypes = [vp, i32, C.POINTER(Problem), C.POINTER(SolverOpts), vp, i64, vp, vp, vp,
                                   vp, vp]
     L.picard_mg_solve.restype = i32
+    L.picard_mg_solve_noalloc.argtypes = L.picard_mg_solve.argtypes
+    L.picard_mg_solve_noalloc.restype = i32
     L.mlmc_level_estimate.argtypes = [vp, i32, C.POINTER(Level), i32, i32, C.POINTER(Marginal),
                                       C.POINTER(SolverOpts), C.POINTER(LevelSums), vp, vp]
     L.mlmc_level_estimate.restype = i32

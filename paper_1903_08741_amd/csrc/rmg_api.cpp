@@ -64,6 +64,7 @@ struct rmg_ctx {
   void* ws = nullptr;
   size_t ws_cap = 0;
   size_t ws_limit = 0;         // 0: no cap
+  void* scratch = nullptr;     // device address of the fixed scratch array on this device
   int32_t* h_count = nullptr;  // pinned host mirror of the active-sample counters
   hipStream_t side[8] = {};
   hipEvent_t ev[8] = {};
@@ -646,6 +647,11 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device, const char* tune_cache_path) {
     c->tune_path = tune_cache_path;
     load_tune_cache(c);
   }
+  // the fixed scratch array's address on this device (each device holds its own copy)
+  if (scratch_address(&c->scratch) != hipSuccess || !c->scratch) {
+    rmg_ctx_destroy(c);
+    return RMG_EHIP;
+  }
   for (auto& s : c->side) {
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       rmg_ctx_destroy(c);
@@ -849,9 +855,15 @@ int sample_fields(rmg_ctx* ctx, int n, int n_fields, int n_modes, const double* 
   return RMG_OK;
 }
 
-int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
-                    const double* d_fields, int64_t S, double* d_h_out, double* d_qoi,
-                    int32_t* d_status, rmg_sample_stats* d_stats, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+// picard_mg_solve, with its workspace in the context's workspace (grown with hipMalloc
+// when needed) or, for the allocation-free variant, in the fixed device scratch array
+// (the call then also launches its passes eagerly: no graph is instantiated).
+int solve_impl(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+               const double* d_fields, int64_t S, double* d_h_out, double* d_qoi, int32_t* d_status,
+               rmg_sample_stats* d_stats, hipStream_t stream, bool noalloc) {
   if (!ctx) return RMG_EINVAL;
   ctx->err.clear();
   if (!pow2_in(n, 2, 1024)) return fail(ctx, RMG_EINVAL, "n=%d must be a power of two in 2..1024", n);
@@ -889,24 +901,56 @@ int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_s
   // captured graph cannot be recorded on the legacy default stream)
   j.stream = ctx->side[0];
   j.h_count = ctx->h_count;
-  if ((rc = reserve(ctx, class_ws_bytes(j)))) return rc;
   Arena ar;
-  ar.base = (char*)ctx->ws;
-  ar.cap = ctx->ws_cap;
+  if (noalloc) {
+    // the allocation-free variant: the workspace is the fixed scratch array
+    const size_t need = class_ws_bytes(j) + 256;
+    if (need > kScratchBytes)
+      return fail(ctx, RMG_EINVAL, "this solve needs %zu bytes of scratch; the fixed scratch of the allocation-free "
+                  "entry point holds %zu bytes (use picard_mg_solve, or fewer samples per call)", need,
+                  kScratchBytes);
+    ar.base = (char*)ctx->scratch;
+    ar.cap = kScratchBytes;
+  } else {
+    if ((rc = reserve(ctx, class_ws_bytes(j)))) return rc;
+    ar.base = (char*)ctx->ws;
+    ar.cap = ctx->ws_cap;
+  }
   class_carve(j, ar);
   if (ar.off > ar.cap) return fail(ctx, RMG_ENOMEM, "internal error: workspace accounting (%zu > %zu)", ar.off, ar.cap);
   HIP_TRY(ctx, hipEventRecord(ctx->ev[0], stream));
   HIP_TRY(ctx, hipStreamWaitEvent(j.stream, ctx->ev[0], 0));
-  rc = run_classes(ctx, jobs, !(opts->flags & 2));
+  rc = run_classes(ctx, jobs, !noalloc && !(opts->flags & 2));
   HIP_TRY(ctx, hipEventRecord(ctx->ev[1], j.stream));
   HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev[1], 0));
   if (rc) return rc;
-  std::vector<int32_t> st(S);
-  HIP_TRY(ctx, hipMemcpyAsync(st.data(), d_status, sizeof(int32_t) * S, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(ctx, hipStreamSynchronize(stream));
-  for (int32_t v : st)
-    if (v != RMG_SAMPLE_OK) return fail(ctx, RMG_ENOTCONV, "some samples did not converge");
+  // statuses checked in chunks through a fixed host buffer
+  int32_t st[1024];
+  bool all_ok = true;
+  for (int64_t s0 = 0; s0 < S && all_ok; s0 += 1024) {
+    const int64_t k = std::min<int64_t>(1024, S - s0);
+    HIP_TRY(ctx, hipMemcpyAsync(st, d_status + s0, sizeof(int32_t) * k, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    for (int64_t q = 0; q < k; ++q)
+      if (st[q] != RMG_SAMPLE_OK) all_ok = false;
+  }
+  if (!all_ok) return fail(ctx, RMG_ENOTCONV, "some samples did not converge");
   return RMG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int picard_mg_solve(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+                    const double* d_fields, int64_t S, double* d_h_out, double* d_qoi,
+                    int32_t* d_status, rmg_sample_stats* d_stats, hipStream_t stream) {
+  return solve_impl(ctx, n, problem, opts, d_fields, S, d_h_out, d_qoi, d_status, d_stats, stream, false);
+}
+
+int picard_mg_solve_noalloc(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts,
+                            const double* d_fields, int64_t S, double* d_h_out, double* d_qoi,
+                            int32_t* d_status, rmg_sample_stats* d_stats, hipStream_t stream) {
+  return solve_impl(ctx, n, problem, opts, d_fields, S, d_h_out, d_qoi, d_status, d_stats, stream, true);
 }
 
 int picard_mg_adjoint(rmg_ctx* ctx, int n, const rmg_problem* problem, const rmg_solver_opts* opts, int n_modes,

@@ -123,6 +123,11 @@ struct AdjArgs {
   int max_its;         // fixed-point iterations allowed per step
 };
 
+// Size of the fixed device scratch array of the allocation-free solve entry point.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+// Device address of that array on the current device.
+hipError_t scratch_address(void** ptr);
+
 // LDS bytes of the whole-sample kernel for grid n (0 if it does not fit).
 size_t whole_sample_lds_bytes(int n, int nc, bool fp64, int F, bool* state_in_lds);
 hipError_t launch_whole_sample(const SolveArgs& a, bool fp64, hipStream_t st);

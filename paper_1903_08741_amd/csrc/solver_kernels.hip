@@ -1162,4 +1162,16 @@ hipError_t launch_stream_finish(const SolveArgs& a, const StreamPlan& pl, hipStr
   return hipGetLastError();
 }
 
+// ------------------------------------------------- fixed scratch (no allocation)
+// Workspace of picard_mg_solve_noalloc: a file-scope device array, one per GPU, held
+// until the process ends.  Host code must not pass the array's name to a kernel (on
+// the host it is only a stand-in symbol): it takes the device address from
+// scratch_address() once per device, with that device current, and uses that.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** ptr) {
+  *ptr = nullptr;
+  return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 }  // namespace rmg
