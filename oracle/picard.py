@@ -76,6 +76,10 @@ def picard_step(problem, fields, p_old, theta_old, opts, mode, stats):
         K, theta, C = constitutive.evaluate(problem, p, fields)
         kx, kz = fv.face_conductivities(K)
         f = fv.picard_rhs(p, theta, theta_old, kx, kz, h, dt, gb, gt)
+        if not (np.all(np.isfinite(f)) and np.all(np.isfinite(kz)) and np.all(np.isfinite(C))):
+            # a blown-up iterate: this iteration's correction cannot be finite
+            stats["cycles"] += 1 if mode == "direct" else max(1, opts.get("cycles_per_picard", 1))
+            return p, theta, STATUS_NONFINITE, k, float("nan")
         dp = _linear_solve(kx, kz, C / dt, f, opts, mode, stats)
         p = p + dp
         dpn = float(np.max(np.abs(dp)))
