@@ -58,12 +58,12 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per k_down launch from the committed PMC profile (FETCH_SIZE and WRITE_SIZE,
-    each scaled by a plain copy's reading), or None when the kernel sources changed since."""
+def _profile_record(tag):
+    """The last `tag:` line of the committed k_down profile as a dict, or None when there is
+    none or the kernel sources changed since it was taken."""
     try:
         with open(TRAFFIC_PROFILE) as fh:
-            lines = [ln for ln in fh if ln.startswith("traffic-record:")]
+            lines = [ln for ln in fh if ln.startswith(tag + ":")]
     except OSError:
         return None
     if not lines:
@@ -71,7 +71,22 @@ def recorded_traffic():
     rec = dict(kv.split("=", 1) for kv in lines[-1].split()[1:])
     if rec.get("source_digest") != kernel_source_digest():
         return None
+    return rec
+
+
+def recorded_traffic():
+    """HBM bytes per k_down launch from the committed PMC profile (FETCH_SIZE and WRITE_SIZE,
+    each scaled by a plain copy's reading), or None when the kernel sources changed since."""
+    rec = _profile_record("traffic-record")
+    if rec is None:
+        return None
     return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+
+
+def recorded_trace_us():
+    """Average k_down kernel duration over every launch of the committed kernel trace, or None."""
+    rec = _profile_record("trace-record")
+    return None if rec is None else float(rec["avg_launch_us"])
 
 
 def build_levels(torch, rmg, W, precision, dev, max_picard):
@@ -866,6 +881,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="32 x 32 streaming tiles on every level and no schedule tuning (profiling runs: "
                          "timing under a counter profiler is distorted)")
+    ap.add_argument("--tune-cache", default="",
+                    help="file for the library's tuning choices (read at start, written when it tunes), so "
+                         "that a profiled run repeats an unprofiled run's tiles and schedule")
+    ap.add_argument("--tiles", choices=("auto", "32", "16"), default="auto",
+                    help="streaming tile edges: autotuned (default), or 32 / 16 on every level")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-grid, FP64-path, solver-variant and large-batch figures (outside the "
                          "timed region)")
@@ -903,13 +923,15 @@ def main():
     opts.cycle = rmg.CYCLE_W if args.cycle == "W" else rmg.CYCLE_V
     opts.fallback_cycles = args.fallback_cycles
     opts.fallback_max_picard = args.fallback_max_picard if args.fallback_cycles else 0
-    if args.no_autotune:
+    if args.no_autotune or args.tiles == "32":
         opts.flags |= rmg.FLAG_NO_AUTOTUNE
+    if args.tiles == "16":
+        opts.flags |= rmg.FLAG_TILES_16
     if args.confine == "on":
         opts.flags |= rmg.FLAG_CONFINE
     elif args.confine == "off":
         opts.flags |= rmg.FLAG_NO_CONFINE
-    ctx = rmg.default_context(0)
+    ctx = rmg.Context(0, tune_cache=args.tune_cache) if args.tune_cache else rmg.default_context(0)
     if args.grid:
         res = per_grid(torch, rmg, ctx, levels, opts, marg, only=args.grid)
         if not res:
@@ -962,6 +984,12 @@ def main():
             "compulsory_bytes_per_cell": 5.25 * es,
             "sweep_model_bytes_per_cell": (2 * 20 + 17) * es / 4,
             "frac_sweep_model": (gbs * (2 * 20 + 17) / 4 / 5.25) / HBM_PEAK_GBS}
+    tus = None if vg else recorded_trace_us()
+    if tus and kt["launches"]:
+        # the same algorithmic bytes per launch at the committed trace's average duration
+        tg = roof["algo_bytes_per_launch"] / (tus * 1e-6) / 1e9
+        roof.update({"traced_avg_launch_us": tus, "achieved_at_traced_us": tg, "frac_at_traced_us": tg / HBM_PEAK_GBS,
+                     "event_over_trace": roof["avg_launch_us"] / tus})
     roof_fine = None
     if kf["total_ms"] > 0:
         fg = kf["algo_bytes"] / (kf["total_ms"] * 1e-3) / 1e9
