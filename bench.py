@@ -721,9 +721,13 @@ def sweep_bench(args, torch, rmg, W):
     from paper_1903_08741_amd import kl_setup
     cfg, tw = W.SWEEP, W.TRAVELLING_WAVE
     dev = torch.device("cuda:0")
-    n, P, M = cfg["n"], cfg["samples_per_pair"], cfg["n_modes"]
+    P, M = cfg["samples_per_pair"], cfg["n_modes"]
+    n = args.sweep_h
+    dt = 1.0 / args.sweep_dt
+    n_steps = int(np.ceil(W.SWEEP_T_FINAL / dt - 1e-9))  # first multiple of dt at or past T_final
+    phi = W.MATERN_PHI1 if args.sweep_phi == 1 else W.MATERN_PHI2
     A, NV = W.SWEEP_ALPHA, W.SWEEP_N
-    _, tables = kl_setup.kl_tables(0.0, 0.0, M, [n], matern_phi=W.MATERN_PHI1)
+    _, tables = kl_setup.kl_tables(0.0, 0.0, M, [n], matern_phi=phi)
     ctx = rmg.default_context(0)
     B = torch.from_numpy(tables[n]).to(dev)
     xi = torch.from_numpy(W.xi_draws(cfg["workload_id"], 0, range(P), 1, M)).to(dev)
@@ -736,8 +740,8 @@ def sweep_bench(args, torch, rmg, W):
     nv = torch.tensor([v for _, v in pairs], dtype=torch.float64, device=dev).repeat_interleave(P)
     fields[:, 1] = av[:, None]
     fields[:, 2] = nv[:, None]
-    prob = rmg.Problem(model=rmg.VGM, n_steps=tw["n_steps"], theta_r=tw["theta_r"], theta_s=tw["theta_s"],
-                       h_top=tw["h_top"], h_bottom=tw["h_bottom"], h_init=tw["h_init"], dt=tw["dt"],
+    prob = rmg.Problem(model=rmg.VGM, n_steps=n_steps, theta_r=tw["theta_r"], theta_s=tw["theta_s"],
+                       h_top=tw["h_top"], h_bottom=tw["h_bottom"], h_init=tw["h_init"], dt=dt,
                        init_profile=1, init_rate=tw["init_rate"])
     precision = rmg.MIXED if args.precision == "mixed" else rmg.FP64
     opts = rmg.SolverOpts(precision=precision, cycle=rmg.CYCLE_W, cycles_per_picard=0, eps_mg=cfg["eps_mg"],
@@ -763,10 +767,12 @@ def sweep_bench(args, torch, rmg, W):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 multigrid in f64 Picard" if precision == rmg.MIXED else "f64",
-        "data": "synthetic (seeded Matern Phi_1 KL Ks fields; alpha, n from Table alpha_n)",
+        "data": f"synthetic (seeded Matern Phi_{args.sweep_phi} KL Ks fields; alpha, n from Table alpha_n)",
         "config": {"workload": f"robustness sweep: {len(A)}x{len(NV)} (alpha, n) pairs x {P} Ks fields = {S} "
-                               f"solves of {n}^2, vG, infiltration problem, {tw['n_steps']} steps dt=1/64, "
-                               "W(2,2) to eps_MG 1e-5, eps_PI 1e-5, at most 50 Picard iterations",
+                               f"solves of {n}^2 (h=1/{n}), Matern Phi_{args.sweep_phi}, vG, infiltration "
+                               f"problem, {n_steps} steps dt=1/{args.sweep_dt}, W(2,2) to eps_MG 1e-5, "
+                               "eps_PI 1e-5, at most 50 Picard iterations",
+                   "h": f"1/{n}", "dt": f"1/{args.sweep_dt}", "phi": args.sweep_phi,
                    "solves": S, "converged": int(ok.sum()), "precision": args.precision},
         "roofline": None,
         "cpu_baseline": None,
@@ -861,6 +867,12 @@ def main():
     ap.add_argument("--grid", type=int, default=0,
                     help="gardner: solve only this grid size's class of the MLMC workload (one untimed and "
                          "one timed call; for profiling one class)")
+    ap.add_argument("--sweep-h", type=int, choices=(32, 64), default=32,
+                    help="sweep: cells per side (h = 1/32 or 1/64, the two grids of Section 4.3)")
+    ap.add_argument("--sweep-dt", type=int, choices=(64, 128), default=64,
+                    help="sweep: time step 1/64 or 1/128 (Section 4.3)")
+    ap.add_argument("--sweep-phi", type=int, choices=(1, 2), default=1,
+                    help="sweep: Matern parameter set Phi_1 (isotropic) or Phi_2 (anisotropic) of Table Matern")
     ap.add_argument("--eps-sweep", action="store_true",
                     help="pcmlmc gardner: cost of Algorithm 1 against the tolerance, the finest grid refined "
                          "as eps halves (h_L ~ eps)")
@@ -886,6 +898,8 @@ def main():
                          "that a profiled run repeats an unprofiled run's tiles and schedule")
     ap.add_argument("--tiles", choices=("auto", "32", "16"), default="auto",
                     help="streaming tile edges: autotuned (default), or 32 / 16 on every level")
+    ap.add_argument("--large-batch", action="store_true",
+                    help="only the down-leg smoother's rate on the large batch (64 samples of 512^2)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-grid, FP64-path, solver-variant and large-batch figures (outside the "
                          "timed region)")
@@ -932,6 +946,9 @@ def main():
     elif args.confine == "off":
         opts.flags |= rmg.FLAG_NO_CONFINE
     ctx = rmg.Context(0, tune_cache=args.tune_cache) if args.tune_cache else rmg.default_context(0)
+    if args.large_batch:
+        print(json.dumps({"roofline_large_batch": large_batch_roofline(torch, rmg, ctx, W, levels, marg)}), flush=True)
+        return
     if args.grid:
         res = per_grid(torch, rmg, ctx, levels, opts, marg, only=args.grid)
         if not res:

@@ -266,20 +266,57 @@ __device__ __forceinline__ double wave_read(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Pivot order of the coarsest solve: the red cells ((i + j) even) first, then the
+// black ones.  The five-point operator couples red cells only to black cells, so a
+// red pivot row holds its diagonal and its black neighbours only (earlier red pivots
+// leave it untouched: its entries in their columns are zero) and the eight red steps
+// do not depend on one another; the black steps then eliminate the dense 8 x 8 (or
+// 2 x 2) Schur complement.
+template <int M>
+struct CoarsestOrder {
+  int piv[M * M];
+  constexpr CoarsestOrder() : piv() {
+    int t = 0;
+    for (int colour = 0; colour < 2; ++colour)
+      for (int c = 0; c < M * M; ++c)
+        if ((((c % M) + (c / M)) & 1) == colour) piv[t++] = c;
+  }
+};
+// Reciprocal of a wave-uniform FP64 pivot: the hardware estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r), which double its correct bits each
+// (about 1 ulp at the end).  Unlike the correctly rounded division sequence it does
+// not pass through the VCC register, so the independent red pivots' reciprocals
+// overlap, and a black pivot's costs five dependent operations.
+__device__ __forceinline__ double pivot_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__host__ __device__ constexpr bool grid_adjacent(int m, int a, int b) {
+  const int di = a % m - b % m, dj = a / m - b / m;
+  return (di == 1 || di == -1) ? dj == 0 : ((dj == 1 || dj == -1) && di == 0);
+}
+
 // Exact solve on the coarsest level (N = m*m = 4 or 16 unknowns) in FP64:
 // Gauss-Jordan elimination without pivoting on the symmetric positive definite
 // matrix, in the registers of the first wavefront.  Lane c holds row c of the
-// matrix (columns 0..N-1) and its right-hand side; step k reads the pivot row from
-// lane k (a wave-uniform value, so no LDS round trip and no barrier) and replaces
-// every row c != k by row_c - (a_ck / a_kk) row_k on the columns j > k (column k
-// is then logically zero and never read again).  The unknown is the row's
-// right-hand side times the reciprocal of its pivot.  Lanes N..63 duplicate rows.
+// matrix (columns 0..N-1) and its right-hand side; the step of pivot k reads the
+// pivot row from lane k (a wave-uniform value, so no LDS round trip and no barrier)
+// and replaces every row c != k by row_c - (a_ck / a_kk) row_k on the columns of
+// the pivots still to come (column k is then logically zero and never read again).
+// Pivots are taken in CoarsestOrder, and a red pivot's step touches only the
+// columns of its neighbours (its other entries are zero, so the skipped updates
+// would subtract exact zeros).  The unknown is the row's right-hand side times the
+// reciprocal of its pivot.  Lanes N..63 duplicate rows.
 // Kept out of line: inlined, its unrolled rows and scalar pivot-row reads raised
 // the register pressure of the calling kernels, whose sweep loops then reloaded
 // spilled scalar registers (every level and class ran slower).
 template <class R, int N>
 __device__ __attribute__((noinline)) void coarsest_gauss_jordan(const LdsLevel<R>& L) {
   constexpr int m = N == 16 ? 4 : 2, lg = N == 16 ? 2 : 1;
+  constexpr CoarsestOrder<m> ord{};
   const int c = (int)(threadIdx.x & (N - 1));
   const int j = c >> lg, i = c - (j << lg);
   const double aw = (double)L.cw[c], ae = (double)L.cw[c + 1];
@@ -298,14 +335,17 @@ __device__ __attribute__((noinline)) void coarsest_gauss_jordan(const LdsLevel<R
   }
   double b = (double)L.f[c], rpiv = 0.0;
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    // lane k's row is not modified in step k, so each pivot-row entry can be read
-    // just before the column it updates
-    const double pk = 1.0 / wave_read(a[k], k);
+  for (int t = 0; t < N; ++t) {
+    const int k = ord.piv[t];
+    // lane k's row is not modified in its own step, so each pivot-row entry can be
+    // read just before the column it updates
+    const double pk = pivot_recip(wave_read(a[k], k));
     rpiv = c == k ? pk : rpiv;
     const double mk = c != k ? a[k] * pk : 0.0;
 #pragma unroll
-    for (int col = k + 1; col < N; ++col) {
+    for (int u = t + 1; u < N; ++u) {
+      const int col = ord.piv[u];
+      if (t < N / 2 && !grid_adjacent(m, k, col)) continue;
       const double akj = wave_read(a[col], k);
       if (c != k) a[col] = a[col] - mk * akj;
     }

@@ -33,13 +33,23 @@ __device__ __forceinline__ unsigned rmg_magic(int w) {
   if (w >= 1 && w <= kMagicMax) return kMagic.v[w];
   return (unsigned)((0x100000000ull + (unsigned long long)w - 1ull) / (unsigned long long)w);
 }
-// Tile handled by this workgroup.  Workgroups are handed to the 8 XCDs round-robin
-// by linear id; when the tile count is a multiple of 8 the tiles are renumbered so
-// that each XCD receives a contiguous band of tiles and the halos its workgroups
-// share stay in that XCD's L2.
-__device__ __forceinline__ int xcd_tile() {
-  const int g = gridDim.x, b = blockIdx.x;
-  return (g & 7) ? b : (b & 7) * (g >> 3) + (b >> 3);
+// Sample and tile of this workgroup of a (tiles x samples) launch.  Workgroups are
+// handed to the 8 XCDs round-robin by linear id; when the tile count is a multiple of
+// 8 the tiles are renumbered so that each XCD receives a contiguous band of every
+// sample's tiles and the halos its workgroups share can stay in that XCD's L2.
+// (Renumbering whole samples onto one XCD instead measured slower: the 256^2 class
+// of the 5-level workload 379 ms against 359 ms, the large-batch smoother 2.78
+// against 2.82 TB/s.)
+struct SampleTile {
+  int64_t s;
+  int tile;
+};
+__device__ __forceinline__ SampleTile xcd_sample_tile() {
+  const int g = (int)gridDim.x, x = (int)blockIdx.x;
+  SampleTile w;
+  w.s = blockIdx.y;
+  w.tile = (g & 7) ? x : (x & 7) * (g >> 3) + (x >> 3);
+  return w;
 }
 
 // ------------------------------------------------------------ streaming smoother
@@ -91,11 +101,12 @@ struct BlkRegion {
 
 __device__ __forceinline__ int blk_lds(const BlkRegion& g, int lx, int ly) { return (ly + 1) * g.UW + lx + 1; }
 
-// Load block (bx, by) of the region (inside the domain) into registers.
+// Load block (bx, by) of the region (inside the domain) into registers; with cdt_out,
+// also its four C/dt values.
 template <class R>
 __device__ __forceinline__ void blk_load(Blk<R>& b, const BlkRegion& g, int bx, int by, int m, const R* F,
                                          const R* CW, const R* CS, const R* CDT, const R* CTOP, const R* U,
-                                         const R* UC, int mc, bool u_zero) {
+                                         const R* UC, int mc, bool u_zero, R* cdt_out = nullptr) {
   using V = typename Vec2<R>::T;
   const int gx = 2 * (g.gbx0 + bx), gy = 2 * (g.gby0 + by);
   const int64_t c0 = (int64_t)gy * m + gx, c2 = c0 + m;
@@ -127,6 +138,8 @@ __device__ __forceinline__ void blk_load(Blk<R>& b, const BlkRegion& g, int bx, 
   b.vy[0][0] = s0.x; b.vy[0][1] = s1.x; b.vy[0][2] = n0.x;
   b.vy[1][0] = s0.y; b.vy[1][1] = s1.y; b.vy[1][2] = n0.y;
   const R cdt[4] = {t0.x, t0.y, t1.x, t1.y};
+  if (cdt_out)
+    for (int k = 0; k < 4; ++k) cdt_out[k] = cdt[k];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int cx = k & 1, cy = k >> 1;
@@ -235,18 +248,19 @@ constexpr size_t blk_lds_bytes(int ts, int hb) {
 template <class R, int TS, int NB>
 __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero_, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int64_t s = blockIdx.y;
+  const SampleTile w = xcd_sample_tile();
+  const int64_t s = w.s;
   const SampleState sst = pl.state[s];
   if (!slot_runs(sst, slot)) return;
   const int u_zero = l == 0 ? (int)slot_first(sst, slot, u_zero_) : u_zero_;
   const int m = a.n >> l, mc = m >> 1;
   // timed launches count the cells they process: once per active sample (one
   // counter update per workgroup would serialise thousands of atomics on one address)
-  if (pl.tcells && blockIdx.x == 0 && threadIdx.x == 0)
+  if (pl.tcells && w.tile == 0 && threadIdx.x == 0)
     atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)m * (unsigned long long)m);
   const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
   const int ntx = m / TS;
-  const int tile = xcd_tile();
+  const int tile = w.tile;
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   RMG_LDS R* L = (RMG_LDS R*)smem;
   Blk<R> b[NB];
@@ -297,14 +311,15 @@ template <class R, int TS, int NB>
 __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final__, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kBlock / 64];
-  const int64_t s = blockIdx.y;
+  const SampleTile w = xcd_sample_tile();
+  const int64_t s = w.s;
   const SampleState sst = pl.state[s];
   if (!slot_runs(sst, slot)) return;
   const int final_ = l == 0 ? (int)slot_last(sst, slot, final__) : final__;
   const int m = a.n >> l, mc = m >> 1;
   const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
   const int ntx = m / TS;
-  const int tile = xcd_tile();
+  const int tile = w.tile;
   const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
   RMG_LDS R* L = (RMG_LDS R*)smem;
   Blk<R> b[NB];
@@ -316,6 +331,19 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
                        (const R*)pl.lv.cw[l] + s * M2, (const R*)pl.lv.cs[l] + s * M2,
                        (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m,
                        (const R*)pl.lv.u[l] + s * M2, UC, mc, false);
+  // the Picard update's FP64 head values are loaded before the sweeps, which hide
+  // their latency
+  double* p = a.p + s * M2;
+  double2 pv[NB][2];
+  if (final_) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!own[q]) continue;
+      const int64_t c0 = (int64_t)(2 * (g.gby0 + by[q])) * m + 2 * (g.gbx0 + bx[q]);
+      pv[q][0] = *(const double2*)(p + c0);
+      pv[q][1] = *(const double2*)(p + c0 + m);
+    }
+  }
   for (int st = 0; st < 2 * a.nu2; ++st) {
     if (st & 1)
       blk_half_sweep<R, NB, 1>(b, live, bx, by, g, L);
@@ -340,13 +368,12 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
     }
     return;
   }
-  double* p = a.p + s * M2;
   double mx = 0.0, bad = 0.0;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     if (!own[q]) continue;
     const int64_t c0 = (int64_t)(2 * (g.gby0 + by[q])) * m + 2 * (g.gbx0 + bx[q]);
-    const double2 p0 = *(const double2*)(p + c0), p1 = *(const double2*)(p + c0 + m);
+    const double2 p0 = pv[q][0], p1 = pv[q][1];
     const double d0 = (double)b[q].u[0], d1 = (double)b[q].u[1], d2 = (double)b[q].u[2], d3 = (double)b[q].u[3];
     double2 o0, o1;
     o0.x = p0.x + d0;

@@ -484,19 +484,20 @@ template <class R>
 __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl, int J) {
   __shared__ double sp[34 * 34], sK[34 * 34];
   __shared__ R bufA[3 * 32 * 32 + 32], bufB[3 * 16 * 16 + 16];
-  const int64_t s = blockIdx.y;
+  const SampleTile w = xcd_sample_tile();
+  const int64_t s = w.s;
   const rmg_problem P = class_problem(a.cp, s);
   SampleState st = pl.state_prev[s];
-  const bool restart = pass_control(st, a, pl, P, s, J, blockIdx.x == 0 && threadIdx.x == 0);
+  const bool restart = pass_control(st, a, pl, P, s, J, w.tile == 0 && threadIdx.x == 0);
   // a sample in the middle of its iteration keeps the coefficients formed at its start
   if (!st.active || st.cyc0 > 0) return;
   const int new_step = st.new_step;
   const int n = a.n;
-  if (pl.tcells && blockIdx.x == 0 && threadIdx.x == 0)  // timed: cells (once per sample)
+  if (pl.tcells && w.tile == 0 && threadIdx.x == 0)  // timed: cells (once per sample)
     atomicAdd(pl.tcells, (unsigned long long)n * (unsigned long long)n);
   const int T = n < kTile ? n : kTile, TL = T + 2;
   const int ntx = n / T;
-  const int tile = xcd_tile();
+  const int tile = w.tile;
   const int x0 = (tile % ntx) * T, y0 = (tile / ntx) * T;
   const int64_t N = (int64_t)n * n;
   double* p = a.p + s * N;
@@ -624,6 +625,211 @@ template <class R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; };
 template <> struct Vec16<double> { using T = double2; };
 
+// ---------------------------------------------------------------------------
+// The 64 x 64 top level of the coarse kernel in the register-block form of the
+// streaming smoother (FP32, 512 threads, two 2 x 2 blocks per thread).  Each thread
+// loads its blocks' right-hand side, coefficients and iterate from global memory
+// straight into registers (no staging of the level in LDS); LDS mirrors only the
+// iterate, with a zero ring, in the top level's place of the hierarchy.  A red-black
+// update reads two neighbours from LDS, the residual restriction eight per block and
+// no coefficient, and the coarsening of the coefficients (Section 4.2) uses the
+// block's registers.  The first red half-sweep after the coarse correction reads
+// its neighbours as iterate plus the prolongated correction (eq. transfer), so the
+// up leg needs no separate prolongation phase.  Per cell the operations and their
+// order are those of lds_cycle_top_cached, so the results are bit-identical.
+constexpr int kTopBlkM = 64;
+template <class R, int NT>
+struct TopBlk {
+  static constexpr int NB = kTopBlkM * kTopBlkM / 4 / NT;
+  Blk<R> b[NB];
+  R cdt[NB][4];
+  int bx[NB], by[NB];
+  bool live[NB];
+};
+
+template <class R, int NT>
+__device__ __forceinline__ void top_blk_setup(TopBlk<R, NT>& T, BlkRegion& g, RMG_LDS R* L, const R* F, const R* CW,
+                                              const R* CS, const R* CDT, const R* CT, const R* U, bool u_zero) {
+  constexpr int M = kTopBlkM, NB = TopBlk<R, NT>::NB;
+  g.hb = 0;
+  g.BW = M / 2;
+  g.UW = M + 2;
+  g.gbx0 = g.gby0 = 0;
+  g.mb = M / 2;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int k = (int)threadIdx.x + q * NT;
+    T.by[q] = k / (M / 2);
+    T.bx[q] = k % (M / 2);
+    T.live[q] = true;
+    blk_load(T.b[q], g, T.bx[q], T.by[q], M, F, CW, CS, CDT, CT, U, (const R*)nullptr, M / 2, u_zero, T.cdt[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L[blk_lds(g, 2 * T.bx[q] + (k & 1), 2 * T.by[q] + (k >> 1))] = T.b[q].u[k];
+  for (int e = threadIdx.x; e < 4 * (M + 1); e += NT) {
+    const int side = e / (M + 1), i = e - side * (M + 1);
+    int lx, ly;
+    if (side == 0) { lx = i - 1; ly = -1; }
+    else if (side == 1) { lx = i; ly = M; }
+    else if (side == 2) { lx = -1; ly = i; }
+    else { lx = M; ly = i - 1; }
+    L[blk_lds(g, lx, ly)] = (R)0;
+  }
+  __syncthreads();
+}
+
+template <class R, int NT>
+__device__ __forceinline__ void top_blk_sweeps(TopBlk<R, NT>& T, const BlkRegion& g, RMG_LDS R* L, int nu) {
+  for (int st = 0; st < 2 * nu; ++st) {
+    if (st & 1)
+      blk_half_sweep<R, TopBlk<R, NT>::NB, 1>(T.b, T.live, T.bx, T.by, g, L);
+    else
+      blk_half_sweep<R, TopBlk<R, NT>::NB, 0>(T.b, T.live, T.bx, T.by, g, L);
+    __syncthreads();
+  }
+}
+
+// Residual, its restriction to level 1 (zero iterate there) and, with `coarsen`, the
+// level-1 coefficients.
+template <class R, int NT>
+__device__ __forceinline__ void top_blk_restrict(const TopBlk<R, NT>& T, const BlkRegion& g, const RMG_LDS R* L,
+                                                 const LdsLevel<R>& C, bool coarsen) {
+  constexpr int MC = kTopBlkM / 2;
+#pragma unroll
+  for (int q = 0; q < TopBlk<R, NT>::NB; ++q) {
+    const Blk<R>& b = T.b[q];
+    R r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const R snb = blk_cell_snb(b, g, L, T.bx[q], T.by[q], k);
+      r[k] = (b.f[k] + snb) - b.d[k] * b.u[k];
+    }
+    const int kc = T.by[q] * MC + T.bx[q];
+    C.f[kc] = restrict4<R>(r[0], r[1], r[2], r[3]);
+    C.u[kc] = (R)0;
+    if (coarsen) {
+      C.cw[kc] = coarse_face<R>(b.vx[0][0], b.vx[1][0]);
+      C.cs[kc] = coarse_face<R>(b.vy[0][0], b.vy[1][0]);
+      C.cdt[kc] = coarse_cdt<R>(T.cdt[q][0], T.cdt[q][1], T.cdt[q][2], T.cdt[q][3]);
+      if (T.by[q] == MC - 1) C.cs[MC * MC + T.bx[q]] = coarse_face<R>(b.vy[0][2], b.vy[1][2]);
+    }
+  }
+}
+
+// Up leg: nu2 sweeps after the coarse correction of level 1 (prolongation folded into
+// the first red half-sweep), or the plain prolongation when nu2 = 0.
+template <class R, int NT>
+__device__ __forceinline__ void top_blk_up(TopBlk<R, NT>& T, const BlkRegion& g, RMG_LDS R* L, const LdsLevel<R>& C,
+                                           int nu2) {
+  constexpr int MC = kTopBlkM / 2, NB = TopBlk<R, NT>::NB;
+  if (nu2 == 0) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const R uc = C.u[T.by[q] * MC + T.bx[q]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) T.b[q].u[k] = T.b[q].u[k] + uc;
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    Blk<R>& b = T.b[q];
+    const int bx = T.bx[q], by = T.by[q];
+    const int x = 2 * bx, y = 2 * by;
+    const R uc = C.u[by * MC + bx];
+    const R z = (R)0;
+    // cell 0 = (x, y) and cell 3 = (x + 1, y + 1); their in-block neighbours are black
+    const R w0 = bx > 0 ? L[blk_lds(g, x - 1, y)] + C.u[by * MC + bx - 1] : z;
+    const R e0 = b.u[1] + uc;
+    const R s0 = by > 0 ? L[blk_lds(g, x, y - 1)] + C.u[(by - 1) * MC + bx] : z;
+    const R n0 = b.u[2] + uc;
+    const R w3 = b.u[2] + uc;
+    const R e3 = bx < MC - 1 ? L[blk_lds(g, x + 2, y + 1)] + C.u[by * MC + bx + 1] : z;
+    const R s3 = b.u[1] + uc;
+    const R n3 = by < MC - 1 ? L[blk_lds(g, x + 1, y + 2)] + C.u[(by + 1) * MC + bx] : z;
+    const R sn0 = blk_snb<R>(b.vx[0][0], b.vx[0][1], b.vy[0][0], b.vy[0][1], w0, e0, s0, n0);
+    const R sn3 = blk_snb<R>(b.vx[1][1], b.vx[1][2], b.vy[1][1], b.vy[1][2], w3, e3, s3, n3);
+    b.u[0] = blk_gs(b.f[0], sn0, b.d[0], b.rd[0]);
+    b.u[3] = blk_gs(b.f[3], sn3, b.d[3], b.rd[3]);
+    // red cells read only black ones, so they can be published at once
+    L[blk_lds(g, x, y)] = b.u[0];
+    L[blk_lds(g, x + 1, y + 1)] = b.u[3];
+  }
+  __syncthreads();
+  blk_half_sweep<R, NB, 1>(T.b, T.live, T.bx, T.by, g, L);
+  __syncthreads();
+  top_blk_sweeps<R, NT>(T, g, L, nu2 - 1);
+}
+
+#ifndef RMG_TOP_BLK
+#define RMG_TOP_BLK 1
+#endif
+// k_coarse_v on a 64 x 64 top level (FP32): the register-block top level, the levels
+// below it as lds_cycle_top_cached runs them, then the store of the correction or
+// (fin) the Picard update.
+template <class R, int NT>
+__device__ void coarse_v_top_blk(const SolveArgs& a, const StreamPlan& pl, int64_t s, int lt, const LdsHier<R>& lev,
+                                 int nlev, bool u_zero, bool fin) {
+  constexpr int M = kTopBlkM, NB = TopBlk<R, NT>::NB;
+  constexpr int64_t M2 = (int64_t)M * M;
+  lds_zero_padding<R, NT>(lev.base + lev.offset(1), M / 2, nlev - 1);
+  RMG_LDS R* L = (RMG_LDS R*)lev.base;
+  TopBlk<R, NT> T;
+  BlkRegion g;
+  R* U = (R*)pl.lv.u[lt] + s * M2;
+  top_blk_setup<R, NT>(T, g, L, (const R*)pl.lv.f[lt] + s * M2, (const R*)pl.lv.cw[lt] + s * M2,
+                       (const R*)pl.lv.cs[lt] + s * M2, (const R*)pl.lv.cdt[lt] + s * M2,
+                       (const R*)pl.lv.ctop[lt] + s * M, U, u_zero);
+  top_blk_sweeps<R, NT>(T, g, L, a.nu1);
+  top_blk_restrict<R, NT>(T, g, L, lev[1], true);
+  __syncthreads();
+  for (int gg = 0; gg < a.gamma; ++gg) {
+    if (RMG_NEST_CACHE && nlev >= 3)
+      lds_cycle_top_cached<R, NT, M / 2, 0, 1>(lev, nlev, a.nu1, a.nu2, a.gamma, gg == 0, gg == 0);
+    else
+      lds_cycle<R, NT>(lev, 1, nlev, a.nu1, a.nu2, a.gamma, gg == 0, gg == 0);
+  }
+  top_blk_up<R, NT>(T, g, L, lev[1], a.nu2);
+  using V = typename Vec2<R>::T;
+  if (!fin) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int64_t c0 = (int64_t)(2 * T.by[q]) * M + 2 * T.bx[q];
+      V o0, o1;
+      o0.x = T.b[q].u[0];
+      o0.y = T.b[q].u[1];
+      o1.x = T.b[q].u[2];
+      o1.y = T.b[q].u[3];
+      *(V*)(U + c0) = o0;
+      *(V*)(U + c0 + M) = o1;
+    }
+    return;
+  }
+  double* p = a.p + s * M2;
+  double* red = (double*)lev.base - (NT / 64 + 1);
+  double mx = 0.0, bad = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int64_t c0 = (int64_t)(2 * T.by[q]) * M + 2 * T.bx[q];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t c = c0 + (k >> 1) * M + (k & 1);
+      const double d = (double)T.b[q].u[k];
+      p[c] += d;
+      mx = fmax(mx, fabs(d));
+      if (!isfinite(d)) bad = 1.0;
+    }
+  }
+  mx = block_max<NT>(mx, red);
+  bad = block_max<NT>(bad, red);
+  if (threadIdx.x == 0) {
+    pl.dpmax[s] = (unsigned long long)__double_as_longlong(mx);
+    if (bad > 0.0) pl.state[s].nanflag = 1;
+  }
+}
+
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero_, int final_, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -642,6 +848,12 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   double* red = (double*)smem;
   R* rbase = (R*)(red + NT / 64 + 1);
   const LdsHier<R> lev = lds_hier(rbase, m);
+  if constexpr (RMG_TOP_BLK && sizeof(R) == 4 && NT == 512) {
+    if (m == kTopBlkM && nlev >= 2) {
+      coarse_v_top_blk<R, NT>(a, pl, s, lt, lev, nlev, u_zero != 0, fin != 0);
+      return;
+    }
+  }
   lds_zero_padding<R, NT>(rbase, m, nlev);
   // the top level is loaded before the first barrier: its global loads overlap the
   // start-up of the workgroup's waves

@@ -107,6 +107,7 @@ MATERN_PHI2 = (0.5, 0.1, 0.01, 1.0)
 TRAVELLING_WAVE = dict(model="vg", theta_r=0.05, theta_s=0.5, h_top=-0.4, h_bottom=0.1, h_init=-0.4,
                        init_rate=80.0, dt=1.0 / 64.0, n_steps=7, ks_baseline=0.2)
 SWEEP = dict(workload_id=4, n=32, samples_per_pair=64, n_modes=64, eps=1e-5, eps_mg=1e-5, max_picard=50)
+SWEEP_T_FINAL = 0.1
 
 # Adaptive PC_MLMC (Algorithm 1) on the van Genuchten workload above: six levels 32^2 ..
 # 1024^2 with n shifted by (L - l) * 0.1 on level l, 100 steps of dt = 0.0025 (the same
