@@ -393,4 +393,110 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
   }
 }
 
+// Up leg of cycle slot `slot` fused with the down leg of slot + 1 on the finest level
+// (the two are adjacent when a Picard iteration runs several cycles): prolongation
+// of level 1, nu2 sweeps, then - for a sample whose iteration continues - nu1 sweeps
+// of the next cycle, its residual and restriction, in one launch.  The halo is nu1 +
+// nu2 + 1 blocks, so the owned cells see exactly the values the two separate
+// kernels would compute (bit-identical results).  Input: lv.u[0] (the correction
+// the down leg of slot wrote) and level 1's correction; output: the continuing
+// samples' corrections in lv.ub[0] (the next up leg reads them there) and level 1's
+// right-hand side; a sample whose iteration ends in slot applies the Picard update
+// instead, as k_up does.
+template <class R, int TS, int NB>
+__global__ __launch_bounds__(kBlock) void k_up_down(SolveArgs a, StreamPlan pl, int slot) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[kBlock / 64];
+  const SampleTile w = xcd_sample_tile();
+  const int64_t s = w.s;
+  const SampleState sst = pl.state[s];
+  if (!slot_runs(sst, slot)) return;
+  const bool final_ = slot_last(sst, slot, 0);
+  const int m = a.n, mc = m >> 1;
+  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
+  const int ntx = m / TS;
+  const int tile = w.tile;
+  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
+  RMG_LDS R* L = (RMG_LDS R*)smem;
+  Blk<R> b[NB];
+  bool live[NB], own[NB];
+  int bx[NB], by[NB];
+  BlkRegion g;
+  const R* UC = (const R*)(1 == pl.ltop ? pl.lv.u[1] : pl.lv.ub[1]) + s * MC2;
+  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, a.nu1 + a.nu2 + 1, m, x0, y0, (const R*)pl.lv.f[0] + s * M2,
+                       (const R*)pl.lv.cw[0] + s * M2, (const R*)pl.lv.cs[0] + s * M2,
+                       (const R*)pl.lv.cdt[0] + s * M2, (const R*)pl.lv.ctop[0] + s * m,
+                       (const R*)pl.lv.u[0] + s * M2, UC, mc, false);
+  double* p = a.p + s * M2;
+  double2 pv[NB][2];
+  if (final_) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!own[q]) continue;
+      const int64_t c0 = (int64_t)(2 * (g.gby0 + by[q])) * m + 2 * (g.gbx0 + bx[q]);
+      pv[q][0] = *(const double2*)(p + c0);
+      pv[q][1] = *(const double2*)(p + c0 + m);
+    }
+  }
+  const int nsweep = 2 * a.nu2 + (final_ ? 0 : 2 * a.nu1);
+  for (int st = 0; st < nsweep; ++st) {
+    // the up leg's sweeps, then the down leg's: both start with a red half-sweep
+    const int colour = st < 2 * a.nu2 ? (st & 1) : ((st - 2 * a.nu2) & 1);
+    if (colour)
+      blk_half_sweep<R, NB, 1>(b, live, bx, by, g, L);
+    else
+      blk_half_sweep<R, NB, 0>(b, live, bx, by, g, L);
+    __syncthreads();
+  }
+  using V = typename Vec2<R>::T;
+  if (!final_) {
+    R* U = (R*)pl.lv.ub[0] + s * M2;
+    R* FC = (R*)pl.lv.f[1] + s * MC2;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!own[q]) continue;
+      R r[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const R snb = blk_cell_snb(b[q], g, L, bx[q], by[q], k);
+        r[k] = (b[q].f[k] + snb) - b[q].d[k] * b[q].u[k];
+      }
+      const int gbx = g.gbx0 + bx[q], gby = g.gby0 + by[q];
+      FC[(int64_t)gby * mc + gbx] = restrict4<R>(r[0], r[1], r[2], r[3]);
+      const int64_t c0 = (int64_t)(2 * gby) * m + 2 * gbx;
+      V o0, o1;
+      o0.x = b[q].u[0];
+      o0.y = b[q].u[1];
+      o1.x = b[q].u[2];
+      o1.y = b[q].u[3];
+      *(V*)(U + c0) = o0;
+      *(V*)(U + c0 + m) = o1;
+    }
+    return;
+  }
+  double mx = 0.0, bad = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (!own[q]) continue;
+    const int64_t c0 = (int64_t)(2 * (g.gby0 + by[q])) * m + 2 * (g.gbx0 + bx[q]);
+    const double2 p0 = pv[q][0], p1 = pv[q][1];
+    const double d0 = (double)b[q].u[0], d1 = (double)b[q].u[1], d2 = (double)b[q].u[2], d3 = (double)b[q].u[3];
+    double2 o0, o1;
+    o0.x = p0.x + d0;
+    o0.y = p0.y + d1;
+    o1.x = p1.x + d2;
+    o1.y = p1.y + d3;
+    *(double2*)(p + c0) = o0;
+    *(double2*)(p + c0 + m) = o1;
+    mx = fmax(fmax(mx, fabs(d0)), fmax(fabs(d1), fmax(fabs(d2), fabs(d3))));
+    if (!isfinite(d0) || !isfinite(d1) || !isfinite(d2) || !isfinite(d3)) bad = 1.0;
+  }
+  mx = block_max<kBlock>(mx, red);
+  bad = block_max<kBlock>(bad, red);
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(pl.dpmax + s, mx);
+    if (bad > 0.0) atomicOr(&pl.state[s].nanflag, 1);
+  }
+}
+
 }  // namespace rmg

@@ -1248,8 +1248,12 @@ static_assert(blk_nb(16, 5) <= 2 && blk_nb(16, 4) <= 1 && blk_nb(32, 5) <= 3 && 
 // Cycles from the finest level: `ncyc` cycles with uniform flags (slot = kUniform: cycle
 // k starts from zero iff k = 0 and applies the Picard update iff k = ncyc - 1), or one
 // cycle in cycle slot `slot` (flags from each sample's state).
+// Parts of a cycle from the finest level that stream_cycles launches.
+enum CyclePart { kCycleFull = 0, kCycleDown0 = 1, kCycleBelow0 = 2 };
+
 template <class R>
-static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st, int ncyc, int slot) {
+static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStream_t st, int ncyc, int slot,
+                                CyclePart part = kCycleFull) {
   const bool fp64 = sizeof(R) == 8;
   const int n = a.n;
   const int nc = n >> (a.nlev - 1);
@@ -1272,19 +1276,53 @@ static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStr
     }
     const int m = n >> l, ts = pl.ts[l];
     const unsigned tiles = (unsigned)((m / ts) * (m / ts));
-    const bool timed = tm && (tm->which & RMG_TIME_SMOOTHER_DOWN) && tm->ring[0].room();
-    hipEvent_t* ev = timed ? tm->ring[0].next() : nullptr;
-    StreamPlan plx = pl;
-    plx.tcells = timed ? tm->d_cells : nullptr;
-    launch_down<R>(ts, dim3(tiles, (unsigned)a.S), st, ev, a, plx, l, zero ? 1 : 0, slot);
+    if (!(l == 0 && part == kCycleBelow0)) {
+      const bool timed = tm && (tm->which & RMG_TIME_SMOOTHER_DOWN) && tm->ring[0].room();
+      hipEvent_t* ev = timed ? tm->ring[0].next() : nullptr;
+      StreamPlan plx = pl;
+      plx.tcells = timed ? tm->d_cells : nullptr;
+      launch_down<R>(ts, dim3(tiles, (unsigned)a.S), st, ev, a, plx, l, zero ? 1 : 0, slot);
+    }
+    if (l == 0 && part == kCycleDown0) return;
     for (int k = 0; k < a.gamma; ++k) self(self, l + 1, k == 0, last);
-    launch_up<R>(ts, dim3(tiles, (unsigned)a.S), st, a, pl, l, (l == 0 && last) ? 1 : 0, slot);
+    if (!(l == 0 && part == kCycleBelow0)) launch_up<R>(ts, dim3(tiles, (unsigned)a.S), st, a, pl, l, (l == 0 && last) ? 1 : 0, slot);
   };
   if (slot >= 0)
     cycle(cycle, 0, false, false);
   else
     for (int cyc = 0; cyc < ncyc; ++cyc) cycle(cycle, 0, cyc == 0, cyc == ncyc - 1);
   return err;
+}
+
+#ifndef RMG_FUSE_UP_DOWN
+#define RMG_FUSE_UP_DOWN 1
+#endif
+template <class R>
+static void launch_up_down(int ts, dim3 grid, hipStream_t st, const SolveArgs& a, const StreamPlan& pl, int slot) {
+  const int hb = a.nu1 + a.nu2 + 1, nb = blk_nb(ts, hb);
+  const size_t lds = blk_lds_bytes<R>(ts, hb);
+  if (ts == 16) {
+    if (nb <= 2)
+      hipLaunchKernelGGL((k_up_down<R, 16, 2>), grid, dim3(kBlock), lds, st, a, pl, slot);
+    else
+      hipLaunchKernelGGL((k_up_down<R, 16, 3>), grid, dim3(kBlock), lds, st, a, pl, slot);
+  } else {
+    if (nb <= 3)
+      hipLaunchKernelGGL((k_up_down<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, slot);
+    else
+      hipLaunchKernelGGL((k_up_down<R, 32, 4>), grid, dim3(kBlock), lds, st, a, pl, slot);
+  }
+}
+static_assert(blk_nb(16, 5) <= 2 && blk_nb(16, 9) <= 3 && blk_nb(32, 5) <= 3 && blk_nb(32, 7) <= 4,
+              "blocks per thread of the instantiated fused kernels (nu1 + nu2 <= 6 with 32 x 32 tiles)");
+// Whether the J cycle slots of a pass run with the finest level's up and down legs
+// fused between consecutive slots: several slots, a streaming finest level, fixed
+// cycle counts (residual-controlled cycling checks between cycles) and a halo that
+// the instantiated kernels cover.
+static bool fuse_up_down(const SolveArgs& a, const StreamPlan& pl, int J) {
+  const int hb = a.nu1 + a.nu2 + 1;
+  return RMG_FUSE_UP_DOWN && J >= 2 && a.cpp > 0 && pl.ltop >= 1 &&
+         blk_nb(pl.ts[0], hb) <= (pl.ts[0] == 16 ? 3 : 4);
 }
 
 // LDS of k_fine_coarse: that of k_coarse_v (the p / K staging lies in the top level's place).
@@ -1327,9 +1365,27 @@ static hipError_t stream_iteration(const SolveArgs& a, const StreamPlan& pl, hip
     plx.tcells = timed ? tm->d_cells + 4 : nullptr;
     launch_k(k_fine<R>, dim3(tiles, (unsigned)a.S), blk, 0, st, timed ? tm->ring[2].next() : nullptr, a, plx, J);
   }
-  for (int j = 0; j < J; ++j) {
-    const hipError_t err = stream_cycles<R>(a, pl, st, 1, j);
+  if (fuse_up_down(a, pl, J)) {
+    // slot j's finest up leg and slot j + 1's down leg in one launch; the fused kernel of
+    // slot j reads u and writes ub of the plan of parity j, so the plans alternate
+    StreamPlan sw = pl;
+    std::swap(sw.lv.u[0], sw.lv.ub[0]);
+    const unsigned tiles = (unsigned)((n / pl.ts[0]) * (n / pl.ts[0]));
+    hipError_t err = stream_cycles<R>(a, pl, st, 1, 0, kCycleDown0);
+    for (int j = 0; j < J && err == hipSuccess; ++j) {
+      err = stream_cycles<R>(a, pl, st, 1, j, kCycleBelow0);
+      const StreamPlan& pj = (j & 1) ? sw : pl;
+      if (j + 1 < J)
+        launch_up_down<R>(pl.ts[0], dim3(tiles, (unsigned)a.S), st, a, pj, j);
+      else
+        launch_up<R>(pl.ts[0], dim3(tiles, (unsigned)a.S), st, a, pj, 0, 0, j);
+    }
     if (err != hipSuccess) return err;
+  } else {
+    for (int j = 0; j < J; ++j) {
+      const hipError_t err = stream_cycles<R>(a, pl, st, 1, j);
+      if (err != hipSuccess) return err;
+    }
   }
   if (a.cpp == 0) {  // residual-controlled cycling: one cycle per pass, then the check
     const int64_t M2 = (int64_t)n * n;
