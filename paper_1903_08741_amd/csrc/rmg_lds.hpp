@@ -380,10 +380,12 @@ __device__ __forceinline__ double lane_value(double v, int src) {
 // lane 9 k and the pivot column of a lane's row and the pivot row by lane permutes;
 // finally the red unknowns follow from their black neighbours,
 // u_r = (f_r + sum_b a_rb u_b) / d_r.  Reciprocals: pivot_recip.
-// (Measured on one wavefront with its caches warm: 4330 clocks per solve, against 4990
-// for a branch-free variant that gathers rows into lanes for elimination with
-// wave-uniform pivot rows; single-wavefront code pays the full latency of every
-// instruction, and the readlanes of that variant outnumbered the permutes saved.)
+// (Measured on one wavefront with its caches warm: 3930 clocks per solve; 4330 with
+// a branch per neighbour direction, whose LDS loads and reciprocals then ran one
+// direction after the other; 4990 for a variant that gathers rows into lanes for
+// elimination with wave-uniform pivot rows: single-wavefront code pays the full
+// latency of every instruction, and that variant's readlanes outnumbered the
+// permutes it saved.)
 template <class R>
 __device__ __attribute__((noinline)) void coarsest_schur16(RMG_LDS R* Lu, const RMG_LDS R* Lf, const RMG_LDS R* Lcw,
                                                           const RMG_LDS R* Lcs, const RMG_LDS R* Lcdt) {
@@ -405,25 +407,35 @@ __device__ __attribute__((noinline)) void coarsest_schur16(RMG_LDS R* Lu, const 
   };
   double sv = r8 == c8 ? diag(b) : 0.0;
   double g = (double)Lf[b];
-  // red neighbours of b in the order west, east, south, north
+  // red neighbours of b in the order west, east, south, north; a neighbour outside the
+  // grid is read at b itself and its terms are selected away, so the four directions
+  // are straight-line code whose LDS loads and reciprocals overlap
+  double t[4], fr[4], krp[4];
+  bool in[4];
 #pragma unroll
   for (int dir = 0; dir < 4; ++dir) {
     const int di = dir == 0 ? -1 : dir == 1 ? 1 : 0, dj = dir == 2 ? -1 : dir == 3 ? 1 : 0;
     const int ir = ib + di, jr = jb + dj;
-    if (ir < 0 || ir >= m || jr < 0 || jr >= m) continue;
-    const int r = jr * m + ir;
+    in[dir] = ir >= 0 && ir < m && jr >= 0 && jr < m;
+    const int r = in[dir] ? jr * m + ir : b;
     const double kbr = dir == 0 ? (double)Lcw[b] : dir == 1 ? (double)Lcw[b + 1]
                      : dir == 2 ? (double)Lcs[b] : (double)Lcs[b + m];
-    const double t = kbr * pivot_recip(diag(r));
-    g = g + t * (double)Lf[r];
+    t[dir] = kbr * pivot_recip(diag(r));
+    fr[dir] = (double)Lf[r];
     // coupling of r with the column's black cell, if they are neighbours
     const int ei = ip - ir, ej = jp - jr;
-    double krp = 0.0;
-    if (ei == -1 && ej == 0) krp = (double)Lcw[r];
-    if (ei == 1 && ej == 0) krp = (double)Lcw[r + 1];
-    if (ei == 0 && ej == -1) krp = (double)Lcs[r];
-    if (ei == 0 && ej == 1) krp = (double)Lcs[r + m];
-    sv = sv - t * krp;
+    const double kw = (double)Lcw[r], ke = (double)Lcw[r + 1], ks = (double)Lcs[r], kn = (double)Lcs[r + m];
+    double k = 0.0;
+    k = (ei == -1 && ej == 0) ? kw : k;
+    k = (ei == 1 && ej == 0) ? ke : k;
+    k = (ei == 0 && ej == -1) ? ks : k;
+    k = (ei == 0 && ej == 1) ? kn : k;
+    krp[dir] = k;
+  }
+#pragma unroll
+  for (int dir = 0; dir < 4; ++dir) {
+    if (in[dir]) g = g + t[dir] * fr[dir];
+    if (in[dir]) sv = sv - t[dir] * krp[dir];
   }
   double rpiv = 0.0;
 #pragma unroll
@@ -446,8 +458,11 @@ __device__ __attribute__((noinline)) void coarsest_schur16(RMG_LDS R* Lu, const 
   if (lane < 8) {
     const int jr = lane >> 1, ir = 2 * (lane & 1) + (jr & 1);
     const int r = jr * m + ir;
-    const double uw = ir > 0 ? (double)Lu[r - 1] : 0.0, ue = ir < m - 1 ? (double)Lu[r + 1] : 0.0;
-    const double us = jr > 0 ? (double)Lu[r - m] : 0.0, un = jr < m - 1 ? (double)Lu[r + m] : 0.0;
+    // neighbours outside the grid are read at r and replaced by zero
+    const double vw = (double)Lu[ir > 0 ? r - 1 : r], ve = (double)Lu[ir < m - 1 ? r + 1 : r];
+    const double vs = (double)Lu[jr > 0 ? r - m : r], vn = (double)Lu[jr < m - 1 ? r + m : r];
+    const double uw = ir > 0 ? vw : 0.0, ue = ir < m - 1 ? ve : 0.0;
+    const double us = jr > 0 ? vs : 0.0, un = jr < m - 1 ? vn : 0.0;
     double t1 = (double)Lcw[r] * uw;
     t1 = t1 + (double)Lcw[r + 1] * ue;
     double t2 = (double)Lcs[r] * us;
