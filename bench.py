@@ -783,6 +783,20 @@ def sweep_bench(args, torch, rmg, W):
     print(json.dumps(res), flush=True)
 
 
+def tuned_schedule(ctx):
+    """The library's tuning choices after the timed calls: streaming tile edges per grid, and
+    for the batched call the compute-unit confinement and the passes per graph batch."""
+    out = {"tiles": {}, "batched_call": None}
+    for sig, val in ctx.tune_choices().items():
+        v = [int(x) for x in val.split()]
+        if sig.startswith("tiles "):
+            n = sig.split()[1].split("=")[1]
+            out["tiles"][n] = v
+        elif sig.startswith("sched ") and len(v) == 2:
+            out["batched_call"] = {"confine": bool(v[0]), "passes_per_batch": v[1]}
+    return out
+
+
 def level_report(sums, levels):
     """Per level: pairs, failed and retried pairs with their fractions, and the level mean."""
     out = []
@@ -989,6 +1003,7 @@ def main():
     dt = time.perf_counter() - t0
     ms = 1000.0 * dt / args.steps
     kt = ctx.kernel_timing(_abi.TIME_SMOOTHER_DOWN)
+    schedule = tuned_schedule(ctx)
     kc = ctx.kernel_timing(_abi.TIME_COARSE)
     kf = ctx.kernel_timing(_abi.TIME_FINE)
     ctx.set_kernel_timing(_abi.TIME_NONE)
@@ -1068,7 +1083,7 @@ def main():
                    "levels": per_level,
                    "picard_iterations_per_step": picard, "precision": args.precision,
                    "cycles_per_picard": args.cycles, "max_picard": args.max_picard,
-                   "fallback_cycles": args.fallback_cycles, "confine": args.confine},
+                   "fallback_cycles": args.fallback_cycles, "confine": args.confine, "schedule": schedule},
         "roofline": roof,
         "roofline_coarse": coarse_bound(kc),
         "roofline_fine": roof_fine,

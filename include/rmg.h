@@ -240,6 +240,12 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device, const char* tune_cache_path);
  * exceed the cap returns RMG_ENOMEM without allocating (a workspace already held above
  * a new cap is released by the next call that needs to grow it). */
 int rmg_ctx_set_workspace_limit(rmg_ctx* ctx, int64_t bytes);
+/* The context's tuning choices as text, one per line: "<device key> <signature>\t<choice>"
+ * (the tune-cache file's format; signatures "tiles ..." map to the two streaming tile
+ * edges, "sched ..." to "<confine 0|1> <passes per graph batch>").  Writes at most
+ * cap - 1 bytes and a terminating NUL into buf (buf may be NULL when cap is 0); returns
+ * the full length in bytes (excluding the NUL), or a negative rmg error code. */
+int64_t rmg_ctx_tune_dump(rmg_ctx* ctx, char* buf, int64_t cap);
 /* Release the context and its workspace (waits for its device to be idle). */
 void rmg_ctx_destroy(rmg_ctx* ctx);
 /* Text of the last error on this context ("" if none); valid until the next call. */

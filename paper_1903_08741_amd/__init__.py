@@ -122,6 +122,21 @@ class Context:
         """Cap the context's workspace (0: no cap); calls that would exceed it raise RMG_ENOMEM."""
         self._raise(self._lib.rmg_ctx_set_workspace_limit(self._h, int(nbytes)))
 
+    def tune_choices(self):
+        """The context's tuning choices: {signature: choice} (tile edges per streaming class
+        signature "tiles ...", "confine passes" per batched-call signature "sched ...")."""
+        n = self._lib.rmg_ctx_tune_dump(self._h, None, 0)
+        if n < 0:
+            self._raise(int(n))
+        buf = C.create_string_buffer(int(n) + 1)
+        self._lib.rmg_ctx_tune_dump(self._h, buf, int(n) + 1)
+        out = {}
+        for line in buf.value.decode().splitlines():
+            k, _, v = line.partition("\t")
+            i = k.find("] ")  # drop the device key "[arch cu=N] "
+            out[k[i + 2:] if k.startswith("[") and i >= 0 else k] = v
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.rmg_ctx_destroy(self._h)

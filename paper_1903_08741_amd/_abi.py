@@ -30,7 +30,7 @@ FLAG_NO_CONFINE = 256
 COST_WORK, COST_TIME = 0, 1
 
 EXPORTED = ("rmg_struct_size", "rmg_ctx_create", "rmg_ctx_destroy", "rmg_last_error",
-            "rmg_ctx_set_workspace_limit", "sample_fields", "picard_mg_solve", "picard_mg_solve_noalloc",
+            "rmg_ctx_set_workspace_limit", "rmg_ctx_tune_dump", "sample_fields", "picard_mg_solve", "picard_mg_solve_noalloc",
             "mlmc_level_estimate",
             "rmg_set_kernel_timing", "rmg_get_kernel_timing", "pc_mlmc", "rmg_mlmc_optimal_samples",
             "picard_mg_adjoint", "picard_mg_outflux")
@@ -136,6 +136,8 @@ def lib():
     L.rmg_ctx_create.restype = i32
     L.rmg_ctx_set_workspace_limit.argtypes = [vp, i64]
     L.rmg_ctx_set_workspace_limit.restype = i32
+    L.rmg_ctx_tune_dump.argtypes = [vp, C.c_char_p, i64]
+    L.rmg_ctx_tune_dump.restype = i64
     L.rmg_ctx_destroy.argtypes = [vp]
     L.rmg_ctx_destroy.restype = None
     L.rmg_last_error.argtypes = [vp]

@@ -727,6 +727,19 @@ int rmg_ctx_set_workspace_limit(rmg_ctx* c, int64_t bytes) {
   return RMG_OK;
 }
 
+int64_t rmg_ctx_tune_dump(rmg_ctx* c, char* buf, int64_t cap) {
+  if (!c || cap < 0 || (cap > 0 && !buf)) return RMG_EINVAL;
+  c->err.clear();
+  std::string text;
+  for (const auto& kv : c->tune) text += kv.first + '\t' + kv.second + '\n';
+  if (cap > 0) {
+    const size_t n = std::min<size_t>(text.size(), (size_t)cap - 1);
+    std::memcpy(buf, text.data(), n);
+    buf[n] = '\0';
+  }
+  return (int64_t)text.size();
+}
+
 static void free_timer_events(rmg_ctx* c) {
   for (auto& t : c->timers)
     for (auto& r : t.ring) {

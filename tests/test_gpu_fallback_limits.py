@@ -169,9 +169,15 @@ def test_tune_cache_is_persisted_and_reused(tmp_path):
     c1 = rmg.Context(0, tune_cache=path)
     a = c1.picard_mg_solve(128, fields, prob, opts)
     torch.cuda.synchronize()
+    choices = c1.tune_choices()
     c1.close()
     text = open(path).read()
     assert "tiles n=128 S=3" in text and "gfx" in text
+    # the context reports the same choices as the file holds (device key stripped)
+    lines = [ln.split("\t") for ln in text.splitlines()]
+    assert len(choices) == len(lines) >= 1
+    for key, val in lines:
+        assert choices[key[key.index("] ") + 2:]] == val
     mtime = os.path.getmtime(path)
     c2 = rmg.Context(0, tune_cache=path)
     b = c2.picard_mg_solve(128, fields, prob, opts)
