@@ -891,8 +891,9 @@ def main():
                     help="pcmlmc gardner: cost of Algorithm 1 against the tolerance, the finest grid refined "
                          "as eps halves (h_L ~ eps)")
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=5,
-                    help="untimed calls first (the first calls of a workload tune tiles and the schedule)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed calls first (the first calls of a workload tune tiles and the schedule: "
+                         "default 9 for the batched MLMC calls, 5 otherwise)")
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     ap.add_argument("--max-picard", type=int, default=None,
                     help="Picard iterations per step, first attempt (default 100; adjoint workload 500)")
@@ -923,6 +924,8 @@ def main():
     # the adjoint workload keeps one attempt with a 500-iteration limit: with a 100-iteration
     # first attempt and the fallback, 639 of its 1024 samples got gradients, against 835
     adj = args.workload == "adjoint"
+    if args.warmup is None:
+        args.warmup = 9 if args.workload in ("gardner", "vg") else 5
     if args.max_picard is None:
         args.max_picard = 500 if adj else 100
     if args.fallback_cycles is None:

@@ -1389,9 +1389,12 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
   // Schedule of the call: whether the whole-sample classes move to the restricted stream
   // while streaming classes run beside them (flag bit 7 forces it, bit 8 forbids it;
   // whether it helps depends on which class is critical), and the passes per batch G.
-  // Otherwise the choice is tuned per call signature across calls: each candidate runs
-  // one whole call and is timed, then the fastest (a later candidate must beat the
-  // first by 5 %) is kept and written to the tune cache.  Results never depend on it.
+  // Otherwise the choice is tuned per call signature across calls: the candidates run
+  // whole calls in turn, each timed twice (round robin, kSchedRounds rounds), then the one
+  // with the fastest of its calls is kept (a later candidate must beat the first by 2 %,
+  // about twice the call-to-call spread) and written to the tune cache.  Results never
+  // depend on it.
+  constexpr size_t kSchedRounds = 2;
   const bool can_confine = ctx->wstream && any_whole && nside > 0;
   const bool tune_sched = (opts->flags & (8 | 16)) == 0;
   std::vector<std::pair<int, int>> cands;  // (confine, G)
@@ -1422,7 +1425,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
         (g0 == 8 || g0 == 16)) {
       sched = {c0, g0};
     } else {
-      sched_cand = (int)ctx->sched_trials[skey].size();
+      sched_cand = (int)(ctx->sched_trials[skey].size() % cands.size());
       sched = cands[sched_cand];
     }
   }
@@ -1496,10 +1499,13 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
   if (sched_cand >= 0 && !ctx->tuned_now) {  // a call that also tuned tiles is not a fair trial
     auto& tr = ctx->sched_trials[skey];
     tr.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_sched0).count());
-    if (tr.size() == cands.size()) {
+    if (tr.size() == kSchedRounds * cands.size()) {
+      const size_t nc = cands.size();
+      std::vector<double> t(nc, 1e300);
+      for (size_t q = 0; q < tr.size(); ++q) t[q % nc] = std::min(t[q % nc], tr[q]);
       size_t best = 0;
-      for (size_t q = 1; q < tr.size(); ++q)
-        if (tr[q] < 0.95 * tr[0] && tr[q] < tr[best]) best = q;
+      for (size_t q = 1; q < nc; ++q)
+        if (t[q] < 0.98 * t[0] && t[q] < t[best]) best = q;
       char cv[32];
       snprintf(cv, sizeof cv, "%d %d", cands[best].first, cands[best].second);
       tune_put(ctx, skey, cv);
