@@ -244,7 +244,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(sopts, deadline_s=75.0):
+def cpu_baseline(sopts, converged=None, deadline_s=75.0):
     """Time the CPU oracle on a bounded sample of the workload, one solve per worker process.
 
     Sample: the first draws of the fine member of each level: 32 solves on 16^2, 32 on 32^2,
@@ -253,8 +253,9 @@ def cpu_baseline(sopts, deadline_s=75.0):
     measured; the workload's oracle time is (solves per grid) x (mean time per solve), over
     the worker count.  Solves still running at the deadline count with their elapsed time
     (a lower bound on their time), which makes the reported CPU rate an upper bound.
-    Converged solves are counted on both sides (the GPU value counts solves of converged
-    pairs; the oracle's rate is solves per second).
+    Converged solves are counted on both sides: the workload's time covers all its solves
+    (a failing one costs its iterations too) and the rate counts the solves of converged
+    pairs, `converged` (the GPU run's count: the twin oracle takes the same decisions).
     """
     import multiprocessing as mp
     import workloads as W
@@ -294,20 +295,22 @@ def cpu_baseline(sopts, deadline_s=75.0):
     est = sum(c * sum(per[n]) / len(per[n]) for n, c in counts.items())
     est_wall = est / cores
     total = sum(counts.values())
+    counted = total if converged is None else converged
     desc = ", ".join(f"{run[n]}x{n}^2" for n in sorted(run))
     note = ""
     if unfinished:
         note = ("; still running at the " + f"{deadline_s:.0f} s deadline: " +
                 ", ".join(f"{k} on {n}^2" for n, k in sorted(unfinished.items())) +
                 " (counted at their elapsed time, so the rate is an upper bound)")
-    return {"value": total / est_wall, "unit": "sample solves/s", "cores": cores, "kind": "oracle",
+    return {"value": counted / est_wall, "unit": "sample solves/s", "cores": cores, "kind": "oracle",
             "cpu_model": cpu_model(), "workers_cap": 16,
             "per_grid_s_per_solve": {str(n): sum(v) / len(v) for n, v in sorted(per.items())},
             "sample": f"{len(jobs)} oracle solves ({desc}; the first draws of each level's fine member, "
                       f"twin mode with the benchmark's solver and fallback settings) in {wall:.1f}s wall on "
                       f"{min(cores, len(jobs))} processes (one per core, at most 16); the {total}-solve "
                       f"workload's time is the per-grid mean time per solve times the solves per grid, "
-                      f"divided by the worker count{note}"}
+                      f"divided by the worker count; the rate counts its {counted} solves of converged "
+                      f"pairs{note}"}
 
 
 # ------------------------------------------------------------ adjoint workload
@@ -1054,7 +1057,7 @@ def main():
         t1 = time.time()
         cpu = cpu_baseline(dict(max_picard=args.max_picard, cycles_per_picard=args.cycles,
                                 cycle=args.cycle, fallback_cycles=args.fallback_cycles,
-                                fallback_max_picard=args.fallback_max_picard))
+                                fallback_max_picard=args.fallback_max_picard), converged=converged)
         log(f"cpu baseline {time.time() - t1:.1f}s")
     fb = (f", failed samples restarted with {args.fallback_cycles} {args.cycle}(2,2) per Picard step "
           f"(limit {args.fallback_max_picard})" if args.fallback_cycles else "")
