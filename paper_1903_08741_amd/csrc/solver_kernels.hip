@@ -649,7 +649,8 @@ struct TopBlk {
 
 template <class R, int NT>
 __device__ __forceinline__ void top_blk_setup(TopBlk<R, NT>& T, BlkRegion& g, RMG_LDS R* L, const R* F, const R* CW,
-                                              const R* CS, const R* CDT, const R* CT, const R* U, bool u_zero) {
+                                              const R* CS, const R* CDT, const R* CT, const R* U, bool u_zero,
+                                              const LdsHier<R>& lev, int nlev) {
   constexpr int M = kTopBlkM, NB = TopBlk<R, NT>::NB;
   g.hb = 0;
   g.BW = M / 2;
@@ -664,6 +665,8 @@ __device__ __forceinline__ void top_blk_setup(TopBlk<R, NT>& T, BlkRegion& g, RM
     T.live[q] = true;
     blk_load(T.b[q], g, T.bx[q], T.by[q], M, F, CW, CS, CDT, CT, U, (const R*)nullptr, M / 2, u_zero, T.cdt[q]);
   }
+  // the padding of the levels below, while the global loads above are in flight
+  lds_zero_padding<R, NT>(lev.base + lev.offset(1), M / 2, nlev - 1);
 #pragma unroll
   for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -774,14 +777,13 @@ __device__ void coarse_v_top_blk(const SolveArgs& a, const StreamPlan& pl, int64
                                  int nlev, bool u_zero, bool fin) {
   constexpr int M = kTopBlkM, NB = TopBlk<R, NT>::NB;
   constexpr int64_t M2 = (int64_t)M * M;
-  lds_zero_padding<R, NT>(lev.base + lev.offset(1), M / 2, nlev - 1);
   RMG_LDS R* L = (RMG_LDS R*)lev.base;
   TopBlk<R, NT> T;
   BlkRegion g;
   R* U = (R*)pl.lv.u[lt] + s * M2;
   top_blk_setup<R, NT>(T, g, L, (const R*)pl.lv.f[lt] + s * M2, (const R*)pl.lv.cw[lt] + s * M2,
                        (const R*)pl.lv.cs[lt] + s * M2, (const R*)pl.lv.cdt[lt] + s * M2,
-                       (const R*)pl.lv.ctop[lt] + s * M, U, u_zero);
+                       (const R*)pl.lv.ctop[lt] + s * M, U, u_zero, lev, nlev);
   top_blk_sweeps<R, NT>(T, g, L, a.nu1);
   top_blk_restrict<R, NT>(T, g, L, lev[1], true);
   __syncthreads();
