@@ -183,7 +183,7 @@ typedef struct {
 /* Size in bytes of the named ABI struct ("rmg_problem", "rmg_solver_opts", "rmg_kernel_timing",
  * "rmg_sample_stats", "rmg_level_sums", "rmg_level", "rmg_marginal", "rmg_pc_level",
  * "rmg_pc_opts", "rmg_pc_level_out", "rmg_pc_result"), or -1 if
- * unknown; lets bindings check their struct layouts against this build. */
+ * unknown; lets bindings check their struct layouts against the compiled library. */
 int64_t rmg_struct_size(const char* name);
 
 /* Kernel timing (diagnostics; used by the benchmark to price the kernels against the

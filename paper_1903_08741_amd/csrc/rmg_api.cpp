@@ -162,7 +162,7 @@ int check_problem(rmg_ctx* ctx, const rmg_problem* p, int n_fields) {
   const int need = p->model == RMG_VGM ? 3 : 1;
   if (n_fields < need) return fail(ctx, RMG_EINVAL, "model %d needs %d fields, got %d", p->model, need, n_fields);
   if (p->qoi != RMG_QOI_MEAN_SATURATION)
-    return fail(ctx, RMG_EINVAL, "qoi %d is not supported by this build", p->qoi);
+    return fail(ctx, RMG_EINVAL, "qoi %d is not supported by this library", p->qoi);
   if (!(p->dt > 0.0) || p->n_steps < 1) return fail(ctx, RMG_EINVAL, "need dt > 0 and n_steps >= 1");
   if (!(p->theta_s > p->theta_r)) return fail(ctx, RMG_EINVAL, "need theta_s > theta_r");
   if (p->init_profile != 0 && p->init_profile != 1) return fail(ctx, RMG_EINVAL, "init_profile must be 0 or 1");
