@@ -101,10 +101,22 @@ __device__ __forceinline__ CellFields load_fields(const double* fields, int F, i
   return f;
 }
 
+// Reciprocal by the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), each doubling its correct bits (about 1 ulp at the end).  Unlike
+// the correctly rounded division sequence it does not pass through the VCC register,
+// so independent quotients of one thread overlap instead of running one after another.
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // Harmonic mean 2ab/(a+b) of eq. five_stencil; symmetric bit-for-bit in (a, b).
 __device__ __forceinline__ double hmean(double a, double b) {
   const double s = a + b;
-  return s > 0.0 ? 2.0 * (a * b) / s : 0.0;
+  return s > 0.0 ? (2.0 * (a * b)) * recip_nr(s) : 0.0;
 }
 
 // ------------------------------------------------------- outer Picard residual
@@ -153,8 +165,9 @@ __device__ __forceinline__ FineCell fine_cell(int i, int j, int n, double pc, do
     flow += Kc * (((g_top - pc) * (2.0 * inv_h) + 1.0) * inv_h);
     r.ctop = 2.0 * Kc * inv_h2;
   }
-  r.cdt = C / dt;
-  r.f = flow - (theta - theta_old) / dt;
+  const double inv_dt = recip_nr(dt);
+  r.cdt = C * inv_dt;
+  r.f = flow - (theta - theta_old) * inv_dt;
   return r;
 }
 

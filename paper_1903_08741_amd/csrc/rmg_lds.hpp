@@ -282,18 +282,9 @@ struct CoarsestOrder {
         if ((((c % M) + (c / M)) & 1) == colour) piv[t++] = c;
   }
 };
-// Reciprocal of a wave-uniform FP64 pivot: the hardware estimate refined by two
-// Newton-Raphson steps r <- r + r (1 - x r), which double its correct bits each
-// (about 1 ulp at the end).  Unlike the correctly rounded division sequence it does
-// not pass through the VCC register, so the independent red pivots' reciprocals
-// overlap, and a black pivot's costs five dependent operations.
-__device__ __forceinline__ double pivot_recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
+// Reciprocal of a pivot: recip_nr (no VCC-serialised division sequence, so the
+// independent red pivots' reciprocals overlap).
+__device__ __forceinline__ double pivot_recip(double x) { return recip_nr(x); }
 __host__ __device__ constexpr bool grid_adjacent(int m, int a, int b) {
   const int di = a % m - b % m, dj = a / m - b / m;
   return (di == 1 || di == -1) ? dj == 0 : ((dj == 1 || dj == -1) && di == 0);
