@@ -194,7 +194,8 @@ def large_batch_roofline(torch, rmg, ctx, W, levels, marg):
     """The down-leg smoother on a batch large enough to stream from HBM: 64 samples of a
     512 x 512 grid (16.8 M cells, FP32 multigrid arrays ~0.5 GB), 64 Picard iterations of
     one step.  Fields: the 256^2 KL fields of the first 64 draws of the roofline workload,
-    each cell repeated on a 2 x 2 block."""
+    each cell repeated on a 2 x 2 block.  The Picard tolerance is set below anything the
+    iteration reaches, so that no sample stops early and every launch covers all 64 samples."""
     from paper_1903_08741_amd import _abi
     cfg = W.SMOOTHER_ROOF
     n, S = cfg["n"], cfg["n_samples"]
@@ -203,7 +204,7 @@ def large_batch_roofline(torch, rmg, ctx, W, levels, marg):
     f2 = ctx.sample_fields(n // 2, c["basis"], xi, marg).view(S, 1, n // 2, n // 2)
     fields = f2.repeat_interleave(2, dim=2).repeat_interleave(2, dim=3).reshape(S, 1, n * n).contiguous()
     prob = rmg.Problem(n_steps=1)
-    opts = rmg.SolverOpts(precision=rmg.MIXED, max_picard=64)
+    opts = rmg.SolverOpts(precision=rmg.MIXED, max_picard=64, eps_picard=1e-300)
     ctx.picard_mg_solve(n, fields, prob, opts)
     ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN)
     torch.cuda.synchronize()

@@ -58,6 +58,18 @@ __device__ __forceinline__ bool slot_last(const SampleState& st, int slot, int u
   return slot < 0 ? uniform_flag != 0 : st.cyc0 + slot + 1 == st.cpp;
 }
 
+// The fields of a sample's state that the cycle kernels branch on (active, cyc0, cpp),
+// read together: with the short-circuit in slot_runs the compiler would order the
+// second load behind a branch on the first, one more memory round trip.
+__device__ __forceinline__ SampleState slot_fields(const SampleState* p) {
+  SampleState st{};
+  st.active = p->active;
+  st.cyc0 = p->cyc0;
+  st.cpp = p->cpp;
+  asm volatile("" ::"v"(st.active), "v"(st.cyc0), "v"(st.cpp));
+  return st;
+}
+
 // Problems of one grid-size class: samples [0, seg_split) use prob[0], the rest prob[1].
 struct ClassProblems {
   rmg_problem prob[2];
@@ -76,6 +88,25 @@ struct LevelPtrs {
   void* cs[kMaxLevels];
   void* cdt[kMaxLevels];
   void* ctop[kMaxLevels];
+};
+
+// Arrays of the level of one down or up launch, resolved on the host.  The kernel
+// reads them at fixed argument offsets in its first batch of scalar loads; indexing
+// the plan's per-level tables by a level argument would need a dependent load.
+struct LegArgs {
+  const void* f;
+  const void* cw;
+  const void* cs;
+  const void* cdt;
+  const void* ctop;
+  const void* uin;  // iterate read (a down leg that starts from zero reads none)
+  void* uout;       // iterate written
+  void* fc;         // right-hand side of level l + 1 (the down legs write it)
+  const void* uc;   // correction of level l + 1 (the up legs prolong it)
+  int l, m;         // level and its edge
+  int hb;           // halo of the kernel's region in 2 x 2 blocks
+  int lgntx;        // log2 of the output tiles per row
+  unsigned mg;      // ceil(2^32 / BW), BW = TS / 2 + 2 hb blocks per region row
 };
 
 struct SolveArgs {

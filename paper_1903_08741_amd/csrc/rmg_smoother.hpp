@@ -101,43 +101,77 @@ struct BlkRegion {
 
 __device__ __forceinline__ int blk_lds(const BlkRegion& g, int lx, int ly) { return (ly + 1) * g.UW + lx + 1; }
 
-// Load block (bx, by) of the region (inside the domain) into registers; with cdt_out,
-// also its four C/dt values.
+// Raw global values of one block: its two rows of f, C/dt and the west and south
+// faces, the east faces of its right column, the south faces of the block above (or
+// the top-boundary faces), its iterate and the coarse correction of its coarse cell.
 template <class R>
-__device__ __forceinline__ void blk_load(Blk<R>& b, const BlkRegion& g, int bx, int by, int m, const R* F,
-                                         const R* CW, const R* CS, const R* CDT, const R* CTOP, const R* U,
-                                         const R* UC, int mc, bool u_zero, R* cdt_out = nullptr) {
+struct BlkRaw {
+  using V = typename Vec2<R>::T;
+  V f0, f1, t0, t1, w0, w1, s0, s1, n0, u0, u1;
+  R e0, e1, uc;
+};
+
+// Issue the loads of block (bx, by) of the region, which must lie inside the domain
+// (the caller clamps the coordinates of blocks outside it and masks them later).
+// Every load is unconditional, so the loads of all of a thread's blocks are in flight
+// before the first value is used.
+template <class R>
+__device__ __forceinline__ void blk_fetch(BlkRaw<R>& r, const BlkRegion& g, int bx, int by, int m, const R* F,
+                                          const R* CW, const R* CS, const R* CDT, const R* CTOP, const R* UC,
+                                          int mc) {
   using V = typename Vec2<R>::T;
   const int gx = 2 * (g.gbx0 + bx), gy = 2 * (g.gby0 + by);
   const int64_t c0 = (int64_t)gy * m + gx, c2 = c0 + m;
-  const V f0 = *(const V*)(F + c0), f1 = *(const V*)(F + c2);
-  const V t0 = *(const V*)(CDT + c0), t1 = *(const V*)(CDT + c2);
-  const V w0 = *(const V*)(CW + c0), w1 = *(const V*)(CW + c2);
-  const V s0 = *(const V*)(CS + c0), s1 = *(const V*)(CS + c2);
   const bool east = gx + 2 < m, north = gy + 2 < m;
-  const R e0 = east ? CW[c0 + 2] : (R)0, e1 = east ? CW[c2 + 2] : (R)0;
-  const V n0 = north ? *(const V*)(CS + c2 + m) : *(const V*)(CTOP + gx);
+  r.f0 = *(const V*)(F + c0);
+  r.f1 = *(const V*)(F + c2);
+  r.t0 = *(const V*)(CDT + c0);
+  r.t1 = *(const V*)(CDT + c2);
+  r.w0 = *(const V*)(CW + c0);
+  r.w1 = *(const V*)(CW + c2);
+  r.s0 = *(const V*)(CS + c0);
+  r.s1 = *(const V*)(CS + c2);
+  r.e0 = CW[east ? c0 + 2 : c0];
+  r.e1 = CW[east ? c2 + 2 : c2];
+  r.e0 = east ? r.e0 : (R)0;
+  r.e1 = east ? r.e1 : (R)0;
+  r.n0 = *(const V*)(north ? CS + c2 + m : CTOP + gx);
+  r.uc = UC ? UC[(int64_t)(g.gby0 + by) * mc + g.gbx0 + bx] : (R)0;
+}
+template <class R>
+__device__ __forceinline__ void blk_fetch_u(BlkRaw<R>& r, const BlkRegion& g, int bx, int by, int m, const R* U) {
+  using V = typename Vec2<R>::T;
+  const int64_t c0 = (int64_t)(2 * (g.gby0 + by)) * m + 2 * (g.gbx0 + bx);
+  r.u0 = *(const V*)(U + c0);
+  r.u1 = *(const V*)(U + c0 + m);
+}
+
+// Registers of a block from its raw values (u_zero: the iterate is zero; with UC the
+// coarse correction is added to it); with cdt_out, also its four C/dt values.
+template <class R>
+__device__ __forceinline__ void blk_build(Blk<R>& b, const BlkRaw<R>& r, bool u_zero, bool with_uc,
+                                          R* cdt_out = nullptr) {
+  using V = typename Vec2<R>::T;
   V u0, u1;
   if (u_zero) {
     u0.x = u0.y = u1.x = u1.y = (R)0;
   } else {
-    u0 = *(const V*)(U + c0);
-    u1 = *(const V*)(U + c2);
+    u0 = r.u0;
+    u1 = r.u1;
   }
-  if (UC) {
-    const R uc = UC[(int64_t)(g.gby0 + by) * mc + g.gbx0 + bx];
-    u0.x = u0.x + uc;
-    u0.y = u0.y + uc;
-    u1.x = u1.x + uc;
-    u1.y = u1.y + uc;
+  if (with_uc) {
+    u0.x = u0.x + r.uc;
+    u0.y = u0.y + r.uc;
+    u1.x = u1.x + r.uc;
+    u1.y = u1.y + r.uc;
   }
-  b.f[0] = f0.x; b.f[1] = f0.y; b.f[2] = f1.x; b.f[3] = f1.y;
+  b.f[0] = r.f0.x; b.f[1] = r.f0.y; b.f[2] = r.f1.x; b.f[3] = r.f1.y;
   b.u[0] = u0.x; b.u[1] = u0.y; b.u[2] = u1.x; b.u[3] = u1.y;
-  b.vx[0][0] = w0.x; b.vx[0][1] = w0.y; b.vx[0][2] = e0;
-  b.vx[1][0] = w1.x; b.vx[1][1] = w1.y; b.vx[1][2] = e1;
-  b.vy[0][0] = s0.x; b.vy[0][1] = s1.x; b.vy[0][2] = n0.x;
-  b.vy[1][0] = s0.y; b.vy[1][1] = s1.y; b.vy[1][2] = n0.y;
-  const R cdt[4] = {t0.x, t0.y, t1.x, t1.y};
+  b.vx[0][0] = r.w0.x; b.vx[0][1] = r.w0.y; b.vx[0][2] = r.e0;
+  b.vx[1][0] = r.w1.x; b.vx[1][1] = r.w1.y; b.vx[1][2] = r.e1;
+  b.vy[0][0] = r.s0.x; b.vy[0][1] = r.s1.x; b.vy[0][2] = r.n0.x;
+  b.vy[1][0] = r.s0.y; b.vy[1][1] = r.s1.y; b.vy[1][2] = r.n0.y;
+  const R cdt[4] = {r.t0.x, r.t0.y, r.t1.x, r.t1.y};
   if (cdt_out)
     for (int k = 0; k < 4; ++k) cdt_out[k] = cdt[k];
 #pragma unroll
@@ -151,6 +185,18 @@ __device__ __forceinline__ void blk_load(Blk<R>& b, const BlkRegion& g, int bx, 
     b.d[k] = d;
     b.rd[k] = sizeof(R) == 4 ? (R)__builtin_amdgcn_rcpf((float)d) : (R)0;
   }
+}
+
+// Load block (bx, by) of the region (inside the domain) into registers; with cdt_out,
+// also its four C/dt values.
+template <class R>
+__device__ __forceinline__ void blk_load(Blk<R>& b, const BlkRegion& g, int bx, int by, int m, const R* F,
+                                         const R* CW, const R* CS, const R* CDT, const R* CTOP, const R* U,
+                                         const R* UC, int mc, bool u_zero, R* cdt_out = nullptr) {
+  BlkRaw<R> r;
+  blk_fetch(r, g, bx, by, m, F, CW, CS, CDT, CTOP, UC, mc);
+  if (!u_zero) blk_fetch_u(r, g, bx, by, m, U);
+  blk_build(b, r, u_zero, UC != nullptr, cdt_out);
 }
 
 // Neighbour sums of the four cells of block (bx, by) from the current iterate.
@@ -184,11 +230,14 @@ __device__ __forceinline__ void blk_half_sweep(Blk<R> (&b)[NB], const bool (&liv
 }
 
 // Common set-up: the thread's blocks, their registers, the LDS iterate (zero outside
-// the domain and on the ring).  Returns after the barrier that publishes the iterate.
+// the domain and on the ring).  The loads of all of the thread's blocks are issued
+// first (a block outside the domain or the region loads a clamped in-domain block and
+// is masked), the LDS ring is cleared while they are in flight.  Returns after the
+// barrier that publishes the iterate.
 template <class R, int TS, int NB>
 __device__ __forceinline__ void blk_setup(Blk<R> (&b)[NB], bool (&live)[NB], bool (&own)[NB], int (&bx)[NB],
-                                          int (&by)[NB], BlkRegion& g, RMG_LDS R* L, int hb, int m, int x0,
-                                          int y0, const R* F, const R* CW, const R* CS, const R* CDT,
+                                          int (&by)[NB], BlkRegion& g, RMG_LDS R* L, int hb, unsigned mg, int m,
+                                          int x0, int y0, const R* F, const R* CW, const R* CS, const R* CDT,
                                           const R* CTOP, const R* U, const R* UC, int mc, bool u_zero) {
   g.hb = hb;
   g.BW = TS / 2 + 2 * hb;
@@ -197,8 +246,9 @@ __device__ __forceinline__ void blk_setup(Blk<R> (&b)[NB], bool (&live)[NB], boo
   g.gby0 = y0 / 2 - hb;
   g.mb = m / 2;
   const int nblk = g.BW * g.BW;
-  const unsigned mg = rmg_magic(g.BW);
   const int t = (int)threadIdx.x;
+  BlkRaw<R> raw[NB];
+  int cbx[NB], cby[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int k = t + q * kBlock;
@@ -207,17 +257,13 @@ __device__ __forceinline__ void blk_setup(Blk<R> (&b)[NB], bool (&live)[NB], boo
     const int gbx = g.gbx0 + bx[q], gby = g.gby0 + by[q];
     live[q] = k < nblk && gbx >= 0 && gbx < g.mb && gby >= 0 && gby < g.mb;
     own[q] = live[q] && bx[q] >= hb && bx[q] < hb + TS / 2 && by[q] >= hb && by[q] < hb + TS / 2;
+    cbx[q] = min(max(gbx, 0), g.mb - 1) - g.gbx0;
+    cby[q] = min(max(gby, 0), g.mb - 1) - g.gby0;
+    blk_fetch(raw[q], g, cbx[q], cby[q], m, F, CW, CS, CDT, CTOP, UC, mc);
   }
+  if (!u_zero) {
 #pragma unroll
-  for (int q = 0; q < NB; ++q)
-    if (live[q]) blk_load(b[q], g, bx[q], by[q], m, F, CW, CS, CDT, CTOP, U, UC, mc, u_zero);
-  // LDS iterate: every block of the region (zero outside the domain) and the zero ring
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    if (t + q * kBlock >= nblk) continue;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      L[blk_lds(g, 2 * bx[q] + (k & 1), 2 * by[q] + (k >> 1))] = live[q] ? b[q].u[k] : (R)0;
+    for (int q = 0; q < NB; ++q) blk_fetch_u(raw[q], g, cbx[q], cby[q], m, U);
   }
   const int W2 = 2 * g.BW;
   for (int e = t; e < 4 * (W2 + 1); e += kBlock) {
@@ -229,7 +275,34 @@ __device__ __forceinline__ void blk_setup(Blk<R> (&b)[NB], bool (&live)[NB], boo
     else { lx = W2; ly = i - 1; }                  // right ring column
     L[blk_lds(g, lx, ly)] = (R)0;
   }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) blk_build(b[q], raw[q], u_zero, UC != nullptr);
+  // LDS iterate: every block of the region (zero outside the domain)
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if (t + q * kBlock >= nblk) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      L[blk_lds(g, 2 * bx[q] + (k & 1), 2 * by[q] + (k >> 1))] = live[q] ? b[q].u[k] : (R)0;
+  }
   __syncthreads();
+}
+
+// Region width of a kernel's tiles: its magic number for the block enumeration.
+inline unsigned blk_magic_host(int ts, int hb) {
+  const unsigned long long w = (unsigned long long)(ts / 2 + 2 * hb);
+  return (unsigned)((0x100000000ull + w - 1ull) / w);
+}
+
+// The prologue's uniform values in scalar registers before the sample's state is
+// read: the compiler then issues every argument load in one batch instead of
+// interleaving them with the dependent loads that follow.
+__device__ __forceinline__ void sgpr_ready(const void* p) { asm volatile("" ::"s"(p)); }
+__device__ __forceinline__ void sgpr_ready(int v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ void sgpr_ready(unsigned v) { asm volatile("" ::"s"(v)); }
+template <class... T>
+__device__ __forceinline__ void sgpr_ready_all(const T&... v) {
+  (sgpr_ready(v), ...);
 }
 
 constexpr int blk_nb(int ts, int hb) {
@@ -246,31 +319,31 @@ constexpr size_t blk_lds_bytes(int ts, int hb) {
 // slot: kUniform, or the cycle slot of the pass (the finest level's u_zero then follows
 // from the sample's state: zero on the first cycle of its Picard iteration).
 template <class R, int TS, int NB>
-__global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int l, int u_zero_, int slot) {
+__global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, LegArgs lg, int u_zero_, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int m = lg.m, mc = m >> 1;
+  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
+  sgpr_ready_all((int)gridDim.x, (const void*)pl.state, lg.f, lg.cw, lg.cs, lg.cdt, lg.ctop, lg.uin, lg.uout, lg.fc, m, lg.hb, lg.lgntx, lg.mg, lg.l,
+                 u_zero_, slot, (const void*)pl.tcells);
   const SampleTile w = xcd_sample_tile();
   const int64_t s = w.s;
-  const SampleState sst = pl.state[s];
+  const SampleState sst = slot_fields(pl.state + s);
   if (!slot_runs(sst, slot)) return;
-  const int u_zero = l == 0 ? (int)slot_first(sst, slot, u_zero_) : u_zero_;
-  const int m = a.n >> l, mc = m >> 1;
+  const int u_zero = lg.l == 0 ? (int)slot_first(sst, slot, u_zero_) : u_zero_;
   // timed launches count the cells they process: once per active sample (one
   // counter update per workgroup would serialise thousands of atomics on one address)
   if (pl.tcells && w.tile == 0 && threadIdx.x == 0)
     atomicAdd(pl.tcells + (u_zero ? 0 : 1), (unsigned long long)m * (unsigned long long)m);
-  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
-  const int ntx = m / TS;
   const int tile = w.tile;
-  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
+  const int x0 = (tile & ((1 << lg.lgntx) - 1)) * TS, y0 = (tile >> lg.lgntx) * TS;
   RMG_LDS R* L = (RMG_LDS R*)smem;
   Blk<R> b[NB];
   bool live[NB], own[NB];
   int bx[NB], by[NB];
   BlkRegion g;
-  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, a.nu1 + 1, m, x0, y0, (const R*)pl.lv.f[l] + s * M2,
-                       (const R*)pl.lv.cw[l] + s * M2, (const R*)pl.lv.cs[l] + s * M2,
-                       (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m,
-                       (const R*)pl.lv.ub[l] + s * M2, nullptr, mc, u_zero != 0);
+  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, lg.hb, lg.mg, m, x0, y0, (const R*)lg.f + s * M2,
+                       (const R*)lg.cw + s * M2, (const R*)lg.cs + s * M2, (const R*)lg.cdt + s * M2,
+                       (const R*)lg.ctop + s * m, (const R*)lg.uin + s * M2, nullptr, mc, u_zero != 0);
   for (int st = 0; st < 2 * a.nu1; ++st) {
     if (st & 1)
       blk_half_sweep<R, NB, 1>(b, live, bx, by, g, L);
@@ -279,8 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
     __syncthreads();
   }
   using V = typename Vec2<R>::T;
-  R* U = (R*)pl.lv.u[l] + s * M2;
-  R* FC = (R*)pl.lv.f[l + 1] + s * MC2;
+  R* U = (R*)lg.uout + s * M2;
+  R* FC = (R*)lg.fc + s * MC2;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     if (!own[q]) continue;
@@ -308,29 +381,29 @@ __global__ __launch_bounds__(kBlock) void k_down(SolveArgs a, StreamPlan pl, int
 // and ||dp||_inf instead of a store.  Halo: nu2 blocks (2 nu2 cells).
 // slot as for k_down: on the finest level the Picard update follows the sample's last cycle.
 template <class R, int TS, int NB>
-__global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l, int final__, int slot) {
+__global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, LegArgs lg, int final__, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kBlock / 64];
+  const int m = lg.m, mc = m >> 1;
+  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
+  sgpr_ready_all((int)gridDim.x, (const void*)pl.state, lg.f, lg.cw, lg.cs, lg.cdt, lg.ctop, lg.uin, lg.uout, lg.uc, m, lg.hb, lg.lgntx, lg.mg, lg.l,
+                 final__, slot);
   const SampleTile w = xcd_sample_tile();
   const int64_t s = w.s;
-  const SampleState sst = pl.state[s];
+  const SampleState sst = slot_fields(pl.state + s);
   if (!slot_runs(sst, slot)) return;
-  const int final_ = l == 0 ? (int)slot_last(sst, slot, final__) : final__;
-  const int m = a.n >> l, mc = m >> 1;
-  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
-  const int ntx = m / TS;
+  const int final_ = lg.l == 0 ? (int)slot_last(sst, slot, final__) : final__;
   const int tile = w.tile;
-  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
+  const int x0 = (tile & ((1 << lg.lgntx) - 1)) * TS, y0 = (tile >> lg.lgntx) * TS;
   RMG_LDS R* L = (RMG_LDS R*)smem;
   Blk<R> b[NB];
   bool live[NB], own[NB];
   int bx[NB], by[NB];
   BlkRegion g;
-  const R* UC = (const R*)(l + 1 == pl.ltop ? pl.lv.u[l + 1] : pl.lv.ub[l + 1]) + s * MC2;
-  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, a.nu2, m, x0, y0, (const R*)pl.lv.f[l] + s * M2,
-                       (const R*)pl.lv.cw[l] + s * M2, (const R*)pl.lv.cs[l] + s * M2,
-                       (const R*)pl.lv.cdt[l] + s * M2, (const R*)pl.lv.ctop[l] + s * m,
-                       (const R*)pl.lv.u[l] + s * M2, UC, mc, false);
+  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, lg.hb, lg.mg, m, x0, y0, (const R*)lg.f + s * M2,
+                       (const R*)lg.cw + s * M2, (const R*)lg.cs + s * M2, (const R*)lg.cdt + s * M2,
+                       (const R*)lg.ctop + s * m, (const R*)lg.uin + s * M2, (const R*)lg.uc + s * MC2, mc,
+                       false);
   // the Picard update's FP64 head values are loaded before the sweeps, which hide
   // their latency
   double* p = a.p + s * M2;
@@ -353,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
   }
   if (!final_) {
     using V = typename Vec2<R>::T;
-    R* U = (R*)pl.lv.ub[l] + s * M2;
+    R* U = (R*)lg.uout + s * M2;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       if (!own[q]) continue;
@@ -404,29 +477,29 @@ __global__ __launch_bounds__(kBlock) void k_up(SolveArgs a, StreamPlan pl, int l
 // right-hand side; a sample whose iteration ends in slot applies the Picard update
 // instead, as k_up does.
 template <class R, int TS, int NB>
-__global__ __launch_bounds__(kBlock) void k_up_down(SolveArgs a, StreamPlan pl, int slot) {
+__global__ __launch_bounds__(kBlock) void k_up_down(SolveArgs a, StreamPlan pl, LegArgs lg, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kBlock / 64];
+  const int m = lg.m, mc = m >> 1;
+  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
+  sgpr_ready_all((int)gridDim.x, (const void*)pl.state, lg.f, lg.cw, lg.cs, lg.cdt, lg.ctop, lg.uin, lg.uout, lg.fc, lg.uc, m, lg.hb, lg.lgntx, lg.mg,
+                 slot);
   const SampleTile w = xcd_sample_tile();
   const int64_t s = w.s;
-  const SampleState sst = pl.state[s];
+  const SampleState sst = slot_fields(pl.state + s);
   if (!slot_runs(sst, slot)) return;
   const bool final_ = slot_last(sst, slot, 0);
-  const int m = a.n, mc = m >> 1;
-  const int64_t M2 = (int64_t)m * m, MC2 = (int64_t)mc * mc;
-  const int ntx = m / TS;
   const int tile = w.tile;
-  const int x0 = (tile % ntx) * TS, y0 = (tile / ntx) * TS;
+  const int x0 = (tile & ((1 << lg.lgntx) - 1)) * TS, y0 = (tile >> lg.lgntx) * TS;
   RMG_LDS R* L = (RMG_LDS R*)smem;
   Blk<R> b[NB];
   bool live[NB], own[NB];
   int bx[NB], by[NB];
   BlkRegion g;
-  const R* UC = (const R*)(1 == pl.ltop ? pl.lv.u[1] : pl.lv.ub[1]) + s * MC2;
-  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, a.nu1 + a.nu2 + 1, m, x0, y0, (const R*)pl.lv.f[0] + s * M2,
-                       (const R*)pl.lv.cw[0] + s * M2, (const R*)pl.lv.cs[0] + s * M2,
-                       (const R*)pl.lv.cdt[0] + s * M2, (const R*)pl.lv.ctop[0] + s * m,
-                       (const R*)pl.lv.u[0] + s * M2, UC, mc, false);
+  blk_setup<R, TS, NB>(b, live, own, bx, by, g, L, lg.hb, lg.mg, m, x0, y0, (const R*)lg.f + s * M2,
+                       (const R*)lg.cw + s * M2, (const R*)lg.cs + s * M2, (const R*)lg.cdt + s * M2,
+                       (const R*)lg.ctop + s * m, (const R*)lg.uin + s * M2, (const R*)lg.uc + s * MC2, mc,
+                       false);
   double* p = a.p + s * M2;
   double2 pv[NB][2];
   if (final_) {
@@ -450,8 +523,8 @@ __global__ __launch_bounds__(kBlock) void k_up_down(SolveArgs a, StreamPlan pl, 
   }
   using V = typename Vec2<R>::T;
   if (!final_) {
-    R* U = (R*)pl.lv.ub[0] + s * M2;
-    R* FC = (R*)pl.lv.f[1] + s * MC2;
+    R* U = (R*)lg.uout + s * M2;
+    R* FC = (R*)lg.fc + s * MC2;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       if (!own[q]) continue;

@@ -1209,22 +1209,47 @@ static void launch_k(K kern, dim3 grid, dim3 blk, size_t lds, hipStream_t st, hi
     hipLaunchKernelGGL(kern, grid, blk, lds, st, args...);
 }
 
+// The level's arrays of a down or up launch on level l (ts x ts tiles, a halo of hb
+// blocks), with the iterate read and written and the neighbouring level's array.
+static LegArgs leg_args(const SolveArgs& a, const StreamPlan& pl, int l, int ts, int hb, const void* uin,
+                        void* uout, void* fc, const void* uc) {
+  LegArgs g;
+  g.f = pl.lv.f[l];
+  g.cw = pl.lv.cw[l];
+  g.cs = pl.lv.cs[l];
+  g.cdt = pl.lv.cdt[l];
+  g.ctop = pl.lv.ctop[l];
+  g.uin = uin;
+  g.uout = uout;
+  g.fc = fc;
+  g.uc = uc;
+  g.l = l;
+  g.m = a.n >> l;
+  g.hb = hb;
+  int lgt = 0;
+  while ((ts << lgt) < g.m) ++lgt;
+  g.lgntx = lgt;
+  g.mg = blk_magic_host(ts, hb);
+  return g;
+}
+
 template <class R>
 static void launch_down(int ts, dim3 grid, hipStream_t st, hipEvent_t* ev, const SolveArgs& a,
                         const StreamPlan& pl, int l, int u_zero, int slot) {
   const int hb = a.nu1 + 1, nb = blk_nb(ts, hb);
   const size_t lds = blk_lds_bytes<R>(ts, hb);
   const dim3 b(kBlock);
+  const LegArgs lg = leg_args(a, pl, l, ts, hb, pl.lv.ub[l], pl.lv.u[l], pl.lv.f[l + 1], nullptr);
   if (ts == 16) {
     if (nb <= 1)
-      launch_k(k_down<R, 16, 1>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
+      launch_k(k_down<R, 16, 1>, grid, b, lds, st, ev, a, pl, lg, u_zero, slot);
     else
-      launch_k(k_down<R, 16, 2>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
+      launch_k(k_down<R, 16, 2>, grid, b, lds, st, ev, a, pl, lg, u_zero, slot);
   } else {
     if (nb <= 2)
-      launch_k(k_down<R, 32, 2>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
+      launch_k(k_down<R, 32, 2>, grid, b, lds, st, ev, a, pl, lg, u_zero, slot);
     else
-      launch_k(k_down<R, 32, 3>, grid, b, lds, st, ev, a, pl, l, u_zero, slot);
+      launch_k(k_down<R, 32, 3>, grid, b, lds, st, ev, a, pl, lg, u_zero, slot);
   }
 }
 
@@ -1233,15 +1258,17 @@ static void launch_up(int ts, dim3 grid, hipStream_t st, const SolveArgs& a, con
                       int final_, int slot) {
   const int hb = a.nu2, nb = blk_nb(ts, hb);
   const size_t lds = blk_lds_bytes<R>(ts, hb);
+  const LegArgs lg = leg_args(a, pl, l, ts, hb, pl.lv.u[l], pl.lv.ub[l], nullptr,
+                              l + 1 == pl.ltop ? pl.lv.u[l + 1] : pl.lv.ub[l + 1]);
   if (ts == 16) {
-    hipLaunchKernelGGL((k_up<R, 16, 1>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
+    hipLaunchKernelGGL((k_up<R, 16, 1>), grid, dim3(kBlock), lds, st, a, pl, lg, final_, slot);
   } else {
     if (nb <= 1)
-      hipLaunchKernelGGL((k_up<R, 32, 1>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
+      hipLaunchKernelGGL((k_up<R, 32, 1>), grid, dim3(kBlock), lds, st, a, pl, lg, final_, slot);
     else if (nb == 2)
-      hipLaunchKernelGGL((k_up<R, 32, 2>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
+      hipLaunchKernelGGL((k_up<R, 32, 2>), grid, dim3(kBlock), lds, st, a, pl, lg, final_, slot);
     else
-      hipLaunchKernelGGL((k_up<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, l, final_, slot);
+      hipLaunchKernelGGL((k_up<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, lg, final_, slot);
   }
 }
 static_assert(blk_nb(16, 5) <= 2 && blk_nb(16, 4) <= 1 && blk_nb(32, 5) <= 3 && blk_nb(32, 4) <= 3,
@@ -1303,16 +1330,18 @@ template <class R>
 static void launch_up_down(int ts, dim3 grid, hipStream_t st, const SolveArgs& a, const StreamPlan& pl, int slot) {
   const int hb = a.nu1 + a.nu2 + 1, nb = blk_nb(ts, hb);
   const size_t lds = blk_lds_bytes<R>(ts, hb);
+  const LegArgs lg = leg_args(a, pl, 0, ts, hb, pl.lv.u[0], pl.lv.ub[0], pl.lv.f[1],
+                              1 == pl.ltop ? pl.lv.u[1] : pl.lv.ub[1]);
   if (ts == 16) {
     if (nb <= 2)
-      hipLaunchKernelGGL((k_up_down<R, 16, 2>), grid, dim3(kBlock), lds, st, a, pl, slot);
+      hipLaunchKernelGGL((k_up_down<R, 16, 2>), grid, dim3(kBlock), lds, st, a, pl, lg, slot);
     else
-      hipLaunchKernelGGL((k_up_down<R, 16, 3>), grid, dim3(kBlock), lds, st, a, pl, slot);
+      hipLaunchKernelGGL((k_up_down<R, 16, 3>), grid, dim3(kBlock), lds, st, a, pl, lg, slot);
   } else {
     if (nb <= 3)
-      hipLaunchKernelGGL((k_up_down<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, slot);
+      hipLaunchKernelGGL((k_up_down<R, 32, 3>), grid, dim3(kBlock), lds, st, a, pl, lg, slot);
     else
-      hipLaunchKernelGGL((k_up_down<R, 32, 4>), grid, dim3(kBlock), lds, st, a, pl, slot);
+      hipLaunchKernelGGL((k_up_down<R, 32, 4>), grid, dim3(kBlock), lds, st, a, pl, lg, slot);
   }
 }
 static_assert(blk_nb(16, 5) <= 2 && blk_nb(16, 9) <= 3 && blk_nb(32, 5) <= 3 && blk_nb(32, 7) <= 4,
