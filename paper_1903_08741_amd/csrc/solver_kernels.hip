@@ -442,7 +442,8 @@ __device__ __forceinline__ double start_head(const SolveArgs& a, const rmg_probl
 // Every workgroup of the sample takes the same decision; the first one stores it and
 // clears this pass's maximum.  Returns whether the sample restarts from its initial state.
 __device__ __forceinline__ bool pass_control(SampleState& st, const SolveArgs& a, const StreamPlan& pl,
-                                             const rmg_problem& P, int64_t s, int J, bool store) {
+                                             const rmg_problem& P, int64_t s, int J, bool store,
+                                             unsigned long long dp_prev) {
   bool restart = false;
   if (st.fresh) {
     st.fresh = 0;
@@ -452,7 +453,7 @@ __device__ __forceinline__ bool pass_control(SampleState& st, const SolveArgs& a
     if (a.cpp == 0) {  // residual-controlled cycling: the residual check applied the correction
       if (st.mgdone) {
         st.cpp = done;  // cycles of the iteration, for the totals
-        restart = control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
+        restart = control_step(st, __longlong_as_double((long long)dp_prev), a, P);
         st.cpp = kMgCpp;
         st.cyc0 = 0;
         st.mgdone = 0;
@@ -460,7 +461,7 @@ __device__ __forceinline__ bool pass_control(SampleState& st, const SolveArgs& a
         st.cyc0 = done;
       }
     } else if (done >= st.cpp) {
-      restart = control_step(st, __longlong_as_double((long long)pl.dpmax_prev[s]), a, P);
+      restart = control_step(st, __longlong_as_double((long long)dp_prev), a, P);
       st.cyc0 = 0;
     } else {
       st.cyc0 = done;
@@ -484,11 +485,20 @@ template <class R>
 __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl, int J) {
   __shared__ double sp[34 * 34], sK[34 * 34];
   __shared__ R bufA[3 * 32 * 32 + 32], bufB[3 * 16 * 16 + 16];
+  // the arguments of the prologue in one batch of scalar loads; then the sample's
+  // state and its previous iteration's ||dp||_inf together
+  sgpr_ready_all((int)gridDim.x, (const void*)pl.state_prev, (const void*)pl.dpmax_prev, (const void*)pl.state,
+                 (const void*)pl.dpmax, (const void*)pl.mgres, (const void*)pl.active_count,
+                 (const void*)pl.count_next, (const void*)pl.tcells, (const void*)a.p, (const void*)a.theta_old,
+                 (const void*)a.fields, (const void*)a.p0, a.n, a.F, a.cpp, a.max_picard, a.fb_cpp,
+                 a.fb_max_picard, J);
   const SampleTile w = xcd_sample_tile();
   const int64_t s = w.s;
   const rmg_problem P = class_problem(a.cp, s);
   SampleState st = pl.state_prev[s];
-  const bool restart = pass_control(st, a, pl, P, s, J, w.tile == 0 && threadIdx.x == 0);
+  const unsigned long long dp_prev = pl.dpmax_prev[s];
+  asm volatile("" ::"v"(st.active), "v"(st.fresh), "v"(st.cyc0), "v"(st.jpass), "v"(dp_prev));
+  const bool restart = pass_control(st, a, pl, P, s, J, w.tile == 0 && threadIdx.x == 0, dp_prev);
   // a sample in the middle of its iteration keeps the coefficients formed at its start
   if (!st.active || st.cyc0 > 0) return;
   const int new_step = st.new_step;
@@ -773,17 +783,16 @@ __device__ __forceinline__ void top_blk_up(TopBlk<R, NT>& T, const BlkRegion& g,
 // below it as lds_cycle_top_cached runs them, then the store of the correction or
 // (fin) the Picard update.
 template <class R, int NT>
-__device__ void coarse_v_top_blk(const SolveArgs& a, const StreamPlan& pl, int64_t s, int lt, const LdsHier<R>& lev,
-                                 int nlev, bool u_zero, bool fin) {
+__device__ void coarse_v_top_blk(const SolveArgs& a, const StreamPlan& pl, const LegArgs& lg, int64_t s,
+                                 const LdsHier<R>& lev, int nlev, bool u_zero, bool fin) {
   constexpr int M = kTopBlkM, NB = TopBlk<R, NT>::NB;
   constexpr int64_t M2 = (int64_t)M * M;
   RMG_LDS R* L = (RMG_LDS R*)lev.base;
   TopBlk<R, NT> T;
   BlkRegion g;
-  R* U = (R*)pl.lv.u[lt] + s * M2;
-  top_blk_setup<R, NT>(T, g, L, (const R*)pl.lv.f[lt] + s * M2, (const R*)pl.lv.cw[lt] + s * M2,
-                       (const R*)pl.lv.cs[lt] + s * M2, (const R*)pl.lv.cdt[lt] + s * M2,
-                       (const R*)pl.lv.ctop[lt] + s * M, U, u_zero, lev, nlev);
+  R* U = (R*)lg.uout + s * M2;
+  top_blk_setup<R, NT>(T, g, L, (const R*)lg.f + s * M2, (const R*)lg.cw + s * M2, (const R*)lg.cs + s * M2,
+                       (const R*)lg.cdt + s * M2, (const R*)lg.ctop + s * M, U, u_zero, lev, nlev);
   top_blk_sweeps<R, NT>(T, g, L, a.nu1);
   top_blk_restrict<R, NT>(T, g, L, lev[1], true);
   __syncthreads();
@@ -833,12 +842,17 @@ __device__ void coarse_v_top_blk(const SolveArgs& a, const StreamPlan& pl, int64
 }
 
 template <class R, int NT>
-__global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int u_zero_, int final_, int slot) {
+__global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, LegArgs lg, int u_zero_, int final_,
+                                                 int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t s = blockIdx.x;
-  const SampleState sst = pl.state[s];
+  // every argument of the prologue in one batch of scalar loads, then the sample's state
+  sgpr_ready_all((const void*)pl.state, (const void*)pl.tcells, (const void*)pl.dpmax, (const void*)a.p, lg.f,
+                 lg.cw, lg.cs, lg.cdt, lg.ctop, lg.uout, lg.l, a.n, a.nlev, a.nu1, a.nu2, a.gamma, u_zero_, final_,
+                 slot);
+  const SampleState sst = slot_fields(pl.state + s);
   if (!slot_runs(sst, slot)) return;
-  const int lt = pl.ltop;
+  const int lt = lg.l;
   // on the finest level (lt = 0) the first and last cycle of the sample's iteration
   // follow from its state in a cycle slot; on coarser levels from the enclosing cycle
   const int u_zero = lt == 0 ? slot_first(sst, slot, u_zero_) : u_zero_;
@@ -852,7 +866,7 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   const LdsHier<R> lev = lds_hier(rbase, m);
   if constexpr (RMG_TOP_BLK && sizeof(R) == 4 && NT == 512) {
     if (m == kTopBlkM && nlev >= 2) {
-      coarse_v_top_blk<R, NT>(a, pl, s, lt, lev, nlev, u_zero != 0, fin != 0);
+      coarse_v_top_blk<R, NT>(a, pl, lg, s, lev, nlev, u_zero != 0, fin != 0);
       return;
     }
   }
@@ -862,12 +876,12 @@ __global__ __launch_bounds__(NT) void k_coarse_v(SolveArgs a, StreamPlan pl, int
   const LdsLevel<R> T = lev[0];
   using V = typename Vec16<R>::T;
   constexpr int E = 16 / sizeof(R);  // elements per vector; M2 is a multiple of E
-  const V* F = (const V*)((const R*)pl.lv.f[lt] + s * M2);
-  const V* CW = (const V*)((const R*)pl.lv.cw[lt] + s * M2);
-  const V* CS = (const V*)((const R*)pl.lv.cs[lt] + s * M2);
-  const V* CDT = (const V*)((const R*)pl.lv.cdt[lt] + s * M2);
-  const R* CT = (const R*)pl.lv.ctop[lt] + s * m;
-  R* U = (R*)pl.lv.u[lt] + s * M2;
+  const V* F = (const V*)((const R*)lg.f + s * M2);
+  const V* CW = (const V*)((const R*)lg.cw + s * M2);
+  const V* CS = (const V*)((const R*)lg.cs + s * M2);
+  const V* CDT = (const V*)((const R*)lg.cdt + s * M2);
+  const R* CT = (const R*)lg.ctop + s * m;
+  R* U = (R*)lg.uout + s * M2;
   const int nv = M2 / E;
   constexpr int VB = 4;  // vectors per array and lane whose loads are in flight together
   for (int v0 = threadIdx.x; v0 < nv; v0 += VB * NT) {
@@ -956,7 +970,7 @@ __global__ __launch_bounds__(NT) void k_fine_coarse(SolveArgs a, StreamPlan pl) 
   SampleState st = pl.state_prev[s];
   // every launch is a whole Picard iteration of its sample (all its cycles)
   st.jpass = st.cpp;
-  const bool restart = pass_control(st, a, pl, P, s, st.cpp, threadIdx.x == 0);
+  const bool restart = pass_control(st, a, pl, P, s, st.cpp, threadIdx.x == 0, pl.dpmax_prev[s]);
   if (!st.active) return;
   if (pl.tcells && threadIdx.x == 0) atomicAdd(pl.tcells, 1ull);  // timed: sample launches
   constexpr int M2 = M * M, TL = M + 2, LG = M == 64 ? 6 : M == 32 ? 5 : 4, Q = M2 / NT;
@@ -1299,7 +1313,8 @@ static hipError_t stream_cycles(const SolveArgs& a, const StreamPlan& pl, hipStr
       hipEvent_t* ev = timed ? tm->ring[1].next() : nullptr;
       StreamPlan plx = pl;
       plx.tcells = timed ? tm->d_cells + 2 : nullptr;
-      launch_k(k_coarse_v<R, kCoarseThreads>, dim3((unsigned)a.S), dim3(kCoarseThreads), lcv, st, ev, a, plx,
+      const LegArgs lg = leg_args(a, pl, l, n >> l, 0, pl.lv.u[l], pl.lv.u[l], nullptr, nullptr);
+      launch_k(k_coarse_v<R, kCoarseThreads>, dim3((unsigned)a.S), dim3(kCoarseThreads), lcv, st, ev, a, plx, lg,
                zero ? 1 : 0, last ? 1 : 0, slot);
       return;
     }
