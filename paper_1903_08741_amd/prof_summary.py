@@ -1,7 +1,7 @@
 """Summarise rocprofv3 CSV output into a short text table (per-kernel counts, durations and
 counter averages), so that a profile can be kept as a few KB of text.
 
-    python -m paper_1903_08741_amd.prof_summary DIR [--kernels REGEX] [--per-dispatch]
+    python -m paper_1903_08741_amd.prof_summary DIR [--kernels REGEX] [--by-grid]
 
 DIR is the directory given to rocprofv3 with -d; every *_kernel_stats.csv,
 *_kernel_trace.csv and *_counter_collection.csv below it is read.  Output:
@@ -9,6 +9,10 @@ DIR is the directory given to rocprofv3 with -d; every *_kernel_stats.csv,
     when present (otherwise from the stats file);
   * for counter runs, per kernel (name up to its template arguments' end) and counter: the
     number of dispatches, the mean and the sum of the counter value.
+With --by-grid, both tables are split by launch grid size (threads in x and y), and each
+row also reports the launches whose duration (or counter value) is at least half the
+row's maximum: in a batched solve the launches after the last sample stopped do no work
+and would dilute the mean.
 """
 from __future__ import annotations
 
@@ -37,6 +41,49 @@ def _short(name):
         out.append(ch)
     s = "".join(out)
     return re.sub(r"\s+", " ", s.replace("void ", "").replace("rmg::", "")).strip()
+
+
+def _full(values):
+    """Count and mean of the values at least half the maximum."""
+    mx = max(values)
+    full = [v for v in values if v >= 0.5 * mx]
+    return len(full), sum(full) / len(full)
+
+
+def grid_kernel_table(root, pattern):
+    rows = defaultdict(list)
+    for f in _files(root, "kernel_trace.csv"):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                k = _short(r.get("Kernel_Name", ""))
+                if pattern and not re.search(pattern, k):
+                    continue
+                g = f"{r.get('Grid_Size_X', '?')}x{r.get('Grid_Size_Y', '?')}"
+                rows[(k, g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    out = ["| kernel | grid (threads) | calls | avg us | full calls | full avg us |", "|---|---|---|---|---|---|"]
+    for (k, g), v in sorted(rows.items()):
+        n, m = _full(v)
+        out.append(f"| {k} | {g} | {len(v)} | {sum(v) / len(v):.2f} | {n} | {m:.2f} |")
+    return out
+
+
+def grid_counter_table(root, pattern):
+    acc = defaultdict(list)
+    for f in _files(root, "counter_collection.csv"):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                k = _short(r.get("Kernel_Name", ""))
+                if pattern and not re.search(pattern, k):
+                    continue
+                acc[(k, r.get("Grid_Size", "?"), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    if not acc:
+        return []
+    out = ["| kernel | grid (threads) | counter | dispatches | mean | full dispatches | full mean |",
+           "|---|---|---|---|---|---|---|"]
+    for (k, g, c), v in sorted(acc.items()):
+        n, m = _full(v)
+        out.append(f"| {k} | {g} | {c} | {len(v)} | {sum(v) / len(v):.6g} | {n} | {m:.6g} |")
+    return out
 
 
 def kernel_table(root, pattern):
@@ -89,11 +136,17 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("dir")
     ap.add_argument("--kernels", default="", help="only kernels whose name matches this regex")
+    ap.add_argument("--by-grid", action="store_true", help="split by launch grid size")
     a = ap.parse_args(argv)
     lines = []
-    if _files(a.dir, "kernel_trace.csv") or _files(a.dir, "kernel_stats.csv"):
-        lines += kernel_table(a.dir, a.kernels)
-    ct = counter_table(a.dir, a.kernels)
+    if a.by_grid:
+        if _files(a.dir, "kernel_trace.csv"):
+            lines += grid_kernel_table(a.dir, a.kernels)
+        ct = grid_counter_table(a.dir, a.kernels)
+    else:
+        if _files(a.dir, "kernel_trace.csv") or _files(a.dir, "kernel_stats.csv"):
+            lines += kernel_table(a.dir, a.kernels)
+        ct = counter_table(a.dir, a.kernels)
     if ct:
         lines += [""] + ct
     if not lines:
