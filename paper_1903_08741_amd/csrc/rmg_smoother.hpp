@@ -251,9 +251,11 @@ __device__ __forceinline__ void blk_setup(Blk<R> (&b)[NB], bool (&live)[NB], boo
   int cbx[NB], cby[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int k = t + q * kBlock;
-    by[q] = (int)__umulhi((unsigned)k, mg);
-    bx[q] = k - by[q] * g.BW;
+    // a thread slot beyond the region takes the region's last block (its loads then
+    // hit lines the region fetches anyway) and stays masked
+    const int k = t + q * kBlock, kk = min(k, nblk - 1);
+    by[q] = (int)__umulhi((unsigned)kk, mg);
+    bx[q] = kk - by[q] * g.BW;
     const int gbx = g.gbx0 + bx[q], gby = g.gby0 + by[q];
     live[q] = k < nblk && gbx >= 0 && gbx < g.mb && gby >= 0 && gby < g.mb;
     own[q] = live[q] && bx[q] >= hb && bx[q] < hb + TS / 2 && by[q] >= hb && by[q] < hb + TS / 2;

@@ -519,29 +519,38 @@ __global__ __launch_bounds__(kBlock) void k_fine(SolveArgs a, StreamPlan pl, int
   // in flight meanwhile.  Then the halo ring (one cell per thread): p and K only.
   constexpr int Q = (kTile * kTile + kBlock - 1) / kBlock;
   const int lgT = 31 - __clz(T);
-  double cth[Q], cC[Q], pth[Q];
+  double cth[Q], cC[Q], pth[Q], pvq[Q];
+  CellFields cfq[Q];
+  // every global load of the own cells first (a thread beyond a smaller tile reads the
+  // tile's last cell and discards it), so that they are in flight together
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = min((int)threadIdx.x + q * kBlock, T * T - 1);
+    const int64_t c = (int64_t)(y0 + (k >> lgT)) * n + x0 + (k & (T - 1));
+    cfq[q] = load_fields(a.fields, a.F, N, s, c);
+    pth[q] = new_step ? 0.0 : thold[c];
+    pvq[q] = restart ? 0.0 : p[c];
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int k = (int)threadIdx.x + q * kBlock;
-    cth[q] = cC[q] = pth[q] = 0.0;
+    cth[q] = cC[q] = 0.0;
     if (k < T * T) {
       const int lj = k >> lgT, li = k & (T - 1);
       const int64_t c = (int64_t)(y0 + lj) * n + x0 + li;
-      if (!new_step) pth[q] = thold[c];
-      double pv;
+      double pv = pvq[q];
       if (restart) {  // a restart re-initialises the head (every workgroup of the sample reads
         pv = start_head(a, P, s, c, y0 + lj, n);  // it from the initial state, not from p)
         p[c] = pv;
-      } else {
-        pv = p[c];
       }
-      const CellFields cf = load_fields(a.fields, a.F, N, s, c);
-      const Closure cl = closure(P, pv, cf.Ks, cf.alpha, cf.nvg);
+      const Closure cl = closure(P, pv, cfq[q].Ks, cfq[q].alpha, cfq[q].nvg);
       const int le = (lj + 1) * TL + li + 1;
       sp[le] = pv;
       sK[le] = cl.K;
       cth[q] = cl.theta;
       cC[q] = cl.C;
+    } else {
+      pth[q] = 0.0;
     }
   }
   for (int r = threadIdx.x; r < 4 * TL - 4; r += kBlock) {
@@ -667,14 +676,22 @@ __device__ __forceinline__ void top_blk_setup(TopBlk<R, NT>& T, BlkRegion& g, RM
   g.UW = M + 2;
   g.gbx0 = g.gby0 = 0;
   g.mb = M / 2;
+  // the loads of all of the thread's blocks are in flight before the first is used
+  BlkRaw<R> raw[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int k = (int)threadIdx.x + q * NT;
     T.by[q] = k / (M / 2);
     T.bx[q] = k % (M / 2);
     T.live[q] = true;
-    blk_load(T.b[q], g, T.bx[q], T.by[q], M, F, CW, CS, CDT, CT, U, (const R*)nullptr, M / 2, u_zero, T.cdt[q]);
+    blk_fetch(raw[q], g, T.bx[q], T.by[q], M, F, CW, CS, CDT, CT, (const R*)nullptr, M / 2);
   }
+  if (!u_zero) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) blk_fetch_u(raw[q], g, T.bx[q], T.by[q], M, U);
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) blk_build(T.b[q], raw[q], u_zero, false, T.cdt[q]);
   // the padding of the levels below, while the global loads above are in flight
   lds_zero_padding<R, NT>(lev.base + lev.offset(1), M / 2, nlev - 1);
 #pragma unroll
