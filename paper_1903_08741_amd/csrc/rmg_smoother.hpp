@@ -187,18 +187,6 @@ __device__ __forceinline__ void blk_build(Blk<R>& b, const BlkRaw<R>& r, bool u_
   }
 }
 
-// Load block (bx, by) of the region (inside the domain) into registers; with cdt_out,
-// also its four C/dt values.
-template <class R>
-__device__ __forceinline__ void blk_load(Blk<R>& b, const BlkRegion& g, int bx, int by, int m, const R* F,
-                                         const R* CW, const R* CS, const R* CDT, const R* CTOP, const R* U,
-                                         const R* UC, int mc, bool u_zero, R* cdt_out = nullptr) {
-  BlkRaw<R> r;
-  blk_fetch(r, g, bx, by, m, F, CW, CS, CDT, CTOP, UC, mc);
-  if (!u_zero) blk_fetch_u(r, g, bx, by, m, U);
-  blk_build(b, r, u_zero, UC != nullptr, cdt_out);
-}
-
 // Neighbour sums of the four cells of block (bx, by) from the current iterate.
 template <class R>
 __device__ __forceinline__ R blk_cell_snb(const Blk<R>& b, const BlkRegion& g, const RMG_LDS R* L, int bx, int by,
