@@ -191,11 +191,12 @@ int64_t rmg_struct_size(const char* name);
  * pair that the kernel's dispatch itself records (hipExtLaunchKernelGGL), so a pair
  * brackets the kernel's execution on the device, not the queue time before it; the
  * library also counts the work those launches did.  The streaming solver advances in
- * batches of eight passes (a replayed HIP graph); the first pass of a timed batch is
- * launched eagerly and timed (events of graph nodes cannot be timed).  Grid-size
- * classes with fewer than 2^22 cells per pass time every eighth batch, larger ones
- * every batch, so the totals cover a uniform one-in-64 (one-in-8) sample of the
- * launches.  Results do not depend on timing.
+ * batches of G passes (a replayed HIP graph; G = 8 or 16, chosen by the schedule
+ * tuning of a batched call); the first pass of a timed batch is launched eagerly and
+ * timed (events of graph nodes cannot be timed).  Grid-size classes with fewer than
+ * 2^22 cells per pass time every eighth batch, larger ones every batch, so the totals
+ * cover a uniform one-in-8G (one-in-G) sample of the launches.  Results do not depend
+ * on timing.
  *   RMG_TIME_SMOOTHER_DOWN: the down leg (nu1 fused red-black sweeps + residual +
  *     restriction, Section 4.2).  units = fine cells processed; algorithmic bytes per
  *     cell (each array touched once): read f, the two face coefficients and C/dt, write
