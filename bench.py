@@ -7,6 +7,12 @@ Workload (one "step" = one full pass of the hot path over one batch):
   steps of dt = 0.01, modified Picard to ||dp||_inf < 1e-8 with one V(2,2) per
   Picard step; KL sampling (64 modes) + all solves + level sums, in one call of
   mlmc_level_estimate.  Inputs are resident on the GPU before timing starts.
+  Two steps are kept in flight by default (--in-flight): two library contexts, each
+  driven by a host thread of its own, share the timed steps, so that one step's
+  latency-bound tail (the slowest 256^2 sample's fallback chain, on a few compute
+  units) overlaps the other step's work; those calls run unconfined (flag bit 8).
+  Every step still does the whole workload and returns the same results; the line
+  also reports the rate of the same steps run one after another.
 
 Prints one JSON line (see the "value", "roofline" and "cpu_baseline" keys).
 """
@@ -797,7 +803,9 @@ def tuned_schedule(ctx):
             n = sig.split()[1].split("=")[1]
             out["tiles"][n] = v
         elif sig.startswith("sched ") and len(v) == 2:
-            out["batched_call"] = {"confine": bool(v[0]), "passes_per_batch": v[1]}
+            flags = sig.rsplit("flags=", 1)[-1]
+            key = "batched_call" if flags == "0" else f"batched_call_flags_{flags}"
+            out[key] = {"confine": bool(v[0]), "passes_per_batch": v[1]}
     return out
 
 
@@ -823,6 +831,58 @@ def timed_calls(torch, ctx, levels, marg, opts, steps=1):
         sums, _, _ = ctx.mlmc_level_estimate(levels, marg, opts)
     torch.cuda.synchronize()
     return 1e3 * (time.perf_counter() - t0) / steps, sums
+
+
+def extra_contexts(rmg, ctx, n, tune_cache):
+    """n more contexts on device 0 that start with ctx's tuning choices: the tune-cache file
+    when one is given (ctx has written its choices there), else a temporary copy of them."""
+    import tempfile
+    if tune_cache:
+        return [rmg.Context(0, tune_cache=tune_cache) for _ in range(n)]
+    fd, path = tempfile.mkstemp(prefix="rmg_tune_", suffix=".txt")
+    try:
+        with os.fdopen(fd, "w") as fh:
+            fh.write(ctx.tune_text())
+        return [rmg.Context(0, tune_cache=path) for _ in range(n)]
+    finally:
+        os.unlink(path)
+
+
+def run_in_flight(torch, ctxs, steps, call):
+    """`steps` calls dealt out over the contexts, each context driven by a host thread of its
+    own on a torch stream of its own (a context is not thread safe; separate contexts share
+    nothing, so their calls overlap on the GPU).  Returns the results of every call."""
+    import threading
+    P = len(ctxs)
+    counts = [steps // P + (1 if j < steps % P else 0) for j in range(P)]
+    outs = [[] for _ in range(P)]
+    errs = []
+
+    def worker(j):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for i in range(counts[j]):
+                    outs[j].append(call(ctxs[j]))
+                    log(f"step done (context {j}, {i + 1} of {counts[j]})")
+            st.synchronize()
+        except BaseException as e:  # re-raised in the calling thread
+            errs.append(e)
+
+    th = [threading.Thread(target=worker, args=(j,)) for j in range(P) if counts[j]]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    if errs:
+        raise errs[0]
+    return [r for o in outs for r in o]
+
+
+def same_results(torch, runs):
+    """Whether every call returned the same level sums and bit-identical QoIs."""
+    s0, q0 = runs[0][0], runs[0][1]
+    return all(s == s0 and torch.equal(q.view(torch.int64), q0.view(torch.int64)) for s, q, _ in runs)
 
 
 def solver_variants(torch, rmg, ctx, levels, marg, base, total):
@@ -894,7 +954,11 @@ def main():
     ap.add_argument("--eps-sweep", action="store_true",
                     help="pcmlmc gardner: cost of Algorithm 1 against the tolerance, the finest grid refined "
                          "as eps halves (h_L ~ eps)")
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--in-flight", type=int, default=2,
+                    help="gardner/vg: steps kept in flight at once: as many library contexts, each driven "
+                         "by a host thread of its own on a stream of its own, share the timed steps "
+                         "(1: one step after another; the JSON line also reports that rate)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed calls first (the first calls of a workload tune tiles and the schedule: "
                          "default 9 for the batched MLMC calls, 5 otherwise)")
@@ -1000,21 +1064,72 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.time() - t0:.3f}s rc={rc}")
     from paper_1903_08741_amd import _abi
-    ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN | _abi.TIME_COARSE | _abi.TIME_FINE)
+    if args.in_flight < 1:
+        sys.exit("--in-flight must be at least 1")
+    ctxs = [ctx]
+    fopts = opts
+    if args.in_flight > 1:
+        if args.confine == "default":
+            # steps in flight run unconfined: the confined classes of two contexts take the
+            # same compute-unit masks on queues of their own and did not overlap (340 against
+            # 235 ms per step unconfined, the same results)
+            fopts = rmg.SolverOpts(**{**opts.__dict__})
+            fopts.flags |= rmg.FLAG_NO_CONFINE
+            for i in range(args.warmup):  # the unconfined schedule's batch length
+                ctx.mlmc_level_estimate(levels, marg, fopts)
+            torch.cuda.synchronize()
+        ctxs += extra_contexts(rmg, ctx, args.in_flight - 1, args.tune_cache)
+        for j, c in enumerate(ctxs[1:], 1):
+            for i in range(args.warmup):
+                c.mlmc_level_estimate(levels, marg, fopts)
+            torch.cuda.synchronize()
+            log(f"context {j}: {args.warmup} warm-up calls done")
+    timed_kinds = _abi.TIME_SMOOTHER_DOWN | _abi.TIME_COARSE | _abi.TIME_FINE
+    if args.in_flight == 1:
+        ctx.set_kernel_timing(timed_kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        sums, q, rc = ctx.mlmc_level_estimate(levels, marg, opts, return_qoi=True)
-        log(f"step {i} done rc={rc}")
+    if args.in_flight > 1:
+        runs = run_in_flight(torch, ctxs, args.steps,
+                             lambda c: c.mlmc_level_estimate(levels, marg, fopts, return_qoi=True))
+    else:
+        runs = []
+        for i in range(args.steps):
+            runs.append(ctx.mlmc_level_estimate(levels, marg, opts, return_qoi=True))
+            log(f"step {i} done rc={runs[-1][2]}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1000.0 * dt / args.steps
+    sums = runs[-1][0]
+    identical = same_results(torch, runs)
+    if not identical:
+        log("WARNING: the timed steps did not all return the same results")
+    converged = sum(s["n"] * (2 if lv["n_coarse"] else 1) for s, lv in zip(sums, levels))
+    sequential = None
+    if args.in_flight > 1:
+        # the per-kernel rates come from these sequential steps: with steps in flight a
+        # launch's event pair also brackets its wait for compute units that the other
+        # step's kernels hold (24 us per k_down launch with two steps fully overlapped,
+        # against 6-7 us alone)
+        for c in ctxs[1:]:
+            c.close()
+        ctx.set_kernel_timing(timed_kinds)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            ssums, _, _ = ctx.mlmc_level_estimate(levels, marg, opts)
+        torch.cuda.synchronize()
+        sms = 1e3 * (time.perf_counter() - t1) / args.steps
+        sequential = {"ms_per_step": sms, "value": converged / (sms / 1e3), "steps": args.steps,
+                      "same_level_sums": ssums == sums,
+                      "note": "the same steps one after another on one context with the tuned schedule "
+                              "(outside the timed region)"}
+        log(f"sequential: {sms:.1f} ms per step")
     kt = ctx.kernel_timing(_abi.TIME_SMOOTHER_DOWN)
     schedule = tuned_schedule(ctx)
     kc = ctx.kernel_timing(_abi.TIME_COARSE)
     kf = ctx.kernel_timing(_abi.TIME_FINE)
     ctx.set_kernel_timing(_abi.TIME_NONE)
-    converged = sum(s["n"] * (2 if lv["n_coarse"] else 1) for s, lv in zip(sums, levels))
     per_level = level_report(sums, levels)
     for r in per_level:
         log(f"level {r['level']} ({r['grid']}^2): pairs {r['pairs']} failed {r['failed']} retried {r['retried']} "
@@ -1026,7 +1141,8 @@ def main():
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "traffic": None if vg else recorded_traffic(),
             "kernel": "k_down (nu1 fused red-black sweeps + residual + restriction, level-streaming path)",
-            "timing": "kernel execution time: each timed launch's event pair is recorded by its dispatch",
+            "timing": "kernel execution time: each timed launch's event pair is recorded by its dispatch"
+                      + (" (over the sequential steps: see 'sequential')" if args.in_flight > 1 else ""),
             "launches": kt["launches"], "avg_launch_us": 1e3 * kt["total_ms"] / max(1, kt["launches"]),
             "algo_bytes_per_launch": kt["algo_bytes"] / max(1, kt["launches"]),
             "compulsory_bytes_per_cell": 5.25 * es,
@@ -1090,7 +1206,11 @@ def main():
                    "levels": per_level,
                    "picard_iterations_per_step": picard, "precision": args.precision,
                    "cycles_per_picard": args.cycles, "max_picard": args.max_picard,
-                   "fallback_cycles": args.fallback_cycles, "confine": args.confine, "schedule": schedule},
+                   "fallback_cycles": args.fallback_cycles, "confine": args.confine, "schedule": schedule,
+                   "steps_in_flight": args.in_flight,
+                   "in_flight_confine": ("off" if fopts is not opts else args.confine) if args.in_flight > 1 else None},
+        "in_flight_results_identical": identical,
+        "sequential": sequential,
         "roofline": roof,
         "roofline_coarse": coarse_bound(kc),
         "roofline_fine": roof_fine,

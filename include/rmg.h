@@ -20,7 +20,17 @@
  *   Pointers named d_* are device memory, h_* host memory; all are owned by the
  *   caller and must stay valid until the work enqueued on `stream` completes.
  *   The context owns only its workspace (grown on demand, reused across calls,
- *   freed by rmg_ctx_destroy).  A context is not thread safe.
+ *   freed by rmg_ctx_destroy).  A context is not thread safe: calls on one context
+ *   must not overlap.  Separate contexts share no host state, so calls on different
+ *   contexts may run at the same time from different host threads; their GPU work
+ *   then overlaps (each context has its own streams and workspace) and the results
+ *   are those of the calls made one at a time.  Such calls should not confine their
+ *   classes (mlmc_level_estimate flag bit 8): the confined classes of every context
+ *   run on compute-unit-masked queues with the same masks, and two confined contexts
+ *   were measured not to overlap.  Every context adds 16 streams, 8 of them masked,
+ *   each on a hardware queue of its own: beyond two contexts per device the queues
+ *   are oversubscribed and every call slows down.  (The allocation-free entry point
+ *   is the exception to all of this: every call on one GPU shares its scratch array.)
  *   Every call returns an rmg_status; on failure rmg_last_error() explains it.
  *   No C++ exception crosses this interface.
  */

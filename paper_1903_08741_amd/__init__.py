@@ -122,16 +122,21 @@ class Context:
         """Cap the context's workspace (0: no cap); calls that would exceed it raise RMG_ENOMEM."""
         self._raise(self._lib.rmg_ctx_set_workspace_limit(self._h, int(nbytes)))
 
-    def tune_choices(self):
-        """The context's tuning choices: {signature: choice} (tile edges per streaming class
-        signature "tiles ...", "confine passes" per batched-call signature "sched ...")."""
+    def tune_text(self) -> str:
+        """The context's tuning choices in the tune-cache file's format (rmg_ctx_tune_dump):
+        written to a file and given to a new context, they start it tuned."""
         n = self._lib.rmg_ctx_tune_dump(self._h, None, 0)
         if n < 0:
             self._raise(int(n))
         buf = C.create_string_buffer(int(n) + 1)
         self._lib.rmg_ctx_tune_dump(self._h, buf, int(n) + 1)
+        return buf.value.decode()
+
+    def tune_choices(self):
+        """The context's tuning choices: {signature: choice} (tile edges per streaming class
+        signature "tiles ...", "confine passes" per batched-call signature "sched ...")."""
         out = {}
-        for line in buf.value.decode().splitlines():
+        for line in self.tune_text().splitlines():
             k, _, v = line.partition("\t")
             i = k.find("] ")  # drop the device key "[arch cu=N] "
             out[k[i + 2:] if k.startswith("[") and i >= 0 else k] = v

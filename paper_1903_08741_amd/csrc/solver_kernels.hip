@@ -15,6 +15,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 #include "rmg_device.hpp"
 #include "rmg_internal.hpp"
@@ -297,10 +299,29 @@ size_t whole_sample_lds_bytes(int n, int nc, bool fp64, int F, bool* state_in_ld
   return b <= cap ? b : 0;
 }
 
+// The dynamic-LDS limit of a kernel is a property of the kernel on its device, not of
+// a context: it is only ever raised (to the largest size a launch has needed so far),
+// under a lock, so that calls on separate contexts from separate host threads cannot
+// lower it between another call's setting and its launch.
+constexpr int kLdsDevices = 64;  // devices of one process whose limits are tracked
+static hipError_t raise_dyn_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> set[kLdsDevices];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kLdsDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = set[dev][fn];
+  if (bytes <= cur) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) cur = bytes;
+  return e;
+}
+
 template <class R, int NT, bool SL>
 static hipError_t launch_ws(const SolveArgs& a, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_whole_sample<R, NT, SL>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = raise_dyn_lds((const void*)k_whole_sample<R, NT, SL>, lds);
   if (e != hipSuccess) return e;
   // grid dimension x holds at most 2^31 - 1 workgroups: larger classes go out in parts
   constexpr int64_t kMaxGrid = 1 << 30;
@@ -1464,12 +1485,10 @@ static hipError_t set_stream_lds(const SolveArgs& a, const StreamPlan& pl) {
   const bool fp64 = sizeof(R) == 8;
   const int nc = a.n >> (a.nlev - 1);
   // (the down and up kernels need at most 23 KiB of LDS, below the default limit)
-  hipError_t e = hipFuncSetAttribute((const void*)k_coarse_v<R, kCoarseThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)coarse_lds(a.n >> pl.ltop, nc, fp64));
+  hipError_t e = raise_dyn_lds((const void*)k_coarse_v<R, kCoarseThreads>, coarse_lds(a.n >> pl.ltop, nc, fp64));
   if constexpr (sizeof(R) == 4) {
     if (e == hipSuccess && fine_coarse_fits<R>(a, pl))
-      e = hipFuncSetAttribute((const void*)k_fine_coarse<R, kCoarseThreads, kFusedM>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)fine_coarse_lds(a.n, nc));
+      e = raise_dyn_lds((const void*)k_fine_coarse<R, kCoarseThreads, kFusedM>, fine_coarse_lds(a.n, nc));
   }
   return e;
 }
