@@ -848,24 +848,45 @@ def extra_contexts(rmg, ctx, n, tune_cache):
         os.unlink(path)
 
 
-def run_in_flight(torch, ctxs, steps, call):
+def torch_side_stream(torch):
+    """A context manager that puts the calling thread's torch work on a new stream and waits
+    for that stream on exit."""
+    import contextlib
+
+    @contextlib.contextmanager
+    def on_stream():
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            yield
+        st.synchronize()
+    return on_stream
+
+
+def in_flight_counts(steps, P):
+    """Steps per context when `steps` are dealt out over P contexts (the first ones take one
+    more when P does not divide steps)."""
+    return [steps // P + (1 if j < steps % P else 0) for j in range(P)]
+
+
+def run_in_flight(torch, ctxs, steps, call, on_stream=None):
     """`steps` calls dealt out over the contexts, each context driven by a host thread of its
-    own on a torch stream of its own (a context is not thread safe; separate contexts share
-    nothing, so their calls overlap on the GPU).  Returns the results of every call."""
+    own on a stream of its own (on_stream; default a new torch stream per thread).  A context
+    is not thread safe; separate contexts share nothing, so their calls overlap on the GPU.
+    Returns the results of every call (context by context); an exception in any thread is
+    re-raised here after every thread has ended."""
     import threading
+    on_stream = on_stream or torch_side_stream(torch)
     P = len(ctxs)
-    counts = [steps // P + (1 if j < steps % P else 0) for j in range(P)]
+    counts = in_flight_counts(steps, P)
     outs = [[] for _ in range(P)]
     errs = []
 
     def worker(j):
         try:
-            st = torch.cuda.Stream()
-            with torch.cuda.stream(st):
+            with on_stream():
                 for i in range(counts[j]):
                     outs[j].append(call(ctxs[j]))
                     log(f"step done (context {j}, {i + 1} of {counts[j]})")
-            st.synchronize()
         except BaseException as e:  # re-raised in the calling thread
             errs.append(e)
 
