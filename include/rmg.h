@@ -27,10 +27,12 @@
  *   are those of the calls made one at a time.  Such calls should not confine their
  *   classes (mlmc_level_estimate flag bit 8): the confined classes of every context
  *   run on compute-unit-masked queues with the same masks, and two confined contexts
- *   were measured not to overlap.  Every context adds 16 streams, 8 of them masked,
- *   each on a hardware queue of its own: beyond two contexts per device the queues
- *   are oversubscribed and every call slows down.  (The allocation-free entry point
- *   is the exception to all of this: every call on one GPU shares its scratch array.)
+ *   were measured not to overlap.  A context holds 8 streams, and 8 more with
+ *   compute-unit masks (each on a hardware queue of its own) from its first confined
+ *   call on.  Two contexts in flight on one device measured best: with three, every
+ *   context's streams share the same few hardware queues and the calls slowed down.
+ *   (The allocation-free entry point is the exception to all of this: every call on
+ *   one GPU shares its scratch array.)
  *   Every call returns an rmg_status; on failure rmg_last_error() explains it.
  *   No C++ exception crosses this interface.
  */

@@ -86,7 +86,11 @@ struct rmg_ctx {
   hipEvent_t tev[2] = {};
   // set-up of each streaming class done (the whole-sample launches wait for them)
   hipEvent_t iev[16] = {};
-  // whole-sample classes' stream restricted to part of the compute units (or null)
+  // compute-unit masks are available (the device has at least 32 compute units)
+  bool can_mask = false;
+  int cus = 0;
+  // whole-sample classes' stream restricted to part of the compute units (null until the
+  // context's first confined call)
   hipStream_t wstream = nullptr;
   hipEvent_t wev = nullptr;
   // streams for the streaming classes other than the largest grid, restricted too (or null)
@@ -619,6 +623,29 @@ int64_t rmg_struct_size(const char* name) {
   return -1;
 }
 
+// The compute-unit-masked streams of confined calls, made by a context's first confined
+// call: each holds a hardware queue of its own, and a context that never confines (such as
+// one of several contexts driven at the same time, whose calls run unconfined) then holds
+// none.  The whole-sample stream is made last, so that its presence means all are there.
+static hipError_t ensure_masked_streams(rmg_ctx* c) {
+  if (c->wstream) return hipSuccess;
+  auto mask_of = [c](int pct) {
+    const int keep = std::max(32, c->cus * pct / 100 / 32 * 32);
+    std::vector<uint32_t> m((c->cus + 31) / 32, 0u);
+    for (int k = 0; k < keep; ++k) m[k / 32] |= 1u << (k % 32);
+    return m;
+  };
+  hipError_t e = hipSuccess;
+#if RMG_OTHER_CU_PCT > 0
+  const std::vector<uint32_t> m2 = mask_of(RMG_OTHER_CU_PCT);
+  for (auto& ms : c->mside)
+    if (!ms && (e = hipExtStreamCreateWithCUMask(&ms, (uint32_t)m2.size(), m2.data())) != hipSuccess) return e;
+#endif
+  if (!c->wev && (e = hipEventCreateWithFlags(&c->wev, hipEventDisableTiming)) != hipSuccess) return e;
+  const std::vector<uint32_t> m = mask_of(RMG_WHOLE_CU_PCT);
+  return hipExtStreamCreateWithCUMask(&c->wstream, (uint32_t)m.size(), m.data());
+}
+
 int rmg_ctx_create(rmg_ctx** out, int hip_device, const char* tune_cache_path) {
   if (!out) return RMG_EINVAL;
   *out = nullptr;
@@ -682,24 +709,8 @@ int rmg_ctx_create(rmg_ctx** out, int hip_device, const char* tune_cache_path) {
       rmg_ctx_destroy(c);
       return RMG_EHIP;
     }
-    const int keep = std::max(32, cus * RMG_WHOLE_CU_PCT / 100 / 32 * 32);
-    std::vector<uint32_t> mask((cus + 31) / 32, 0u);
-    for (int k = 0; k < keep; ++k) mask[k / 32] |= 1u << (k % 32);
-    if (hipExtStreamCreateWithCUMask(&c->wstream, (uint32_t)mask.size(), mask.data()) != hipSuccess ||
-        hipEventCreateWithFlags(&c->wev, hipEventDisableTiming) != hipSuccess) {
-      rmg_ctx_destroy(c);
-      return RMG_EHIP;
-    }
-#if RMG_OTHER_CU_PCT > 0
-    const int keep2 = std::max(32, cus * RMG_OTHER_CU_PCT / 100 / 32 * 32);
-    std::vector<uint32_t> mask2((cus + 31) / 32, 0u);
-    for (int k = 0; k < keep2; ++k) mask2[k / 32] |= 1u << (k % 32);
-    for (auto& ms : c->mside)
-      if (hipExtStreamCreateWithCUMask(&ms, (uint32_t)mask2.size(), mask2.data()) != hipSuccess) {
-        rmg_ctx_destroy(c);
-        return RMG_EHIP;
-      }
-#endif
+    c->can_mask = true;  // the masked streams are made by the first confined call
+    c->cus = cus;
   }
 #endif
   for (auto& e : c->tev) {
@@ -1395,7 +1406,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
   // about twice the call-to-call spread) and written to the tune cache.  Results never
   // depend on it.
   constexpr size_t kSchedRounds = 2;
-  const bool can_confine = ctx->wstream && any_whole && nside > 0;
+  const bool can_confine = ctx->can_mask && any_whole && nside > 0;
   const bool tune_sched = (opts->flags & (8 | 16)) == 0;
   std::vector<std::pair<int, int>> cands;  // (confine, G)
   for (int G : {8, 16}) {
@@ -1434,6 +1445,7 @@ int mlmc_level_estimate(rmg_ctx* ctx, int n_levels, const rmg_level* L, int n_fi
   const bool wmasked = can_confine && sched.first;
   std::vector<hipStream_t> sused(ctx->side, ctx->side + nside);
   if (wmasked) {
+    HIP_TRY(ctx, ensure_masked_streams(ctx));
     HIP_TRY(ctx, hipStreamWaitEvent(ctx->wstream, ctx->ev[0], 0));
     for (auto& j : jobs)
       if (j.whole) j.stream = ctx->wstream;
