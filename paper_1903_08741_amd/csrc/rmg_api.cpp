@@ -284,7 +284,11 @@ void load_tune_cache(rmg_ctx* ctx) {
 
 void save_tune_cache(const rmg_ctx* ctx) {
   if (ctx->tune_path.empty()) return;
-  const std::string tmp = ctx->tune_path + ".tmp";
+  // a temporary file of this context's own: contexts that share the cache file and tune at
+  // the same time then never write into one another's copy (the last rename wins whole)
+  char tag[32];
+  snprintf(tag, sizeof tag, ".tmp%llx", (unsigned long long)(uintptr_t)ctx);
+  const std::string tmp = ctx->tune_path + tag;
   {
     std::ofstream out(tmp, std::ios::trunc);
     if (!out) return;  // an unwritable cache only costs tuning time in later processes

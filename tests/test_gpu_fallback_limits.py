@@ -173,6 +173,7 @@ def test_tune_cache_is_persisted_and_reused(tmp_path):
     c1.close()
     text = open(path).read()
     assert "tiles n=128 S=3" in text and "gfx" in text
+    assert os.listdir(tmp_path) == ["rmg_tune.txt"]  # the context's temporary copy was renamed
     # the context reports the same choices as the file holds (device key stripped)
     lines = [ln.split("\t") for ln in text.splitlines()]
     assert len(choices) == len(lines) >= 1
