@@ -18,12 +18,15 @@ import scipy.linalg as sla
 from . import constitutive
 
 
-def solve_column(problem, fields_col, n, eps=1e-13, max_picard=200):
-    """Backward Euler + modified Picard (Section 4.1) on a column; returns p at the final time [n]."""
+def solve_column(problem, fields_col, n, eps=1e-13, max_picard=200, counts=False):
+    """Backward Euler + modified Picard (Section 4.1) on a column; returns p at the final time [n]
+    (with counts=True also the Picard iterations of every step, the one that met the stopping
+    test included)."""
     h, dt = 1.0 / n, problem["dt"]
     gb, gt = problem["h_bottom"], problem["h_top"]
     p = np.full(n, float(problem["h_init"]))
     _, th_old, _ = constitutive.evaluate(problem, p, fields_col)
+    its = []
     for _ in range(problem["n_steps"]):
         for _k in range(max_picard):
             K, th, C = constitutive.evaluate(problem, p, fields_col)
@@ -48,5 +51,6 @@ def solve_column(problem, fields_col, n, eps=1e-13, max_picard=200):
             p = p + dp
             if np.max(np.abs(dp)) < eps:
                 break
+        its.append(_k + 1)
         _, th_old, _ = constitutive.evaluate(problem, p, fields_col)
-    return p
+    return (p, its) if counts else p

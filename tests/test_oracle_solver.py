@@ -284,3 +284,18 @@ def test_non_finite_fields_are_rejected_without_solving():
         f[3, 4] = bad
         r = picard.solve(dict(W.GARDNER_INFILTRATION, n_steps=2), {"Ks": f}, n, dict(W.SOLVER), mode="mg")
         assert r["status"] == picard.STATUS_NONFINITE and r["picard"] == [] and r["cycles"] == 0
+
+
+def test_picard_counts_match_independent_column_solver(kl_basis_small):
+    """The 2-D modified Picard loop (exact linear solves) takes, step by step, as many
+    iterations as the independent 1-D column code on an x-constant field: the same
+    stopping test on the same iterates (Section 4.1)."""
+    n = 16
+    zfield = _field(kl_basis_small, n, 6)[:, 9]
+    Ks2 = np.repeat(zfield[:, None], n, axis=1)
+    prob = dict(W.GARDNER_INFILTRATION, n_steps=4)
+    r = picard.solve(prob, {"Ks": Ks2}, n, dict(W.SOLVER, eps_picard=1e-8, max_picard=300), mode="direct")
+    col, its = onedim.solve_column(prob, {"Ks": zfield}, n, eps=1e-8, counts=True)
+    assert r["status"] == 0
+    assert list(r["picard"]) == its and min(its) > 1
+    assert np.max(np.abs(r["p"] - col[:, None])) <= 1e-8 * np.max(np.abs(col))
