@@ -8,7 +8,8 @@ What fixes each part, independently of the oracle's own code:
   * multigrid: cycles converge to the sparse direct solution of the same system;
   * gravity and boundary treatment: the hydrostatic state is stationary for any
     conductivity field; the steady 1-D Gardner profile has a closed form;
-  * 2-D code vs an independent 1-D column code on x-constant fields;
+  * 2-D code vs an independent 1-D column code on x-constant fields (the solution, and
+    the Picard iterations of every step with exact linear solves);
   * modified Picard: mass balance per step; twin (one cycle per step) and
     lexicographic-smoother variants reach the same fixed point as sparse LU.
 """
