@@ -8,9 +8,10 @@ step.  The oracle cannot solve all 6816 samples in a test, so:
     mixed-precision bar) and convergence status;
   - properties at any size: the level sums equal the exactly rounded sums of the
     returned QoIs; a pair counts as failed exactly when one of its QoIs is NaN;
-  - reproducibility: graph replay, eager launches, timed eager launches and the
-    classes confined to parts of the compute units (flag bit 7) give
-    bit-identical results (no result may depend on workgroup scheduling).
+  - reproducibility: graph replay, eager launches, timed eager launches, the
+    classes confined to parts of the compute units (flag bit 7) and never confined
+    (flag bit 8, as the benchmark's steps in flight run) give bit-identical results
+    (no result may depend on workgroup scheduling).
 """
 from __future__ import annotations
 
@@ -63,7 +64,8 @@ def runs(basis):
     ctx = rmg.Context(0)
     out = {}
     for name, flags, timed in (("graph", 0, False), ("eager", rmg.FLAG_EAGER, False), ("timed", 0, True),
-                               ("graph2", 0, False), ("confined", rmg.FLAG_CONFINE, False)):
+                               ("graph2", 0, False), ("confined", rmg.FLAG_CONFINE, False),
+                               ("unconfined", rmg.FLAG_NO_CONFINE, False)):
         say(f"full-size 5-level MLMC run: {name}")
         ctx.set_kernel_timing(_abi.TIME_SMOOTHER_DOWN if timed else _abi.TIME_NONE)
         opts = rmg.SolverOpts(precision=rmg.MIXED, max_picard=MAX_PICARD, flags=flags)
@@ -85,7 +87,7 @@ def _offsets():
 
 def test_full_size_bitwise_reproducible(runs):
     sums0, q0, rc0 = runs["graph"]
-    for name in ("eager", "timed", "graph2", "confined"):
+    for name in ("eager", "timed", "graph2", "confined", "unconfined"):
         sums, q, rc = runs[name]
         assert rc == rc0
         assert np.array_equal(q, q0, equal_nan=True), name
