@@ -21,7 +21,9 @@
  *   caller and must stay valid until the work enqueued on `stream` completes.
  *   The context owns only its workspace (grown on demand, reused across calls,
  *   freed by rmg_ctx_destroy).  A context is not thread safe: calls on one context
- *   must not overlap.  Separate contexts share no host state, so calls on different
+ *   must not overlap.  Separate contexts share no host state (beyond each kernel's
+ *   dynamic-LDS limit, only ever raised and under a lock, and a tune-cache file given
+ *   to several of them, which each rewrites whole), so calls on different
  *   contexts may run at the same time from different host threads; their GPU work
  *   then overlaps (each context has its own streams and workspace) and the results
  *   are those of the calls made one at a time.  Such calls should not confine their
