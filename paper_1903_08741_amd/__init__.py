@@ -106,7 +106,12 @@ def _check_dev(t, name, dtype=None, shape=None):
 
 
 class Context:
-    """An rmg_ctx on one HIP device (owns the workspace)."""
+    """An rmg_ctx on one HIP device (owns the workspace and its streams).
+
+    A context is not thread safe.  Separate contexts are independent: calls on different
+    contexts from different threads overlap on the GPU and return the results of the same
+    calls made one at a time (mlmc_level_estimate calls made so should pass
+    FLAG_NO_CONFINE; two contexts per device measured best)."""
 
     def __init__(self, device: int = 0, tune_cache: str | None = None):
         """tune_cache: optional file that persists the autotuner's choices across processes."""
